@@ -1,0 +1,8 @@
+"""FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+import this package.  It shares no code with the GPU library.
+"""
+from .render import *  # noqa: F401,F403
+from .render import Field, render_image, render_rays, bone_transforms, camera_rays  # noqa: F401
+from .rng import splitmix64, stratified_xi  # noqa: F401
