@@ -1,0 +1,200 @@
+"""Benchmark of the posed-body renderer on one MI355X.
+
+One step = one full render of the 512x512 seeded-body frame, 128 samples per
+ray, FP32 path (inverse LBS over 24 bones with a 64^3 x 25 weight volume,
+16-level grid with 2^19 entries per level, MLP 32-64-64-64-4), inputs
+resident in HBM.  Printed as ONE JSON line:
+  value      nominal Msamples/s (H*W*S per frame / frame time)
+  roofline   the fused render kernel against the chip's peak (HIP-event
+             timed launches, algorithmic bytes and FLOPs per evaluated sample)
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same frame
+Extra fields: the same frame in mixed precision (FP16 table, BF16 MLP), the
+1024x1024 / 192-sample mixed frame, the 8192-ray training step, and PSNR /
+max-abs of each against the oracle on the sampled pixels.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_2306_16541_amd as m  # noqa: E402
+import scenes  # noqa: E402
+
+METRIC = "Msamples/s & 512² frames/s, BF16 vs FP32 at stated PSNR; serving p99 latency"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK = {"f32": 157.3, "bf16": 2500.0}     # dense TFLOP/s
+BYTES_WARP = 24 * 8 * 4                        # per evaluated sample: 24 bones x 8 corners x fp32
+BYTES_ENC = {"f32": 16 * 8 * 2 * 4, "f16": 16 * 8 * 2 * 2}   # 16 levels x 8 corners x 2 features
+
+
+def mlp_flops(widths):
+    return 2 * sum(a * b for a, b in zip(widths[:-1], widths[1:]))
+
+
+def timed_launches(fn, steps, warmup):
+    """Run fn warmup times, then `steps` times with a HIP event pair around each
+    launch on the current stream.  Returns (wall ms/step, mean kernel ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(st)
+        fn()
+        b.record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def psnr(a, b):
+    mse = float(np.mean((a.astype(np.float64) - b) ** 2))
+    return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+
+def render_bench(sc, table_dt, mlp_dt, steps, warmup):
+    fld, _ = m.upload_scene(sc, "cuda", table_dt, mlp_dt)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    opts = m.make_opts(ert_tau=1e-6)
+    out = torch.empty(sc.H * sc.W, 4, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    m.render(fld, pose, cam, sc.H, sc.W, sc.spp, opts, out=out, counter=cnt)
+    torch.cuda.synchronize()
+    n_eval = int(cnt.item())
+    wall, kern = timed_launches(lambda: m.render(fld, pose, cam, sc.H, sc.W, sc.spp, opts, out=out), steps, warmup)
+    img = out.cpu().numpy()
+    return {"wall_ms": wall, "kernel_ms": kern, "n_eval": n_eval, "img": img}
+
+
+def roofline(res, sc, enc_key, mlp_key, widths):
+    """Both candidate bounds of the fused render kernel; the binding one
+    (larger fraction of its peak) is reported."""
+    k_s = res["kernel_ms"] * 1e-3
+    gbytes = res["n_eval"] * (BYTES_WARP + BYTES_ENC[enc_key]) / 1e9
+    tflop = res["n_eval"] * mlp_flops(widths) / 1e12
+    hbm = {"bound": "hbm", "achieved": gbytes / k_s, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    mf = {"bound": "mfma", "achieved": tflop / k_s, "peak": MFMA_PEAK[mlp_key], "unit": "TFLOP/s"}
+    for r in (hbm, mf):
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+    return (hbm, mf) if hbm["frac"] >= mf["frac"] else (mf, hbm)
+
+
+def oracle_sample(sc, img_fp32, img_mixed, budget_s):
+    """FP64 oracle on a bounded random sample of the frame's pixels."""
+    import oracle
+    g = np.random.default_rng(0)
+    order = g.permutation(sc.H * sc.W)
+    done, refs, t0 = 0, [], time.perf_counter()
+    chunk = 1024
+    while time.perf_counter() - t0 < budget_s and done < order.size:
+        pid = order[done:done + chunk]
+        refs.append(oracle.render_image(sc, pixel_ids=pid).numpy())
+        done += pid.size
+    el = time.perf_counter() - t0
+    pid = order[:done]
+    ref = np.concatenate(refs)
+    hit = ref[:, 3] > 0
+    out = {"value": done * sc.spp / el / 1e6, "unit": "Msamples/s (nominal)", "cores": torch.get_num_threads(),
+           "kind": "oracle",
+           "sample": f"{done} random pixels of the {sc.H}x{sc.W}x{sc.spp} frame ({done * sc.spp} nominal samples, "
+                     f"{el:.1f} s, float64 torch CPU)"}
+    par = {}
+    for name, img in (("fp32", img_fp32), ("mixed", img_mixed)):
+        if img is None:
+            continue
+        d = img[pid]
+        par[name] = {"max_abs": float(np.abs(d - ref).max()), "psnr_all": psnr(d[:, :3], ref[:, :3]),
+                     "psnr_hit": psnr(d[hit, :3], ref[hit, :3]), "pixels": int(done)}
+    return out, par
+
+
+def train_bench(steps, warmup):
+    sc = scenes.scene_body()
+    dev = "cuda"
+    tr = m.Trainer(torch.as_tensor(sc.table, device=dev), [torch.as_tensor(w, device=dev) for w in sc.mlp],
+                   torch.as_tensor(sc.logits, device=dev), sc.level_res, m.F32, m.BF16, max_rays=8192, spp=sc.spp)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    pid, tgt = scenes.train_batch(7, sc.H, sc.W, 8192)
+    pid, tgt = torch.as_tensor(pid, device=dev), torch.as_tensor(tgt, device=dev)
+    k = [0]
+
+    def step():
+        k[0] += 1
+        tr.step(pose, cam, sc.H, sc.W, sc.spp, pid, tgt, seed=k[0])
+    wall, _ = timed_launches(step, steps, warmup)
+    return {"ms_per_step": wall, "steps_per_s": 1e3 / wall, "rays": 8192, "spp": sc.spp,
+            "Msamples_per_s": 8192 * sc.spp / wall / 1e3, "loss": tr.loss(),
+            "dtype": "fp32 table/adam, bf16 MLP"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every ray is independent and the whole frame fits one MI355X; "
+              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    sc = scenes.scene_body()                              # 512x512, 128 spp
+    fp32 = render_bench(sc, m.F32, m.F32, args.steps, args.warmup)
+    widths = [32] + [w.shape[0] for w in sc.mlp]
+    roof, roof2 = roofline(fp32, sc, "f32", "f32", widths)
+    nominal = sc.H * sc.W * sc.spp
+    line = {
+        "metric": METRIC,
+        "value": nominal / (fp32["wall_ms"] * 1e-3) / 1e6,
+        "unit": "Msamples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": fp32["wall_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "posed-body render 512x512, 128 samples/ray, fp32 (24 bones, 64^3x25 weights, "
+                               "16-level grid 2^19/level, MLP 32-64-64-64-4, ~30% of rays opaque)",
+                   "H": sc.H, "W": sc.W, "spp": sc.spp},
+        "frames_per_s": 1e3 / fp32["wall_ms"],
+        "kernel_ms": fp32["kernel_ms"],
+        "evaluated_Msamples_per_s": fp32["n_eval"] / (fp32["kernel_ms"] * 1e-3) / 1e6,
+        "evaluated_samples": fp32["n_eval"],
+        "roofline": roof,
+        "roofline_other_bound": roof2,
+    }
+    mixed = None
+    if not args.quick:
+        mixed = render_bench(sc, m.F16, m.BF16, args.steps, args.warmup)
+        line["mixed_512"] = {
+            "Msamples_per_s": nominal / (mixed["kernel_ms"] * 1e-3) / 1e6, "frames_per_s": 1e3 / mixed["kernel_ms"],
+            "speedup_vs_fp32": fp32["kernel_ms"] / mixed["kernel_ms"], "dtype": "fp16 table, bf16 MLP (fp32 acc)",
+            "roofline": roofline(mixed, sc, "f16", "bf16", widths)[0]}
+        sc3 = scenes.scene_body(H=1024, W=1024, spp=192)
+        big = render_bench(sc3, m.F16, m.BF16, max(3, args.steps // 4), 1)
+        line["mixed_1024_192spp"] = {
+            "Msamples_per_s": 1024 * 1024 * 192 / (big["kernel_ms"] * 1e-3) / 1e6,
+            "frames_per_s": 1e3 / big["kernel_ms"],
+            "evaluated_Msamples_per_s": big["n_eval"] / (big["kernel_ms"] * 1e-3) / 1e6}
+        del big
+        line["train_step_8192x128"] = train_bench(max(3, args.steps // 2), 2)
+    cpu, par = oracle_sample(sc, fp32["img"], None if mixed is None else mixed["img"], args.cpu_budget)
+    line["cpu_baseline"] = cpu
+    line["parity_vs_oracle"] = par
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

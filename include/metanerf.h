@@ -1,0 +1,226 @@
+/*
+ * metanerf.h -- C ABI of the MI355X (gfx950) posed-body volume renderer.
+ *
+ * Paper: "Envisioning a Next Generation Extended Reality Conferencing System
+ * with Efficient Photorealistic Human Rendering" (arXiv 2306.16541).
+ * The library renders a posed human body (Sec. 4, Fig. 2): rays are sampled
+ * inside the body's bounding box (Sec. 4.4), each sample is warped from the
+ * observed pose to the canonical pose by inverse linear blend skinning
+ * (Sec. 4.2, Eq. 7-9), the canonical radiance field c, sigma = MLP(enc(x))
+ * is queried (Sec. 4.4, Eq. 13) and the samples are alpha-composited front
+ * to back (Sec. 2.1, Eq. 3) with the likelihood augmentation of Sec. 4.4.
+ * It also trains that field (Sec. 5.2: squared-error loss of Eq. 14, Adam)
+ * and serves many users' frames (Sec. 3, multi-user conferencing).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns mnr_status; MNR_OK == 0.  Nothing throws across
+ *     the ABI.  On failure mnr_last_error() (thread-local) holds the reason.
+ *   - Arguments are validated on the host before anything is launched; an
+ *     invalid call launches nothing and changes no output.
+ *   - "dev" pointers are device memory on the current HIP device, owned by
+ *     the caller; "host" pointers are read during the call only.  The
+ *     library keeps no device memory outside a server object.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously; a HIP launch error is reported as MNR_E_HIP.
+ *   - All rendering entry points are reentrant on distinct streams.
+ *     Training entry points write gradients/parameters and must be
+ *     serialised by the caller.
+ */
+#ifndef METANERF_H
+#define METANERF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MNR_MAX_BONES 32
+#define MNR_MAX_LEVELS 16
+#define MNR_MAX_LAYERS 4
+#define MNR_MAX_SPP 1024
+
+typedef enum {
+  MNR_OK = 0,
+  MNR_E_INVALID = -1,     /* null pointer, NaN/inf pose, bad option */
+  MNR_E_SHAPE = -2,       /* unsupported size or layer widths */
+  MNR_E_DTYPE = -3,       /* unsupported dtype combination */
+  MNR_E_OOM = -4,         /* request exceeds a memory budget */
+  MNR_E_HIP = -5,         /* HIP runtime error (text in mnr_last_error) */
+  MNR_E_BUSY = -6,        /* server has no free slot right now */
+  MNR_E_UNSUPPORTED = -7  /* valid but not implemented configuration */
+} mnr_status;
+
+typedef enum { MNR_F32 = 0, MNR_F16 = 1, MNR_BF16 = 2 } mnr_dtype;
+
+/* Canonical radiance field (Sec. 4.4, Eq. 13): a multiresolution grid
+ * encoding (Mueller et al. 2022, cited in Sec. 2.3) followed by a bias-free
+ * MLP with ReLU hidden layers; outputs rgb = sigmoid(o[0:3]), sigma =
+ * ReLU(o[3]).
+ *   table: dev [n_levels][2^log2_T][n_feat], dtype table_dtype (F32 or F16).
+ *     Level l has resolution level_res[l]; it is stored densely (vertex
+ *     (x,y,z) at row x + (N+1)(y + (N+1)z)) when (N+1)^3 <= 2^log2_T, else
+ *     at row ((x*1) ^ (y*2654435761) ^ (z*805459861)) mod 2^log2_T (uint32).
+ *     The encoding of point x is taken at u = clamp((x - box_min) /
+ *     (box_max - box_min), 0, 1), p = u*N, cell min(floor(p), N-1).
+ *   w[k]: dev row-major [width[k+1]][width[k]], dtype mlp_dtype (F32 or BF16).
+ * Supported: n_feat = 2, n_levels * n_feat = width[0] = 32, hidden widths
+ * 64, width[n_layers] = 4, 2 <= n_layers <= 4, log2_T <= 24. */
+typedef struct {
+  int32_t n_levels, n_feat, log2_T;
+  int32_t level_res[MNR_MAX_LEVELS];
+  float box_min[3], box_max[3];
+  mnr_dtype table_dtype;
+  const void* table;
+  int32_t n_layers;
+  int32_t width[MNR_MAX_LAYERS + 1];
+  mnr_dtype mlp_dtype;
+  const void* w[MNR_MAX_LAYERS];
+} mnr_field;
+
+/* Canonical blend-weight volume W^c (Sec. 4.2, Eq. 9-10): dev float
+ * [n_bones + 1][res^3], voxel (x,y,z) at x + res*(y + res*z), channel
+ * n_bones = background.  Vertex-aligned over [box_min, box_max]; trilinear
+ * samples treat vertices outside the volume as zero. */
+typedef struct {
+  int32_t n_bones, res;
+  float box_min[3], box_max[3];
+  const float* weights;
+} mnr_motion;
+
+/* Body pose (Sec. 4.1-4.2): host arrays.  parent[j] < j (root: -1), rest
+ * joints [n][3] in the canonical (rest) pose, axis-angle [n][3] of the
+ * observed pose theta^o.  Bone transforms G_j (Eq. 8) are computed from it
+ * by forward kinematics in double precision on the host. */
+typedef struct {
+  int32_t n_joints;
+  const int32_t* parent;
+  const float* rest_joints;
+  const float* axis_angle;
+} mnr_pose;
+
+/* Pinhole camera, x_cam = R_wc * X + T (R_wc row-major); pixel (u, v) =
+ * (id % W, id / W) shoots through its centre (u + 0.5, v + 0.5).  box_min /
+ * box_max bound the body in observation space: samples are taken only inside
+ * it (Sec. 4.4). */
+typedef struct {
+  float fx, fy, cx, cy;
+  float R_wc[9];
+  float T[3];
+  float box_min[3], box_max[3];
+} mnr_camera;
+
+/* Render options.  ert_tau: a ray stops after the 64-sample chunk in which
+ * its transmittance drops below ert_tau (0 disables early termination; the
+ * colour then differs from the full sum by at most ert_tau * (1 + |bg|)).
+ * stratified = 0 samples stratum midpoints; 1 draws the jitter xi of sample
+ * i of ray b from SplitMix64: output n = b*spp + i of the stream seeded with
+ * `seed`, xi = (out >> 40) * 2^-24. */
+typedef struct {
+  float ert_tau;
+  float bg[3];
+  int32_t stratified;
+  uint64_t seed;
+} mnr_opts;
+
+const char* mnr_status_str(mnr_status s);
+const char* mnr_last_error(void);
+const char* mnr_version(void);
+
+/* Forward kinematics (Sec. 4.2, Eq. 8): host-only, double precision,
+ * rounded to float.  G_out: host [n_joints][3][4] = [R_j | t_j] with
+ * G_j(x) = R_j x + t_j mapping an observed point to the canonical pose
+ * (the inverse of bone j's skinning transform). */
+mnr_status mnr_fk_bones(const mnr_pose* pose, float* G_out);
+
+/* Render rays (Sec. 4, Fig. 2; Eq. 3, 7-9, 13).  pixel_ids: dev int32
+ * [n_rays] pixel indices of an H x W image, or NULL for the full frame in
+ * row-major order (then n_rays must equal H*W).  Ids outside [0, H*W)
+ * render as misses.  out_rgba: dev float [n_rays][4] = (r, g, b, opacity);
+ * rays that miss the box get (bg, 0).
+ * t_chunks (optional, dev float [n_rays][ceil(spp/64)]): transmittance at
+ * the start of each 64-sample chunk the ray processed, -1 for chunks it
+ * skipped after early termination (and for missed rays); the adjoint
+ * needs it.  n_evaluated (optional, dev uint64, accumulated with atomics)
+ * counts the samples actually evaluated. */
+mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                      const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
+                      const mnr_opts* opts, const int32_t* pixel_ids, int32_t n_rays,
+                      float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
+                      void* stream);
+
+/* Adjoint of mnr_render (hand-written; recomputes per-sample activations
+ * instead of storing them).  Given t_chunks written by mnr_render with the
+ * same arguments and dL/d(rgba) grad_rgba (dev [n_rays][4]), ACCUMULATES
+ * into
+ *   grad_table   dev float [n_levels][2^log2_T][n_feat]
+ *   grad_w[k]    dev float [width[k+1]][width[k]]
+ *   grad_weights dev float [n_bones + 1][res^3]   (dL/dW^c)
+ * Gradients are those of the forward actually computed (early termination
+ * included).  Summation order of the atomics is not deterministic. */
+mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
+                               const mnr_pose* pose, const mnr_camera* cam, int32_t H, int32_t W,
+                               int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
+                               int32_t n_rays, const float* t_chunks, const float* grad_rgba,
+                               float* grad_table, float* const* grad_w, float* grad_weights,
+                               void* stream);
+
+/* Squared-error loss of Eq. 14's MSE term over RGB: loss = mean over rays
+ * and channels of (rgb - target)^2.  target: dev [n_rays][3].  Writes
+ * grad_rgba dev [n_rays][4] (alpha gradient 0) and, if loss_out != NULL,
+ * the loss to dev float loss_out[0]. */
+mnr_status mnr_mse_loss(const float* rgba, const float* target, int32_t n_rays,
+                        float* grad_rgba, float* loss_out, void* stream);
+
+/* Canonical blend weights from free logits (Sec. 4.2: W^c is produced per
+ * voxel; the build's W^c is a per-voxel softmax over n_channels).
+ * logits, weights: dev float [n_channels][n_voxels]. */
+mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channels,
+                           int64_t n_voxels, void* stream);
+/* Softmax adjoint: grad_logits[c] += w[c] * (g[c] - sum_k w[k] g[k]). */
+mnr_status mnr_softmax_bwd(const float* weights, const float* grad_weights, float* grad_logits,
+                           int32_t n_channels, int64_t n_voxels, void* stream);
+
+/* Adam (Sec. 5.2: beta1 = 0.9, beta2 = 0.99).  Updates dev float param,
+ * m, v [n] in place from grad [n] at step `step` (1-based, bias corrected),
+ * then, if lowp != NULL, writes the rounded (RNE) copy of param to lowp in
+ * lowp_dtype (F16 or BF16). */
+mnr_status mnr_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                         float lr, float beta1, float beta2, float eps, int32_t step,
+                         void* lowp, mnr_dtype lowp_dtype, void* stream);
+
+/* dst = round-to-nearest-even(src) in dtype (F16 or BF16); n elements. */
+mnr_status mnr_convert(const float* src, void* dst, mnr_dtype dtype, int64_t n, void* stream);
+/* Zero n_bytes of dev memory with a kernel (safe inside captured graphs). */
+mnr_status mnr_zero(void* dst, size_t n_bytes, void* stream);
+
+/* One training step (Sec. 5.2): forward, MSE loss, adjoint, softmax adjoint
+ * and Adam on every learnable tensor.  The field's table/MLP pointers are
+ * the low-precision copies read by the renderer (they may alias the fp32
+ * masters when the dtypes are F32).  Learning rates: lr_field for the
+ * table and MLP, lr_motion for the logits.  All buffers are caller-owned
+ * device memory; the state struct lists them. */
+typedef struct {
+  float* table_master; float* table_grad; float* table_m; float* table_v; /* [L*T*F] */
+  float* w_master[MNR_MAX_LAYERS]; float* w_grad[MNR_MAX_LAYERS];
+  float* w_m[MNR_MAX_LAYERS]; float* w_v[MNR_MAX_LAYERS];
+  float* logits; float* logits_grad; float* logits_m; float* logits_v;    /* [(n_bones+1)*res^3] */
+  float* weights_grad;                                                    /* dL/dW^c scratch */
+  float* rgba; float* grad_rgba;                                          /* [n_rays][4] scratch */
+  float* t_chunks;                                          /* [n_rays][ceil(spp/64)] scratch */
+  float* loss;                                                            /* [1] */
+  float lr_field, lr_motion, beta1, beta2, eps;
+  int32_t step;                                                           /* 1-based */
+  int32_t train_motion;                                                   /* 0 = logits frozen */
+} mnr_train_state;
+
+mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                          const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
+                          const mnr_opts* opts, const int32_t* pixel_ids, int32_t n_rays,
+                          const float* target, mnr_train_state* state, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* METANERF_H */

@@ -1,0 +1,381 @@
+"""Python binding of libmetanerf.so, the gfx950 posed-body volume renderer.
+
+Argument marshalling only: every step of rendering and training runs in the
+library's HIP kernels; PyTorch supplies device memory and the current
+stream.  The entry points keep the C names without the `mnr_` prefix
+(`render`, `render_backward`, `train_step`, `fk_bones`, ...).  Importing the
+package fails loudly when the built library is missing: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmetanerf.so")
+
+MAX_BONES, MAX_LEVELS, MAX_LAYERS = 32, 16, 4
+F32, F16, BF16 = 0, 1, 2
+_TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
+
+
+class MnrError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "(or python paper_2306_16541_amd/build.py); there is no CPU fallback")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+
+class Field(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_feat", C.c_int32), ("log2_T", C.c_int32),
+                ("level_res", C.c_int32 * MAX_LEVELS), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
+                ("table_dtype", C.c_int), ("table", C.c_void_p), ("n_layers", C.c_int32),
+                ("width", C.c_int32 * (MAX_LAYERS + 1)), ("mlp_dtype", C.c_int), ("w", C.c_void_p * MAX_LAYERS)]
+
+
+class Motion(C.Structure):
+    _fields_ = [("n_bones", C.c_int32), ("res", C.c_int32), ("box_min", C.c_float * 3),
+                ("box_max", C.c_float * 3), ("weights", C.c_void_p)]
+
+
+class Pose(C.Structure):
+    _fields_ = [("n_joints", C.c_int32), ("parent", C.c_void_p), ("rest_joints", C.c_void_p),
+                ("axis_angle", C.c_void_p)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("R_wc", C.c_float * 9), ("T", C.c_float * 3), ("box_min", C.c_float * 3),
+                ("box_max", C.c_float * 3)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("ert_tau", C.c_float), ("bg", C.c_float * 3), ("stratified", C.c_int32), ("seed", C.c_uint64)]
+
+
+_FP = C.c_void_p
+_PL = C.POINTER(C.c_void_p)
+
+
+class TrainState(C.Structure):
+    _fields_ = ([("table_master", _FP), ("table_grad", _FP), ("table_m", _FP), ("table_v", _FP)] +
+                [("w_master", _FP * MAX_LAYERS), ("w_grad", _FP * MAX_LAYERS), ("w_m", _FP * MAX_LAYERS),
+                 ("w_v", _FP * MAX_LAYERS)] +
+                [("logits", _FP), ("logits_grad", _FP), ("logits_m", _FP), ("logits_v", _FP),
+                 ("weights_grad", _FP), ("rgba", _FP), ("grad_rgba", _FP), ("t_chunks", _FP), ("loss", _FP),
+                 ("lr_field", C.c_float), ("lr_motion", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                 ("eps", C.c_float), ("step", C.c_int32), ("train_motion", C.c_int32)])
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype, f.argtypes = res, args
+    return f
+
+
+_sig("mnr_status_str", C.c_char_p, [C.c_int])
+_sig("mnr_last_error", C.c_char_p, [])
+_sig("mnr_version", C.c_char_p, [])
+_sig("mnr_fk_bones", C.c_int, [C.POINTER(Pose), C.c_void_p])
+_RENDER_COMMON = [C.POINTER(Field), C.POINTER(Motion), C.POINTER(Pose), C.POINTER(Camera), C.c_int32, C.c_int32,
+                  C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_int32]
+_sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_render_backward", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
+                                                       C.c_void_p])
+_sig("mnr_mse_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_softmax_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
+_sig("mnr_softmax_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
+_sig("mnr_adam_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_float,
+                                C.c_float, C.c_float, C.c_int32, C.c_void_p, C.c_int, C.c_void_p])
+_sig("mnr_convert", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p])
+_sig("mnr_zero", C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p])
+_sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
+
+EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
+            "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
+            "mnr_train_step"]
+
+
+def check(status: int, what: str = "") -> None:
+    if status != 0:
+        msg = lib.mnr_last_error().decode()
+        raise MnrError(f"{what}: {lib.mnr_status_str(status).decode()} ({status}): {msg}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version() -> str:
+    return lib.mnr_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Host-side descriptors (plain data, no arithmetic).
+# ---------------------------------------------------------------------------
+
+class PoseHost:
+    """Keeps the host arrays of an mnr_pose alive."""
+
+    def __init__(self, parents, rest_joints, axis_angle):
+        self.parents = np.ascontiguousarray(parents, dtype=np.int32)
+        self.rest = np.ascontiguousarray(rest_joints, dtype=np.float32)
+        self.aa = np.ascontiguousarray(axis_angle, dtype=np.float32)
+        self.c = Pose(int(self.parents.shape[0]), self.parents.ctypes.data, self.rest.ctypes.data, self.aa.ctypes.data)
+
+
+def make_camera(cam, box_min=(-0.5,) * 3, box_max=(0.5,) * 3) -> Camera:
+    c = Camera()
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.R_wc[:] = [float(v) for v in np.asarray(cam.R_wc, dtype=np.float32).ravel()]
+    c.T[:] = [float(v) for v in np.asarray(cam.T, dtype=np.float32).ravel()]
+    c.box_min[:] = list(box_min)
+    c.box_max[:] = list(box_max)
+    return c
+
+
+def make_opts(ert_tau=1e-6, bg=(0.0, 0.0, 0.0), stratified=False, seed=0) -> Opts:
+    return Opts(float(ert_tau), (C.c_float * 3)(*bg), int(bool(stratified)), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def fk_bones(pose: PoseHost) -> np.ndarray:
+    G = np.zeros((pose.parents.shape[0], 3, 4), dtype=np.float32)
+    check(lib.mnr_fk_bones(C.byref(pose.c), G.ctypes.data), "fk_bones")
+    return G
+
+
+class DeviceField:
+    """A canonical field resident on the GPU: grid table + MLP weights (in
+    the dtypes the renderer reads) and the motion-weight volume."""
+
+    def __init__(self, table: torch.Tensor, mlp: Sequence[torch.Tensor], weights: torch.Tensor, level_res,
+                 box_min=(-0.5,) * 3, box_max=(0.5,) * 3, n_feat: int = 2):
+        self.table, self.mlp, self.weights = table, list(mlp), weights
+        dt = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+        f = Field()
+        f.n_levels, f.n_feat = int(table.shape[0]), n_feat
+        f.log2_T = int(table.shape[1]).bit_length() - 1
+        f.level_res[: len(level_res)] = [int(n) for n in level_res]
+        f.box_min[:], f.box_max[:] = list(box_min), list(box_max)
+        f.table_dtype, f.table = dt[table.dtype], table.data_ptr()
+        f.n_layers = len(self.mlp)
+        widths = [int(self.mlp[0].shape[1])] + [int(w.shape[0]) for w in self.mlp]
+        f.width[: len(widths)] = widths
+        f.mlp_dtype = dt[self.mlp[0].dtype]
+        for k, w in enumerate(self.mlp):
+            f.w[k] = w.data_ptr()
+        self.c = f
+        m = Motion()
+        m.n_bones, m.res = int(weights.shape[0]) - 1, int(weights.shape[-1])
+        m.box_min[:], m.box_max[:] = list(box_min), list(box_max)
+        m.weights = weights.data_ptr()
+        self.m = m
+
+
+def softmax_fwd(logits: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    out = torch.empty_like(logits) if out is None else out
+    check(lib.mnr_softmax_fwd(_ptr(logits), _ptr(out), int(logits.shape[0]), int(logits[0].numel()), _stream()),
+          "softmax_fwd")
+    return out
+
+
+def softmax_bwd(weights, grad_weights, grad_logits) -> None:
+    check(lib.mnr_softmax_bwd(_ptr(weights), _ptr(grad_weights), _ptr(grad_logits), int(weights.shape[0]),
+                              int(weights[0].numel()), _stream()), "softmax_bwd")
+
+
+def convert(src: torch.Tensor, dtype: int) -> torch.Tensor:
+    dst = torch.empty(src.shape, dtype=_TORCH_DT[dtype], device=src.device)
+    check(lib.mnr_convert(_ptr(src), _ptr(dst), dtype, src.numel(), _stream()), "convert")
+    return dst
+
+
+def zero_(t: torch.Tensor) -> torch.Tensor:
+    check(lib.mnr_zero(_ptr(t), t.numel() * t.element_size(), _stream()), "zero")
+    return t
+
+
+def upload_scene(sc, device="cuda", table_dtype: int = F32, mlp_dtype: int = F32):
+    """Copy a scenes.Scene's arrays to the GPU and build a DeviceField
+    (softmax and precision conversion run in the library's kernels).
+    Returns (DeviceField, fp32 masters dict)."""
+    table32 = torch.as_tensor(sc.table, device=device)
+    w32 = [torch.as_tensor(w, device=device) for w in sc.mlp]
+    logits = torch.as_tensor(sc.logits, device=device)
+    weights = softmax_fwd(logits)
+    table = table32 if table_dtype == F32 else convert(table32, table_dtype)
+    mlp = w32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in w32]
+    fld = DeviceField(table, mlp, weights, sc.level_res, sc.box_min, sc.box_max)
+    return fld, {"table": table32, "mlp": w32, "logits": logits}
+
+
+def n_chunks(spp: int) -> int:
+    return (spp + 63) // 64
+
+
+def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts] = None,
+           pixel_ids: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+           counter: Optional[torch.Tensor] = None, t_chunks: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """RGBA [n_rays, 4] (full frame: [H*W, 4], row-major pixels)."""
+    n = H * W if pixel_ids is None else int(pixel_ids.numel())
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=field.table.device)
+    check(lib.mnr_render(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
+                         None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(out), _ptr(t_chunks),
+                         _ptr(counter), _stream()), "render")
+    return out
+
+
+def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts],
+                    pixel_ids: Optional[torch.Tensor], t_chunks: torch.Tensor, grad_rgba: torch.Tensor,
+                    grad_table: torch.Tensor, grad_w: List[torch.Tensor], grad_weights: torch.Tensor) -> None:
+    n = H * W if pixel_ids is None else int(pixel_ids.numel())
+    gw = (C.c_void_p * len(grad_w))(*[g.data_ptr() for g in grad_w])
+    check(lib.mnr_render_backward(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
+                                  None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(t_chunks),
+                                  _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights), _stream()),
+          "render_backward")
+
+
+def mse_loss(rgba: torch.Tensor, target: torch.Tensor, grad_rgba: torch.Tensor,
+             loss: Optional[torch.Tensor] = None) -> None:
+    check(lib.mnr_mse_loss(_ptr(rgba), _ptr(target), int(rgba.shape[0]), _ptr(grad_rgba), _ptr(loss), _stream()),
+          "mse_loss")
+
+
+def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.99, eps=1e-8, lowp=None) -> None:
+    dt = F32 if lowp is None else {torch.float16: F16, torch.bfloat16: BF16}[lowp.dtype]
+    check(lib.mnr_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), lr, beta1, beta2, eps, step,
+                            _ptr(lowp), dt, _stream()), "adam_step")
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable render of a ray batch: inputs are the field's table, MLP
+    weights and canonical blend weights (W^c); the adjoint is the library's
+    hand-written backward kernel."""
+
+    @staticmethod
+    def forward(ctx, table, weights, *mlp_and_cfg):
+        *mlp, cfg = mlp_and_cfg
+        field, pose, cam, H, W, spp, opts, pixel_ids = cfg
+        n = H * W if pixel_ids is None else int(pixel_ids.numel())
+        tch = torch.empty((n, n_chunks(spp)), dtype=torch.float32, device=table.device)
+        out = render(field, pose, cam, H, W, spp, opts, pixel_ids, t_chunks=tch)
+        ctx.cfg = cfg
+        ctx.save_for_backward(tch)
+        ctx.shapes = (table.shape, weights.shape, [w.shape for w in mlp])
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (tch,) = ctx.saved_tensors
+        field, pose, cam, H, W, spp, opts, pixel_ids = ctx.cfg
+        dev = tch.device
+        g_table = torch.zeros(ctx.shapes[0], dtype=torch.float32, device=dev)
+        g_weights = torch.zeros(ctx.shapes[1], dtype=torch.float32, device=dev)
+        g_w = [torch.zeros(s, dtype=torch.float32, device=dev) for s in ctx.shapes[2]]
+        render_backward(field, pose, cam, H, W, spp, opts, pixel_ids, tch, grad_out.contiguous().float(),
+                        g_table, g_w, g_weights)
+        return (g_table, g_weights, *g_w, None)
+
+
+class Trainer:
+    """Device-resident training state for mnr_train_step: FP32 masters, Adam
+    moments, gradient and scratch buffers, and the low-precision copies the
+    renderer reads.  Buffers are allocated once (by torch) and reused."""
+
+    def __init__(self, table32: torch.Tensor, mlp32: Sequence[torch.Tensor], logits32: torch.Tensor, level_res,
+                 table_dtype: int = F32, mlp_dtype: int = F32, max_rays: int = 8192, spp: int = 128,
+                 lr_field: float = 5e-4, lr_motion: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
+                 eps: float = 1e-8, train_motion: bool = True, box_min=(-0.5,) * 3, box_max=(0.5,) * 3):
+        dev = table32.device
+        self.table32 = table32.contiguous().clone()
+        self.mlp32 = [w.contiguous().clone() for w in mlp32]
+        self.logits = logits32.contiguous().clone()
+        self.weights = softmax_fwd(self.logits)
+        self.table = self.table32 if table_dtype == F32 else convert(self.table32, table_dtype)
+        self.mlp = self.mlp32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in self.mlp32]
+        self.field = DeviceField(self.table, self.mlp, self.weights, level_res, box_min, box_max)
+        z = lambda t: torch.zeros_like(t, dtype=torch.float32)
+        self.buf = {
+            "table_grad": z(self.table32), "table_m": z(self.table32), "table_v": z(self.table32),
+            "w_grad": [z(w) for w in self.mlp32], "w_m": [z(w) for w in self.mlp32], "w_v": [z(w) for w in self.mlp32],
+            "logits_grad": z(self.logits), "logits_m": z(self.logits), "logits_v": z(self.logits),
+            "weights_grad": z(self.logits),
+            "rgba": torch.zeros(max_rays, 4, device=dev), "grad_rgba": torch.zeros(max_rays, 4, device=dev),
+            "t_chunks": torch.zeros(max_rays * n_chunks(spp), device=dev), "loss": torch.zeros(1, device=dev),
+        }
+        self.max_rays, self.max_spp = max_rays, spp
+        s = TrainState()
+        b = self.buf
+        s.table_master, s.table_grad, s.table_m, s.table_v = (t.data_ptr() for t in
+                                                              (self.table32, b["table_grad"], b["table_m"], b["table_v"]))
+        for k in range(len(self.mlp32)):
+            s.w_master[k], s.w_grad[k] = self.mlp32[k].data_ptr(), b["w_grad"][k].data_ptr()
+            s.w_m[k], s.w_v[k] = b["w_m"][k].data_ptr(), b["w_v"][k].data_ptr()
+        s.logits, s.logits_grad = self.logits.data_ptr(), b["logits_grad"].data_ptr()
+        s.logits_m, s.logits_v = b["logits_m"].data_ptr(), b["logits_v"].data_ptr()
+        s.weights_grad, s.rgba, s.grad_rgba = b["weights_grad"].data_ptr(), b["rgba"].data_ptr(), b["grad_rgba"].data_ptr()
+        s.t_chunks, s.loss = b["t_chunks"].data_ptr(), b["loss"].data_ptr()
+        s.lr_field, s.lr_motion, s.beta1, s.beta2, s.eps = lr_field, lr_motion, beta1, beta2, eps
+        s.step, s.train_motion = 0, int(bool(train_motion))
+        self.state = s
+
+    def step(self, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, pixel_ids: torch.Tensor,
+             target: torch.Tensor, seed: int, ert_tau: float = 1e-6) -> None:
+        n = int(pixel_ids.numel())
+        if n > self.max_rays or spp > self.max_spp:
+            raise ValueError("batch larger than the trainer's buffers")
+        self.state.step += 1
+        opts = make_opts(ert_tau=ert_tau, stratified=True, seed=seed)
+        check(lib.mnr_train_step(C.byref(self.field.c), C.byref(self.field.m), C.byref(pose.c), C.byref(cam), H, W,
+                                 spp, C.byref(opts), _ptr(pixel_ids), n, _ptr(target), C.byref(self.state), _stream()),
+              "train_step")
+
+    def loss(self) -> float:
+        return float(self.buf["loss"].item())
+
+    def state_dict(self) -> dict:
+        b = self.buf
+        return {"step": int(self.state.step), "table": self.table32.cpu(), "mlp": [w.cpu() for w in self.mlp32],
+                "logits": self.logits.cpu(), "table_m": b["table_m"].cpu(), "table_v": b["table_v"].cpu(),
+                "w_m": [t.cpu() for t in b["w_m"]], "w_v": [t.cpu() for t in b["w_v"]],
+                "logits_m": b["logits_m"].cpu(), "logits_v": b["logits_v"].cpu()}
+
+    def load_state_dict(self, sd: dict) -> None:
+        """Restore masters and Adam moments in place, then refresh the
+        renderer's copies (softmax and precision conversion kernels)."""
+        b = self.buf
+        self.table32.copy_(sd["table"])
+        for w, v in zip(self.mlp32, sd["mlp"]):
+            w.copy_(v)
+        self.logits.copy_(sd["logits"])
+        for key in ("table_m", "table_v", "logits_m", "logits_v"):
+            b[key].copy_(sd[key])
+        for key in ("w_m", "w_v"):
+            for t, v in zip(b[key], sd[key]):
+                t.copy_(v)
+        self.state.step = int(sd["step"])
+        softmax_fwd(self.logits, out=self.weights)
+        if self.table is not self.table32:
+            check(lib.mnr_convert(_ptr(self.table32), _ptr(self.table), self.field.c.table_dtype, self.table32.numel(),
+                                  _stream()), "convert")
+        for w32, w in zip(self.mlp32, self.mlp):
+            if w is not w32:
+                check(lib.mnr_convert(_ptr(w32), _ptr(w), self.field.c.mlp_dtype, w32.numel(), _stream()), "convert")

@@ -1,0 +1,323 @@
+// C-ABI entry points: validation on the host, argument packing, launches on
+// the caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "host_common.h"
+#include "kernels.h"
+
+namespace mnr {
+
+static thread_local char g_err[512];
+
+void clear_error() { g_err[0] = 0; }
+
+mnr_status fail(mnr_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+static mnr_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MNR_OK;
+  return fail(MNR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+static mnr_status check_box(const float* lo, const float* hi, const char* who) {
+  if (!finite3(lo) || !finite3(hi)) return fail(MNR_E_INVALID, "%s: non-finite box", who);
+  for (int a = 0; a < 3; ++a)
+    if (!(hi[a] > lo[a])) return fail(MNR_E_INVALID, "%s: box_max must exceed box_min", who);
+  return MNR_OK;
+}
+
+static mnr_status validate_field(const mnr_field* f) {
+  if (!f || !f->table) return fail(MNR_E_INVALID, "field: null pointer");
+  if (f->n_feat != 2) return fail(MNR_E_SHAPE, "field: n_feat must be 2, got %d", f->n_feat);
+  if (f->n_levels < 1 || f->n_levels > MNR_MAX_LEVELS || f->n_levels * f->n_feat != 32)
+    return fail(MNR_E_SHAPE, "field: n_levels * n_feat must be 32 (n_levels %d)", f->n_levels);
+  if (f->log2_T < 4 || f->log2_T > 24) return fail(MNR_E_SHAPE, "field: log2_T must be in [4, 24], got %d", f->log2_T);
+  for (int l = 0; l < f->n_levels; ++l)
+    if (f->level_res[l] < 1 || f->level_res[l] > 65535)
+      return fail(MNR_E_SHAPE, "field: level_res[%d] = %d out of [1, 65535]", l, f->level_res[l]);
+  if (f->table_dtype != MNR_F32 && f->table_dtype != MNR_F16) return fail(MNR_E_DTYPE, "field: table dtype must be F32 or F16");
+  if (f->mlp_dtype != MNR_F32 && f->mlp_dtype != MNR_BF16) return fail(MNR_E_DTYPE, "field: MLP dtype must be F32 or BF16");
+  if (f->n_layers < 2 || f->n_layers > MNR_MAX_LAYERS)
+    return fail(MNR_E_SHAPE, "field: n_layers must be in [2, %d], got %d", MNR_MAX_LAYERS, f->n_layers);
+  if (f->width[0] != 32 || f->width[f->n_layers] != 4)
+    return fail(MNR_E_SHAPE, "field: widths must run 32 -> ... -> 4");
+  for (int k = 1; k < f->n_layers; ++k)
+    if (f->width[k] != 64) return fail(MNR_E_SHAPE, "field: hidden width %d must be 64", f->width[k]);
+  for (int k = 0; k < f->n_layers; ++k)
+    if (!f->w[k]) return fail(MNR_E_INVALID, "field: null weight pointer for layer %d", k);
+  return check_box(f->box_min, f->box_max, "field");
+}
+
+static mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
+                                  int H, int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays,
+                                  const void* out) {
+  if (mnr_status s = validate_field(f)) return s;
+  if (mnr_status s = validate_pose(p)) return s;
+  if (!m || !m->weights) return fail(MNR_E_INVALID, "motion: null pointer");
+  if (m->n_bones != p->n_joints) return fail(MNR_E_SHAPE, "motion: n_bones %d != pose joints %d", m->n_bones, p->n_joints);
+  if (m->res < 2 || m->res > 512) return fail(MNR_E_SHAPE, "motion: res must be in [2, 512], got %d", m->res);
+  if (mnr_status s = check_box(m->box_min, m->box_max, "motion")) return s;
+  if (!c) return fail(MNR_E_INVALID, "camera: null pointer");
+  if (!(c->fx > 0) || !(c->fy > 0) || !std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) ||
+      !std::isfinite(c->cy))
+    return fail(MNR_E_INVALID, "camera: bad intrinsics");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(c->R_wc[i])) return fail(MNR_E_INVALID, "camera: non-finite rotation");
+  if (!finite3(c->T)) return fail(MNR_E_INVALID, "camera: non-finite translation");
+  if (mnr_status s = check_box(c->box_min, c->box_max, "camera")) return s;
+  if (H < 1 || W < 1 || (int64_t)H * W > (1 << 28)) return fail(MNR_E_SHAPE, "image %dx%d out of range", H, W);
+  if (spp < 1 || spp > MNR_MAX_SPP) return fail(MNR_E_SHAPE, "spp must be in [1, %d], got %d", MNR_MAX_SPP, spp);
+  if (n_rays < 0) return fail(MNR_E_SHAPE, "n_rays must be >= 0");
+  if (!pixel_ids && n_rays != 0 && n_rays != H * W) return fail(MNR_E_SHAPE, "full frame needs n_rays == H*W");
+  if (!out && n_rays > 0) return fail(MNR_E_INVALID, "null output");
+  if (o && (!(o->ert_tau >= 0) || !finite3(o->bg))) return fail(MNR_E_INVALID, "opts: bad ert_tau or bg");
+  return MNR_OK;
+}
+
+static void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
+                      int H, int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays) {
+  std::memset(&a, 0, sizeof(a));
+  a.f.table = f->table;
+  for (int k = 0; k < f->n_layers; ++k) a.f.w[k] = f->w[k];
+  const int64_t T = int64_t(1) << f->log2_T;
+  for (int l = 0; l < f->n_levels; ++l) {
+    a.f.level_res[l] = f->level_res[l];
+    const int64_t n1 = f->level_res[l] + 1;
+    if (n1 * n1 * n1 <= T) a.f.dense_mask |= 1u << l;
+  }
+  a.f.n_levels = f->n_levels;
+  a.f.log2_T = f->log2_T;
+  a.f.n_layers = f->n_layers;
+  for (int i = 0; i < 3; ++i) {
+    a.f.gmin[i] = f->box_min[i];
+    a.f.gscale[i] = (float)(1.0 / ((double)f->box_max[i] - f->box_min[i]));
+    a.m.mmin[i] = m->box_min[i];
+    a.m.mscale[i] = (float)((m->res - 1) / ((double)m->box_max[i] - m->box_min[i]));
+  }
+  a.m.weights = m->weights;
+  a.m.res = m->res;
+  a.m.n_bones = m->n_bones;
+  double G[MNR_MAX_BONES * 12];
+  fk_bones_f64(p, G);
+  for (int j = 0; j < p->n_joints; ++j)
+    for (int k = 0; k < 12; ++k) a.G[j][k] = (float)G[12 * j + k];
+  RayArgs& r = a.r;
+  for (int i = 0; i < 9; ++i) r.Rwc[i] = c->R_wc[i];
+  for (int i = 0; i < 3; ++i) {  // camera centre o = -R^T T
+    r.origin[i] = -(r.Rwc[0 * 3 + i] * c->T[0] + r.Rwc[1 * 3 + i] * c->T[1] + r.Rwc[2 * 3 + i] * c->T[2]);
+    r.bmin[i] = c->box_min[i];
+    r.bmax[i] = c->box_max[i];
+  }
+  r.fx = c->fx; r.fy = c->fy; r.cx = c->cx; r.cy = c->cy;
+  r.H = H; r.W = W; r.spp = spp; r.n_rays = n_rays;
+  r.pixel_ids = pixel_ids;
+  r.tiles_x = (W + 15) / 16;
+  if (o) {
+    r.ert_tau = o->ert_tau;
+    for (int i = 0; i < 3; ++i) r.bg[i] = o->bg[i];
+    r.stratified = o->stratified;
+    r.seed = o->seed;
+  } else {
+    r.ert_tau = 1e-6f;
+  }
+}
+
+static int slot_count(int H, int W, const int32_t* pixel_ids, int n_rays) {
+  if (pixel_ids) return n_rays;
+  return ((W + 15) / 16) * ((H + 15) / 16) * 256;
+}
+
+}  // namespace mnr
+
+using namespace mnr;
+
+extern "C" {
+
+const char* mnr_status_str(mnr_status s) {
+  switch (s) {
+    case MNR_OK: return "ok";
+    case MNR_E_INVALID: return "invalid argument";
+    case MNR_E_SHAPE: return "unsupported shape";
+    case MNR_E_DTYPE: return "unsupported dtype";
+    case MNR_E_OOM: return "over memory budget";
+    case MNR_E_HIP: return "HIP error";
+    case MNR_E_BUSY: return "busy";
+    case MNR_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* mnr_last_error(void) { return g_err; }
+
+const char* mnr_version(void) { return "metanerf-gfx950 0.1"; }
+
+mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose, const mnr_camera* cam,
+                      int32_t H, int32_t W, int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
+                      int32_t n_rays, float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
+                      void* stream) {
+  clear_error();
+  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba)) return s;
+  if (n_rays == 0) return MNR_OK;
+  RenderArgs a;
+  pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
+  a.out = out_rgba;
+  a.t_chunks = t_chunks;
+  a.n_eval = n_evaluated;
+  return hip_status(launch_render_fwd(a, slot_count(H, W, pixel_ids, n_rays), field->table_dtype, field->mlp_dtype,
+                                      field->n_layers - 2, (hipStream_t)stream),
+                    "render launch");
+}
+
+mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                               const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
+                               const int32_t* pixel_ids, int32_t n_rays, const float* t_chunks,
+                               const float* grad_rgba, float* grad_table, float* const* grad_w, float* grad_weights,
+                               void* stream) {
+  clear_error();
+  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
+  if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
+  for (int k = 0; k < field->n_layers; ++k)
+    if (!grad_w[k]) return fail(MNR_E_INVALID, "backward: null grad_w[%d]", k);
+  if (n_rays == 0) return MNR_OK;
+  RenderArgs a;
+  pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
+  a.t_chunks = (float*)t_chunks;
+  a.grad_rgba = grad_rgba;
+  a.grad_table = grad_table;
+  for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = grad_w[k];
+  a.grad_weights = grad_weights;
+  return hip_status(launch_render_bwd(a, slot_count(H, W, pixel_ids, n_rays), field->table_dtype, field->mlp_dtype,
+                                      field->n_layers - 2, (hipStream_t)stream),
+                    "backward launch");
+}
+
+mnr_status mnr_mse_loss(const float* rgba, const float* target, int32_t n_rays, float* grad_rgba, float* loss_out,
+                        void* stream) {
+  clear_error();
+  if (n_rays < 0) return fail(MNR_E_SHAPE, "mse: n_rays < 0");
+  if (n_rays == 0) return MNR_OK;
+  if (!rgba || !target || !grad_rgba) return fail(MNR_E_INVALID, "mse: null pointer");
+  return hip_status(launch_mse(rgba, target, n_rays, grad_rgba, loss_out, (hipStream_t)stream), "mse launch");
+}
+
+mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channels, int64_t n_voxels, void* stream) {
+  clear_error();
+  if (!logits || !weights) return fail(MNR_E_INVALID, "softmax: null pointer");
+  if (n_channels < 1 || n_channels > 64 || n_voxels < 0) return fail(MNR_E_SHAPE, "softmax: bad shape");
+  if (n_voxels == 0) return MNR_OK;
+  return hip_status(launch_softmax_fwd(logits, weights, n_channels, n_voxels, (hipStream_t)stream), "softmax launch");
+}
+
+mnr_status mnr_softmax_bwd(const float* weights, const float* grad_weights, float* grad_logits, int32_t n_channels,
+                           int64_t n_voxels, void* stream) {
+  clear_error();
+  if (!weights || !grad_weights || !grad_logits) return fail(MNR_E_INVALID, "softmax_bwd: null pointer");
+  if (n_channels < 1 || n_channels > 64 || n_voxels < 0) return fail(MNR_E_SHAPE, "softmax_bwd: bad shape");
+  if (n_voxels == 0) return MNR_OK;
+  return hip_status(launch_softmax_bwd(weights, grad_weights, grad_logits, n_channels, n_voxels, (hipStream_t)stream),
+                    "softmax_bwd launch");
+}
+
+mnr_status mnr_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int32_t step, void* lowp, mnr_dtype lowp_dtype, void* stream) {
+  clear_error();
+  if (!param || !grad || !m || !v) return fail(MNR_E_INVALID, "adam: null pointer");
+  if (n < 0 || step < 1) return fail(MNR_E_SHAPE, "adam: n >= 0 and step >= 1 required");
+  if (!(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && std::isfinite(lr)))
+    return fail(MNR_E_INVALID, "adam: bad hyper-parameters");
+  if (lowp && lowp_dtype != MNR_F16 && lowp_dtype != MNR_BF16) return fail(MNR_E_DTYPE, "adam: low-precision copy must be F16 or BF16");
+  if (n == 0) return MNR_OK;
+  return hip_status(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, lowp, lowp_dtype, (hipStream_t)stream),
+                    "adam launch");
+}
+
+mnr_status mnr_convert(const float* src, void* dst, mnr_dtype dtype, int64_t n, void* stream) {
+  clear_error();
+  if (!src || !dst) return fail(MNR_E_INVALID, "convert: null pointer");
+  if (dtype != MNR_F16 && dtype != MNR_BF16) return fail(MNR_E_DTYPE, "convert: dtype must be F16 or BF16");
+  if (n < 0) return fail(MNR_E_SHAPE, "convert: n < 0");
+  if (n == 0) return MNR_OK;
+  return hip_status(launch_convert(src, dst, dtype, n, (hipStream_t)stream), "convert launch");
+}
+
+mnr_status mnr_zero(void* dst, size_t n_bytes, void* stream) {
+  clear_error();
+  if (!dst && n_bytes) return fail(MNR_E_INVALID, "zero: null pointer");
+  if (n_bytes % 4) return fail(MNR_E_SHAPE, "zero: size must be a multiple of 4 bytes");
+  if (n_bytes == 0) return MNR_OK;
+  return hip_status(launch_zero(dst, n_bytes, (hipStream_t)stream), "zero launch");
+}
+
+mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                          const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
+                          const int32_t* pixel_ids, int32_t n_rays, const float* target, mnr_train_state* st,
+                          void* stream) {
+  clear_error();
+  if (!st || !target) return fail(MNR_E_INVALID, "train_step: null state or target");
+  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, st->rgba)) return s;
+  if (!st->table_master || !st->table_grad || !st->table_m || !st->table_v || !st->weights_grad || !st->grad_rgba ||
+      !st->loss || !st->t_chunks)
+    return fail(MNR_E_INVALID, "train_step: null state buffer");
+  for (int k = 0; k < field->n_layers; ++k)
+    if (!st->w_master[k] || !st->w_grad[k] || !st->w_m[k] || !st->w_v[k])
+      return fail(MNR_E_INVALID, "train_step: null state buffer for layer %d", k);
+  if (st->train_motion && (!st->logits || !st->logits_grad || !st->logits_m || !st->logits_v))
+    return fail(MNR_E_INVALID, "train_step: null logits state");
+  if (field->table_dtype == MNR_F32 && field->table != st->table_master)
+    return fail(MNR_E_INVALID, "train_step: an F32 table must be the master copy itself");
+  for (int k = 0; k < field->n_layers; ++k)
+    if (field->mlp_dtype == MNR_F32 && field->w[k] != st->w_master[k])
+      return fail(MNR_E_INVALID, "train_step: F32 weights must be the master copies themselves");
+  if (st->step < 1) return fail(MNR_E_SHAPE, "train_step: step must be >= 1");
+  if (n_rays == 0) return MNR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t T = int64_t(1) << field->log2_T;
+  const int64_t n_table = (int64_t)field->n_levels * T * field->n_feat;
+  const int64_t n_vox = (int64_t)motion->res * motion->res * motion->res;
+  const int64_t n_wc = (int64_t)(motion->n_bones + 1) * n_vox;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; return r == hipSuccess; };
+  ok(launch_zero(st->table_grad, n_table * 4, s));
+  for (int k = 0; k < field->n_layers; ++k)
+    ok(launch_zero(st->w_grad[k], (size_t)field->width[k] * field->width[k + 1] * 4, s));
+  ok(launch_zero(st->weights_grad, n_wc * 4, s));
+  RenderArgs a;
+  pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
+  const int slots = slot_count(H, W, pixel_ids, n_rays);
+  a.out = st->rgba;
+  a.t_chunks = st->t_chunks;
+  ok(launch_render_fwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
+  ok(launch_mse(st->rgba, target, n_rays, st->grad_rgba, st->loss, s));
+  a.grad_rgba = st->grad_rgba;
+  a.grad_table = st->table_grad;
+  for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = st->w_grad[k];
+  a.grad_weights = st->weights_grad;
+  ok(launch_render_bwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
+  ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
+                 st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
+                 field->table_dtype, s));
+  for (int k = 0; k < field->n_layers; ++k)
+    ok(launch_adam(st->w_master[k], st->w_grad[k], st->w_m[k], st->w_v[k],
+                   (int64_t)field->width[k] * field->width[k + 1], st->lr_field, st->beta1, st->beta2, st->eps,
+                   st->step, field->mlp_dtype == MNR_F32 ? nullptr : (void*)field->w[k], field->mlp_dtype, s));
+  if (st->train_motion) {
+    ok(launch_zero(st->logits_grad, n_wc * 4, s));
+    ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));
+    ok(launch_adam(st->logits, st->logits_grad, st->logits_m, st->logits_v, n_wc, st->lr_motion, st->beta1,
+                   st->beta2, st->eps, st->step, nullptr, MNR_F32, s));
+    ok(launch_softmax_fwd(st->logits, (float*)motion->weights, motion->n_bones + 1, n_vox, s));
+  }
+  return hip_status(e, "train_step launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,361 @@
+// Per-sample stages of the posed-body renderer, as device functions shared by
+// the forward and adjoint kernels:
+//   warp_sample   inverse linear blend skinning (Sec. 4.2, Eq. 7-9)
+//   encode_level  one level of the multiresolution grid encoding of the
+//                 canonical field's input (Sec. 4.4, Eq. 13)
+//   stage_weights / mlp_tile  the bias-free MLP of Eq. 13 on MFMA
+#pragma once
+#include "device_common.h"
+
+namespace mnr {
+
+// ---------------------------------------------------------------------------
+// Inverse LBS: y_i = G_i x, w_i = trilinear(W^c_i, y_i) (zero outside the
+// volume), L = sum_i w_i, x_skel = sum_i w_i y_i / max(L, eps).
+// ---------------------------------------------------------------------------
+
+struct Tri {  // trilinear cell of one point in a zero-padded volume
+  int i0[3];
+  float f[3];
+};
+
+__device__ __forceinline__ Tri tri_cell(float qx, float qy, float qz) {
+  Tri t;
+  const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+  t.i0[0] = (int)fx; t.i0[1] = (int)fy; t.i0[2] = (int)fz;
+  t.f[0] = qx - fx; t.f[1] = qy - fy; t.f[2] = qz - fz;
+  return t;
+}
+
+// Trilinear sample of one channel plane [R^3] with zero padding.
+__device__ __forceinline__ float tri_sample(const float* __restrict__ plane, int R, const Tri& t) {
+  float v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ix = t.i0[0] + (c & 1), iy = t.i0[1] + ((c >> 1) & 1), iz = t.i0[2] + (c >> 2);
+    const bool ok = (unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R;
+    v[c] = ok ? plane[((size_t)iz * R + iy) * R + ix] : 0.0f;
+  }
+  const float fx = t.f[0], fy = t.f[1], fz = t.f[2];
+  const float x00 = v[0] + fx * (v[1] - v[0]), x10 = v[2] + fx * (v[3] - v[2]);
+  const float x01 = v[4] + fx * (v[5] - v[4]), x11 = v[6] + fx * (v[7] - v[6]);
+  const float y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
+  return y0 + fz * (y1 - y0);
+}
+
+__device__ __forceinline__ void bone_apply(const float* __restrict__ g, const float x[3], float y[3]) {
+  y[0] = fmaf(g[0], x[0], fmaf(g[1], x[1], fmaf(g[2], x[2], g[3])));
+  y[1] = fmaf(g[4], x[0], fmaf(g[5], x[1], fmaf(g[6], x[2], g[7])));
+  y[2] = fmaf(g[8], x[0], fmaf(g[9], x[1], fmaf(g[10], x[2], g[11])));
+}
+
+__device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G)[12], const float x[3],
+                                            float xs[3], float& L) {
+  const int R = m.res;
+  const size_t plane = (size_t)R * R * R;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, sum = 0.f;
+#pragma unroll 1
+  for (int b = 0; b < m.n_bones; ++b) {
+    float y[3];
+    bone_apply(G[b], x, y);
+    const Tri t = tri_cell((y[0] - m.mmin[0]) * m.mscale[0], (y[1] - m.mmin[1]) * m.mscale[1],
+                           (y[2] - m.mmin[2]) * m.mscale[2]);
+    const float w = tri_sample(m.weights + b * plane, R, t);
+    sum += w;
+    acc0 = fmaf(w, y[0], acc0);
+    acc1 = fmaf(w, y[1], acc1);
+    acc2 = fmaf(w, y[2], acc2);
+  }
+  L = sum;
+  const float inv = 1.0f / fmaxf(sum, EPS_L);
+  xs[0] = acc0 * inv; xs[1] = acc1 * inv; xs[2] = acc2 * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Grid encoding of one level.
+// ---------------------------------------------------------------------------
+
+template <typename TableT>
+__device__ __forceinline__ f2 load_feat2(const TableT* __restrict__ p);
+template <>
+__device__ __forceinline__ f2 load_feat2<float>(const float* __restrict__ p) {
+  return *(const f2*)p;
+}
+template <>
+__device__ __forceinline__ f2 load_feat2<_Float16>(const _Float16* __restrict__ p) {
+  const h2 v = *(const h2*)p;
+  return f2{(float)v[0], (float)v[1]};
+}
+
+// Cell of point u (in [0,1]^3) at resolution N: i0 = min(floor(uN), N-1).
+struct GridCell {
+  int i0[3];
+  float f[3];
+};
+
+__device__ __forceinline__ GridCell grid_cell(const float u[3], int N) {
+  GridCell c;
+  const float Nf = (float)N;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float p = u[a] * Nf;
+    const float fl = fminf(floorf(p), Nf - 1.0f);
+    c.i0[a] = (int)fl;
+    c.f[a] = p - fl;
+  }
+  return c;
+}
+
+// Row of corner (dx,dy,dz) of the cell, dense or spatially hashed.
+__device__ __forceinline__ uint32_t grid_row(const GridCell& c, int N, bool dense, uint32_t mask, int k) {
+  const uint32_t x = c.i0[0] + (k & 1), y = c.i0[1] + ((k >> 1) & 1), z = c.i0[2] + (k >> 2);
+  if (dense) {
+    const uint32_t s = (uint32_t)N + 1u;
+    return x + s * (y + s * z);
+  }
+  return (x * 1u ^ y * 2654435761u ^ z * 805459861u) & mask;
+}
+
+template <typename TableT>
+__device__ __forceinline__ f2 encode_level(const TableT* __restrict__ level_table, const float u[3], int N,
+                                           bool dense, uint32_t mask) {
+  const GridCell c = grid_cell(u, N);
+  f2 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = load_feat2(level_table + 2 * (size_t)grid_row(c, N, dense, mask, k));
+  const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+  const f2 x00 = v[0] + fx * (v[1] - v[0]), x10 = v[2] + fx * (v[3] - v[2]);
+  const f2 x01 = v[4] + fx * (v[5] - v[4]), x11 = v[6] + fx * (v[7] - v[6]);
+  const f2 y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
+  return y0 + fz * (y1 - y0);
+}
+
+__device__ __forceinline__ void unit_coords(const FieldArgs& f, const float xs[3], float u[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = fminf(fmaxf((xs[a] - f.gmin[a]) * f.gscale[a], 0.0f), 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// MLP on MFMA.
+//
+// LDS weight layout, per layer: fragments [mt][kg][lane] of 16 bytes.
+//   F32 : kg = 16-input tile t; element j = input 16t + 4g + j (g = lane/16)
+//   BF16: kg = 32-input step s; element e = input 16(2s + e/4) + 4g + e%4
+// Row m of the fragment is output 16mt + lane%16; the output layer is padded
+// to 16 rows with zeros.
+// Per-wave feature layout (B operand of layer 1), F32: [nt][t][lane] x 4
+// floats; BF16: [nt][lane] x 8 bf16; sample = 16nt + lane%16, same K order.
+// ---------------------------------------------------------------------------
+
+template <int P>
+struct MlpShape {
+  static constexpr int KG_IN = (P == MNR_F32) ? IN_FEAT / 16 : IN_FEAT / 32;
+  static constexpr int KG_HID = (P == MNR_F32) ? HIDDEN / 16 : HIDDEN / 32;
+  static constexpr int FRAG = 64 * 16;  // bytes per fragment
+  static constexpr int bytes_first() { return 4 * KG_IN * FRAG; }
+  static constexpr int bytes_hidden() { return 4 * KG_HID * FRAG; }
+  static constexpr int bytes_out() { return KG_HID * FRAG; }
+  static constexpr int bytes_total(int nhh) { return bytes_first() + nhh * bytes_hidden() + bytes_out(); }
+  static constexpr int feat_bytes_per_wave() { return 64 * IN_FEAT * (P == MNR_F32 ? 4 : 2); }
+};
+
+// Position of weight (m, k) of a layer inside its fragments.
+template <int P>
+__device__ __forceinline__ int frag_offset(int m, int k, int kgroups) {
+  const int mt = m >> 4, t = k >> 4, g = (k & 15) >> 2, j = k & 3;
+  const int lane = (m & 15) + 16 * g;
+  if (P == MNR_F32) return (((mt * kgroups + t) * 64 + lane) * 4 + j) * 4;                 // bytes
+  return (((mt * kgroups + (t >> 1)) * 64 + lane) * 8 + (t & 1) * 4 + j) * 2;              // bytes
+}
+
+template <int P, typename WT>
+__device__ void stage_layer(char* lds, const WT* __restrict__ w, int M, int K, int Mpad) {
+  const int kg = (P == MNR_F32) ? K / 16 : K / 32;
+  for (int e = threadIdx.x; e < Mpad * K; e += blockDim.x) {
+    const int m = e / K, k = e - m * K;
+    const float v = (m < M) ? (float)w[(size_t)m * K + k] : 0.0f;
+    if (P == MNR_F32)
+      *(float*)(lds + frag_offset<P>(m, k, kg)) = v;
+    else
+      *(__bf16*)(lds + frag_offset<P>(m, k, kg)) = (__bf16)v;
+  }
+}
+
+// Stage all layers: first (IN_FEAT -> 64), nhh x (64 -> 64), out (64 -> 4).
+template <int P, int NHH>
+__device__ void stage_weights(char* lds, const FieldArgs& f) {
+  typedef typename std::conditional<P == MNR_F32, float, __bf16>::type WT;
+  using S = MlpShape<P>;
+  stage_layer<P>(lds, (const WT*)f.w[0], HIDDEN, IN_FEAT, HIDDEN);
+  for (int l = 0; l < NHH; ++l)
+    stage_layer<P>(lds + S::bytes_first() + l * S::bytes_hidden(), (const WT*)f.w[1 + l], HIDDEN, HIDDEN,
+                   HIDDEN);
+  stage_layer<P>(lds + S::bytes_first() + NHH * S::bytes_hidden(), (const WT*)f.w[1 + NHH], 4, HIDDEN, 16);
+}
+
+// Feature store (lane = sample s, features k, k+1 of the 32).
+template <int P>
+__device__ __forceinline__ void store_feat2(char* feat, int s, int k, f2 v) {
+  const int nt = s >> 4, c = s & 15, t = k >> 4, g = (k & 15) >> 2, j = k & 3;
+  const int lane = c + 16 * g;
+  if (P == MNR_F32) {
+    *(f2*)(feat + (((nt * 2 + t) * 64 + lane) * 4 + j) * 4) = v;
+  } else {
+    bf16x2 b = {(__bf16)v[0], (__bf16)v[1]};
+    *(bf16x2*)(feat + ((nt * 64 + lane) * 8 + t * 4 + j) * 2) = b;
+  }
+}
+
+__device__ __forceinline__ f4 relu4(f4 v) {
+  return f4{fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f)};
+}
+
+__device__ __forceinline__ bf16x8 pack_bf16(f4 lo, f4 hi) {
+  bf16x8 b;
+  b[0] = (__bf16)lo[0]; b[1] = (__bf16)lo[1]; b[2] = (__bf16)lo[2]; b[3] = (__bf16)lo[3];
+  b[4] = (__bf16)hi[0]; b[5] = (__bf16)hi[1]; b[6] = (__bf16)hi[2]; b[7] = (__bf16)hi[3];
+  return b;
+}
+
+// One dense layer: out[mt] = W x, K = 16 * (number of input tiles).
+template <int P, int MT, int KT>
+__device__ __forceinline__ void mma_layer(const char* wl, const f4 (&x)[4], f4 (&out)[4], int lane) {
+  if constexpr (P == MNR_F32) {
+    const f4* W = (const f4*)wl;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const f4 a = W[(mt * KT + t) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], x[t][j], acc, 0, 0, 0);
+      }
+      out[mt] = acc;
+    }
+  } else {
+    const bf16x8* W = (const bf16x8*)wl;
+    constexpr int KS = KT / 2;
+    bf16x8 b[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+      out[mt] = acc;
+    }
+  }
+}
+
+// Layer-1 input of sample tile nt from the wave's feature buffer, as the
+// activation registers x[t] (t = 0, 1) of the F32 layout.
+template <int P>
+__device__ __forceinline__ void load_input(const char* feat, int nt, int lane, f4 (&x)[4]) {
+  if constexpr (P == MNR_F32) {
+    x[0] = ((const f4*)feat)[(nt * 2 + 0) * 64 + lane];
+    x[1] = ((const f4*)feat)[(nt * 2 + 1) * 64 + lane];
+  } else {
+    const bf16x8 b = ((const bf16x8*)feat)[nt * 64 + lane];
+    x[0] = f4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
+    x[1] = f4{(float)b[4], (float)b[5], (float)b[6], (float)b[7]};
+  }
+  x[2] = x[3] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Whole MLP for the 16 samples of tile nt.  Returns the output fragment:
+// lanes 0..15 hold (o0, o1, o2, o3) of sample 16nt + lane.  If `hidden` is
+// non-null, the post-ReLU activations of every hidden layer are stored
+// there ([layer][mt] fragments, for the adjoint).
+template <int P, int NHH>
+__device__ __forceinline__ f4 mlp_tile(const char* wl, const char* feat, int nt, int lane,
+                                       f4 (*hidden)[4] = nullptr) {
+  using S = MlpShape<P>;
+  f4 x[4], h[4];
+  load_input<P>(feat, nt, lane, x);
+  mma_layer<P, 4, 2>(wl, x, h, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(h[mt]);
+  if (hidden) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) hidden[0][mt] = h[mt];
+  }
+#pragma unroll
+  for (int l = 0; l < NHH; ++l) {
+    f4 nh[4];
+    mma_layer<P, 4, 4>(wl + S::bytes_first() + l * S::bytes_hidden(), h, nh, lane);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(nh[mt]);
+    if (hidden) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) hidden[l + 1][mt] = h[mt];
+    }
+  }
+  f4 o[4];
+  mma_layer<P, 1, 4>(wl + S::bytes_first() + NHH * S::bytes_hidden(), h, o, lane);
+  return o[0];
+}
+
+// ---------------------------------------------------------------------------
+// One 64-sample chunk of a ray: sample position, inverse LBS, encoding (into
+// the wave's LDS feature buffer) and the MLP.  Lane i handles sample
+// 64*ch + i.  Returns the ballot of live lanes (valid sample with L > 0);
+// when it is zero nothing else was computed.  On return, lane i holds its
+// sample's raw MLP outputs in `out` (the per-wave scratch `obuf`, 64 x f4,
+// is used for the lane transpose).
+// ---------------------------------------------------------------------------
+
+struct SampleState {
+  float x[3], xs[3], L;
+  bool live;
+};
+
+template <typename TableT, int P, int NHH>
+__device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySetup& rs, int ray_index, int ch,
+                                               int lane, const char* wl, char* feat, f4* obuf, SampleState& st,
+                                               f4& out) {
+  const int S_ = a.r.spp;
+  const int i = ch * 64 + lane;
+  const bool valid = i < S_;
+  float xi = 0.5f;
+  if (a.r.stratified) xi = (float)(splitmix64(a.r.seed, (uint64_t)ray_index * S_ + i) >> 40) * 0x1p-24f;
+  const float s = ((float)i + xi) * rs.delta;
+  st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+  st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+  st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+  st.L = 0.f;
+  st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
+  if (valid) warp_sample(a.m, a.G, st.x, st.xs, st.L);
+  st.live = valid && st.L > 0.f;
+  const uint64_t live_mask = __ballot(st.live);
+  if (live_mask == 0) return 0;
+
+  const TableT* table = (const TableT*)a.f.table;
+  const size_t T = (size_t)1 << a.f.log2_T;
+  const uint32_t mask = (uint32_t)T - 1u;
+  float u[3];
+  unit_coords(a.f, st.xs, u);
+#pragma unroll 1
+  for (int l = 0; l < a.f.n_levels; ++l) {
+    f2 v = {0.f, 0.f};
+    if (st.live)
+      v = encode_level<TableT>(table + (size_t)l * T * 2, u, a.f.level_res[l], (a.f.dense_mask >> l) & 1u, mask);
+    store_feat2<P>(feat, lane, 2 * l, v);
+  }
+  wave_sync_lds();
+  f4 o[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) o[nt] = mlp_tile<P, NHH>(wl, feat, nt, lane);
+  if (lane < 16) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) obuf[nt * 16 + lane] = o[nt];
+  }
+  wave_sync_lds();
+  out = obuf[lane];
+  wave_sync_lds();
+  return live_mask;
+}
+
+}  // namespace mnr

@@ -1,0 +1,26 @@
+// Host-side launchers of the gfx950 kernels (implemented in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace mnr {
+
+// Fused forward renderer.  n_slots: number of ray slots (n_rays, or the
+// 16x16-tiled full frame).  nhh: number of 64->64 hidden layers.
+hipError_t launch_render_fwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
+                             hipStream_t st);
+
+// Adjoint of the forward renderer (accumulates gradients).
+hipError_t launch_render_bwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
+                             hipStream_t st);
+
+hipError_t launch_mse(const float* rgba, const float* target, int n, float* grad, float* loss, hipStream_t st);
+hipError_t launch_softmax_fwd(const float* logits, float* w, int C, int64_t V, hipStream_t st);
+hipError_t launch_softmax_bwd(const float* w, const float* g, float* gl, int C, int64_t V, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int step, void* lowp, mnr_dtype dt, hipStream_t st);
+hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st);
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
+
+}  // namespace mnr

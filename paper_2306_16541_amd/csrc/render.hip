@@ -1,0 +1,144 @@
+// Fused forward renderer (Sec. 4, Fig. 2): one wavefront owns one ray at a
+// time and walks it in chunks of 64 samples, one sample per lane:
+//   sample inside the body box (Sec. 4.4) -> inverse LBS (Eq. 7-9)
+//   -> grid encoding -> MLP on MFMA (Eq. 13) -> front-to-back compositing
+//   with the likelihood augmentation (Eq. 3, Sec. 4.4) as a wave
+//   prefix-product; transmittance is carried across chunks and the ray stops
+//   after the chunk where it falls below ert_tau.
+// Persistent grid: blocks stage the MLP weights into LDS once and loop over
+// rays.  Rays are grouped in 16x16-pixel tiles dealt round-robin to the
+// eight XCDs (block b runs on XCD b % 8), so each XCD's L2 sees spatially
+// coherent gathers.
+#include "field_device.h"
+#include "kernels.h"
+
+namespace mnr {
+
+// Ray slot handled by iteration `it` of wave `w` of block `blk`.
+__device__ __forceinline__ int ray_slot(int blk, int nblk, int w, int it, int n_slots) {
+  const int xcd = blk & 7, lb = blk >> 3;
+  const int nb = (nblk - xcd + 7) >> 3;  // blocks on this XCD
+  const int k = (it * nb + lb) * WAVES_PER_BLOCK + w;  // k-th ray of this XCD
+  const int slot = ((k >> 8) * 8 + xcd) * 256 + (k & 255);
+  return slot < n_slots ? slot : -1;
+}
+
+__device__ __forceinline__ int n_iters(int nblk, int n_slots) {
+  // Enough iterations for the least-loaded XCD to cover its tiles.
+  const int tiles = (n_slots + 255) >> 8;
+  const int tiles_per_xcd = (tiles + 7) >> 3;
+  const int nb_min = nblk >> 3 > 0 ? nblk >> 3 : 1;
+  return (tiles_per_xcd * 256 + nb_min * WAVES_PER_BLOCK - 1) / (nb_min * WAVES_PER_BLOCK);
+}
+
+template <typename TableT, int P, int NHH>
+__global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, int n_slots) {
+  using S = MlpShape<P>;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  char* wl = lds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* feat = lds + S::bytes_total(NHH) + wave * S::feat_bytes_per_wave();
+
+  stage_weights<P, NHH>(wl, a.f);
+  __syncthreads();
+
+  const int S_ = a.r.spp;
+  const int nchunks = (S_ + 63) >> 6;
+  const int iters = n_iters(gridDim.x, n_slots);
+
+  for (int it = 0; it < iters; ++it) {
+    const int slot = ray_slot(blockIdx.x, gridDim.x, wave, it, n_slots);
+    if (slot < 0) continue;
+    const int pix = ray_pixel(a.r, slot);
+    if (!a.r.pixel_ids && pix < 0) continue;  // tile slot outside the image
+    const int orow = a.r.pixel_ids ? slot : pix;
+    RaySetup rs;
+    const bool hit = pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;
+    unsigned live_count = 0;
+    int done = 0;  // chunks processed
+    if (hit) {
+      for (int ch = 0; ch < nchunks; ++ch) {
+        if (a.t_chunks && lane == 0) a.t_chunks[(size_t)orow * nchunks + ch] = Tr;
+        done = ch + 1;
+        SampleState st;
+        f4 out;
+        const uint64_t live_mask =
+            chunk_eval<TableT, P, NHH>(a, rs, orow, ch, lane, wl, feat, (f4*)feat, st, out);
+        if (live_mask == 0) continue;  // nothing visible in this chunk (alpha' = 0)
+        live_count += __popcll(live_mask);
+        const bool live = st.live;
+        const float L = st.L;
+
+        // Composite: alpha = 1 - exp(-sigma delta), alpha' = alpha min(L, 1).
+        const float sigma = fmaxf(out[3], 0.f);
+        const float alpha = -expm1f(-sigma * rs.delta);
+        const float ap = live ? alpha * fminf(L, 1.f) : 0.f;
+        const float incl = wave_prefix_prod(1.f - ap);
+        float excl = shfl_up(incl, 1);
+        if (lane == 0) excl = 1.f;
+        const float w = Tr * excl * ap;
+        const float c0 = 1.f / (1.f + expf(-out[0]));
+        const float c1 = 1.f / (1.f + expf(-out[1]));
+        const float c2 = 1.f / (1.f + expf(-out[2]));
+        C0 += wave_sum(w * c0);
+        C1 += wave_sum(w * c1);
+        C2 += wave_sum(w * c2);
+        Tr *= __shfl(incl, 63, WAVE);
+        if (Tr < a.r.ert_tau) break;
+      }
+    }
+    if (a.t_chunks)
+      for (int ch = done + lane; ch < nchunks; ch += 64) a.t_chunks[(size_t)orow * nchunks + ch] = -1.f;
+    if (lane == 0) {
+      f4 res = {C0 + Tr * a.r.bg[0], C1 + Tr * a.r.bg[1], C2 + Tr * a.r.bg[2], 1.f - Tr};
+      *(f4*)(a.out + (size_t)orow * 4) = res;
+      if (a.n_eval && live_count) atomicAdd(a.n_eval, (unsigned long long)live_count);
+    }
+  }
+}
+
+template <typename TableT, int P, int NHH>
+static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+  using S = MlpShape<P>;
+  const int lds = S::bytes_total(NHH) + WAVES_PER_BLOCK * S::feat_bytes_per_wave();
+  auto kern = render_fwd_kernel<TableT, P, NHH>;
+  static int max_blocks = 0;  // per instantiation
+  if (max_blocks == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds);
+    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  const int need = (n_slots + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  int grid = need < max_blocks ? need : max_blocks;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, st, a, n_slots);
+  return hipGetLastError();
+}
+
+template <int P, int NHH>
+static hipError_t launch_fwd_p(const RenderArgs& a, int n_slots, mnr_dtype tdt, hipStream_t st) {
+  if (tdt == MNR_F16) return launch_fwd_t<_Float16, P, NHH>(a, n_slots, st);
+  return launch_fwd_t<float, P, NHH>(a, n_slots, st);
+}
+
+hipError_t launch_render_fwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt,
+                             int nhh, hipStream_t st) {
+  if (mlp_dt == MNR_BF16) {
+    switch (nhh) {
+      case 0: return launch_fwd_p<MNR_BF16, 0>(a, n_slots, table_dt, st);
+      case 1: return launch_fwd_p<MNR_BF16, 1>(a, n_slots, table_dt, st);
+      default: return launch_fwd_p<MNR_BF16, 2>(a, n_slots, table_dt, st);
+    }
+  }
+  switch (nhh) {
+    case 0: return launch_fwd_p<MNR_F32, 0>(a, n_slots, table_dt, st);
+    case 1: return launch_fwd_p<MNR_F32, 1>(a, n_slots, table_dt, st);
+    default: return launch_fwd_p<MNR_F32, 2>(a, n_slots, table_dt, st);
+  }
+}
+
+}  // namespace mnr

@@ -1,0 +1,418 @@
+// Hand-written adjoint of the fused renderer (training, Sec. 5.2).
+//
+// One wavefront per ray, walking the chunks the forward pass processed from
+// last to first.  Nothing per-sample is stored by the forward pass: each
+// chunk is recomputed (sample, inverse LBS, encoding, MLP) and then
+//   1. compositing adjoint (Eq. 3 with alpha' = alpha * min(L, 1)): with
+//      S_i = alpha'_i c_i + (1 - alpha'_i) S_{i+1} (S after the last
+//      processed sample = background colour; the opacity channel uses
+//      c = 1, background 0), dC/dc_i = T_i alpha'_i and
+//      dC/dalpha'_i = T_i (c_i - S_{i+1}).  S_{i+1} comes from a reverse
+//      affine scan across the wave (division-free), T_i from the saved
+//      chunk-start transmittance and a forward prefix product;
+//   2. MLP adjoint on MFMA, 16 samples at a time: activations recomputed
+//      with the forward weights, dX = W^T dY with transposed weight
+//      fragments, dW = dY X^T accumulated per block in LDS float atomics;
+//   3. encoding adjoint: scatter-add into the table gradient and the
+//      encoding's spatial derivative back to the skinned point x_skel;
+//   4. skinning adjoint (Eq. 7, 9): dx_skel/dw_i = (y_i - x_skel)/L and the
+//      likelihood term dalpha'/dL = alpha [L < 1], scattered through the
+//      trilinear weights into dL/dW^c.
+#include "field_device.h"
+#include "kernels.h"
+
+namespace mnr {
+
+template <int P>
+struct BwdShape {
+  using S = MlpShape<P>;
+  using TB = typename std::conditional<P == MNR_F32, float, __bf16>::type;  // transpose buffer element
+  static constexpr int KT_OUTT = (P == MNR_F32) ? 1 : 2;  // padded K tiles of the transposed output layer
+  static constexpr int KG64 = (P == MNR_F32) ? 4 : 2;     // k-groups of a 64-wide K
+  static constexpr int bytes_first_t() { return 2 * KG64 * S::FRAG; }
+  static constexpr int bytes_hidden_t() { return 4 * KG64 * S::FRAG; }
+  static constexpr int bytes_out_t() { return 4 * 1 * S::FRAG; }
+  static constexpr int bytes_t(int nhh) { return bytes_first_t() + nhh * bytes_hidden_t() + bytes_out_t(); }
+  static constexpr int dw_floats(int nhh) { return HIDDEN * IN_FEAT + nhh * HIDDEN * HIDDEN + 4 * HIDDEN; }
+  static constexpr int tbuf_bytes() { return 2 * 64 * 16 * (int)sizeof(TB); }
+  static constexpr int wave_bytes() { return S::feat_bytes_per_wave() + 64 * IN_FEAT * 4 + tbuf_bytes(); }
+  static constexpr int lds_bytes(int nhh, int nw) {
+    return S::bytes_total(nhh) + bytes_t(nhh) + dw_floats(nhh) * 4 + nw * wave_bytes();
+  }
+};
+
+// Stage W^T of a layer W [M][K] as the A operand of an (K x Mpad) product.
+template <int P, typename WT>
+__device__ void stage_layer_t(char* lds, const WT* __restrict__ w, int M, int K, int Kpad) {
+  const int kg = (P == MNR_F32) ? Kpad / 16 : Kpad / 32;
+  for (int e = threadIdx.x; e < K * Kpad; e += blockDim.x) {
+    const int m = e / Kpad, k = e - m * Kpad;  // element (m, k) of W^T = W[k][m]
+    const float v = (k < M) ? (float)w[(size_t)k * K + m] : 0.0f;
+    if (P == MNR_F32)
+      *(float*)(lds + frag_offset<P>(m, k, kg)) = v;
+    else
+      *(__bf16*)(lds + frag_offset<P>(m, k, kg)) = (__bf16)v;
+  }
+}
+
+template <int P, int NHH>
+__device__ void stage_weights_t(char* lds, const FieldArgs& f) {
+  typedef typename std::conditional<P == MNR_F32, float, __bf16>::type WT;
+  using B = BwdShape<P>;
+  stage_layer_t<P>(lds, (const WT*)f.w[0], HIDDEN, IN_FEAT, HIDDEN);
+  for (int l = 0; l < NHH; ++l)
+    stage_layer_t<P>(lds + B::bytes_first_t() + l * B::bytes_hidden_t(), (const WT*)f.w[1 + l], HIDDEN, HIDDEN,
+                     HIDDEN);
+  stage_layer_t<P>(lds + B::bytes_first_t() + NHH * B::bytes_hidden_t(), (const WT*)f.w[1 + NHH], 4, HIDDEN,
+                   (P == MNR_F32) ? 16 : 32);
+}
+
+__device__ __forceinline__ f4 relu_mask(f4 d, f4 h) {
+  return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
+}
+
+// dW[M_out x K_in] += dY (MT tiles, D layout) x X^T (NT tiles, D layout), over
+// the 16 samples of one tile, accumulated into LDS with float atomics.
+template <int P, int MT, int NT>
+__device__ __forceinline__ void accumulate_dw(typename BwdShape<P>::TB* tb, const f4 (&d)[4], const f4 (&h)[4],
+                                              float* dw, int M_out, int K_in, int lane) {
+  using TB = typename BwdShape<P>::TB;
+  TB* td = tb;            // [64 neurons][16 samples]
+  TB* th = tb + 64 * 16;  // [64 neurons][16 samples]
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) td[(16 * t + 4 * g + j) * 16 + c] = (TB)d[t][j];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (TB)h[t][j];
+  wave_sync_lds();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (P == MNR_F32) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(td[(16 * mt + c) * 16 + 4 * s + g],
+                                                     th[(16 * kt + c) * 16 + 4 * s + g], acc, 0, 0, 0);
+      } else {
+        bf16x8 av, bv;
+        if (g < 2) {
+          av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
+          bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * mt + 4 * g + j;
+        if (row < M_out) atomicAdd(dw + row * K_in + 16 * kt + c, acc[j]);
+      }
+    }
+  }
+  wave_sync_lds();
+}
+
+// MLP adjoint for sample tile nt.  dout: output-layer gradient in D layout
+// (lanes 0..15 hold d/do of sample 16nt + lane).  Writes d/dfeature of the
+// 16 samples into dfeat[sample][32].
+template <int P, int NHH>
+__device__ __forceinline__ void mlp_tile_backward(const char* wl, const char* wt, const char* feat, int nt, int lane,
+                                                  f4 dout, typename BwdShape<P>::TB* tb, float* dw, float* dfeat) {
+  using S = MlpShape<P>;
+  using B = BwdShape<P>;
+  f4 x[4], hid[NHH + 1][4], tmp[4];
+  load_input<P>(feat, nt, lane, x);
+  mma_layer<P, 4, 2>(wl, x, tmp, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) hid[0][mt] = relu4(tmp[mt]);
+#pragma unroll
+  for (int l = 0; l < NHH; ++l) {
+    mma_layer<P, 4, 4>(wl + S::bytes_first() + l * S::bytes_hidden(), hid[l], tmp, lane);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) hid[l + 1][mt] = relu4(tmp[mt]);
+  }
+  float* dw_first = dw;
+  float* dw_hidden = dw + HIDDEN * IN_FEAT;
+  float* dw_out = dw_hidden + NHH * HIDDEN * HIDDEN;
+  const f4 z = {0.f, 0.f, 0.f, 0.f};
+  f4 d[4] = {dout, z, z, z};
+  // output layer
+  accumulate_dw<P, 1, 4>(tb, d, hid[NHH], dw_out, 4, HIDDEN, lane);
+  mma_layer<P, 4, B::KT_OUTT>(wt + B::bytes_first_t() + NHH * B::bytes_hidden_t(), d, tmp, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask(tmp[mt], hid[NHH][mt]);
+  // hidden layers, last to first
+#pragma unroll
+  for (int l = NHH - 1; l >= 0; --l) {
+    accumulate_dw<P, 4, 4>(tb, d, hid[l], dw_hidden + l * HIDDEN * HIDDEN, HIDDEN, HIDDEN, lane);
+    mma_layer<P, 4, 4>(wt + B::bytes_first_t() + l * B::bytes_hidden_t(), d, tmp, lane);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask(tmp[mt], hid[l][mt]);
+  }
+  // first layer
+  accumulate_dw<P, 4, 2>(tb, d, x, dw_first, HIDDEN, IN_FEAT, lane);
+  mma_layer<P, 2, 4>(wt, d, tmp, lane);
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dfeat[(16 * nt + c) * IN_FEAT + 16 * mt + 4 * g + j] = tmp[mt][j];
+}
+
+// Ray slot mapping shared with the forward kernel (16x16 tiles dealt to XCDs).
+template <int NW>
+__device__ __forceinline__ int bwd_ray_slot(int blk, int nblk, int w, int it, int n_slots) {
+  const int xcd = blk & 7, lb = blk >> 3;
+  const int nb = (nblk - xcd + 7) >> 3;
+  const int k = (it * nb + lb) * NW + w;
+  const int slot = ((k >> 8) * 8 + xcd) * 256 + (k & 255);
+  return slot < n_slots ? slot : -1;
+}
+
+template <typename TableT, int P, int NHH, int NW>
+__global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a, int n_slots) {
+  using S = MlpShape<P>;
+  using B = BwdShape<P>;
+  using TB = typename B::TB;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  char* wl = lds;
+  char* wt = wl + S::bytes_total(NHH);
+  float* dw = (float*)(wt + B::bytes_t(NHH));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* wbase = (char*)(dw + B::dw_floats(NHH)) + wave * B::wave_bytes();
+  char* feat = wbase;
+  float* dfeat = (float*)(wbase + S::feat_bytes_per_wave());
+  TB* tb = (TB*)(wbase + S::feat_bytes_per_wave() + 64 * IN_FEAT * 4);
+
+  stage_weights<P, NHH>(wl, a.f);
+  stage_weights_t<P, NHH>(wt, a.f);
+  for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) dw[i] = 0.f;
+  __syncthreads();
+
+  const TableT* table = (const TableT*)a.f.table;
+  const size_t T = (size_t)1 << a.f.log2_T;
+  const uint32_t tmask = (uint32_t)T - 1u;
+  const int S_ = a.r.spp;
+  const int nchunks = (S_ + 63) >> 6;
+  const int R = a.m.res;
+  const size_t plane = (size_t)R * R * R;
+  const int tiles = (n_slots + 255) >> 8;
+  const int nb_min = (gridDim.x >> 3) > 0 ? (gridDim.x >> 3) : 1;
+  const int iters = (((tiles + 7) >> 3) * 256 + nb_min * NW - 1) / (nb_min * NW);
+
+  for (int it = 0; it < iters; ++it) {
+    const int slot = bwd_ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
+    if (slot < 0) continue;
+    const int pix = ray_pixel(a.r, slot);
+    if (!a.r.pixel_ids && pix < 0) continue;
+    const int orow = a.r.pixel_ids ? slot : pix;
+    RaySetup rs;
+    if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) continue;
+    const f4 gout = *(const f4*)(a.grad_rgba + (size_t)orow * 4);
+    float Sc[4] = {a.r.bg[0], a.r.bg[1], a.r.bg[2], 0.f};  // S after the last processed sample
+    for (int ch = nchunks - 1; ch >= 0; --ch) {
+      const float T0 = a.t_chunks[(size_t)orow * nchunks + ch];
+      if (T0 < 0.f) continue;  // not reached by the forward pass
+      SampleState st;
+      f4 out;
+      const uint64_t live_mask =
+          chunk_eval<TableT, P, NHH>(a, rs, orow, ch, lane, wl, feat, (f4*)dfeat, st, out);
+      if (live_mask == 0) continue;  // alpha' = 0 everywhere: S passes through unchanged
+
+      // ---- 1. compositing adjoint -------------------------------------------------
+      const float sigma = fmaxf(out[3], 0.f);
+      const float alpha = -expm1f(-sigma * rs.delta);
+      const float mL = fminf(st.L, 1.f);
+      const float ap = st.live ? alpha * mL : 0.f;
+      float c[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) c[k] = 1.f / (1.f + expf(-out[k]));
+      const float incl = wave_prefix_prod(1.f - ap);
+      float excl = shfl_up(incl, 1);
+      if (lane == 0) excl = 1.f;
+      const float Ti = T0 * excl;
+      // reverse affine scan: S_i = b_i + a_i S_{i+1}
+      float A_ = 1.f - ap;
+      float Bv[4] = {ap * c[0], ap * c[1], ap * c[2], ap};
+#pragma unroll
+      for (int k = 1; k < WAVE; k <<= 1) {
+        const float Ak = shfl_down(A_, k);
+        float Bk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bk[q] = shfl_down(Bv[q], k);
+        if (lane + k < WAVE) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Bv[q] = fmaf(A_, Bk[q], Bv[q]);
+          A_ *= Ak;
+        }
+      }
+      float Si[4], Snext[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Si[q] = fmaf(A_, Sc[q], Bv[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Snext[q] = shfl_down(Si[q], 1);
+        if (lane == WAVE - 1) Snext[q] = Sc[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Sc[q] = __shfl(Si[q], 0, WAVE);
+      float g_ap = gout[3] * Ti * (1.f - Snext[3]);
+      float g_o[4];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        g_ap += gout[k] * Ti * (c[k] - Snext[k]);
+        g_o[k] = gout[k] * Ti * ap * c[k] * (1.f - c[k]);
+      }
+      const float g_sigma = g_ap * mL * rs.delta * (1.f - alpha);
+      g_o[3] = out[3] > 0.f ? g_sigma : 0.f;
+      const float g_L = (st.L < 1.f) ? g_ap * alpha : 0.f;
+      if (!st.live) g_o[0] = g_o[1] = g_o[2] = g_o[3] = 0.f;
+
+      // ---- 2. MLP adjoint -----------------------------------------------------------
+      f4* gobuf = (f4*)dfeat;
+      gobuf[lane] = f4{g_o[0], g_o[1], g_o[2], g_o[3]};
+      wave_sync_lds();
+      f4 dout[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) dout[nt] = (lane < 16) ? gobuf[nt * 16 + lane] : f4{0.f, 0.f, 0.f, 0.f};
+      wave_sync_lds();
+#pragma unroll 1
+      for (int nt = 0; nt < 4; ++nt) mlp_tile_backward<P, NHH>(wl, wt, feat, nt, lane, dout[nt], tb, dw, dfeat);
+      wave_sync_lds();
+
+      // ---- 3. encoding adjoint ------------------------------------------------------
+      if (st.live) {
+        float u[3], g_u[3] = {0.f, 0.f, 0.f};
+        unit_coords(a.f, st.xs, u);
+        const float* df = dfeat + lane * IN_FEAT;
+#pragma unroll 1
+        for (int l = 0; l < a.f.n_levels; ++l) {
+          const int N = a.f.level_res[l];
+          const bool dense = (a.f.dense_mask >> l) & 1u;
+          const GridCell gc = grid_cell(u, N);
+          const float d0 = df[2 * l], d1 = df[2 * l + 1];
+          const TableT* lt = table + (size_t)l * T * 2;
+          float* gt = a.grad_table + (size_t)l * T * 2;
+          float gp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t row = grid_row(gc, N, dense, tmask, k);
+            const float wx = (k & 1) ? gc.f[0] : 1.f - gc.f[0];
+            const float wy = (k & 2) ? gc.f[1] : 1.f - gc.f[1];
+            const float wz = (k & 4) ? gc.f[2] : 1.f - gc.f[2];
+            const float wk = wx * wy * wz;
+            unsafeAtomicAdd(gt + 2 * (size_t)row, wk * d0);
+            unsafeAtomicAdd(gt + 2 * (size_t)row + 1, wk * d1);
+            const f2 v = load_feat2(lt + 2 * (size_t)row);
+            const float dot = d0 * v[0] + d1 * v[1];
+            gp[0] += dot * ((k & 1) ? 1.f : -1.f) * wy * wz;
+            gp[1] += dot * ((k & 2) ? 1.f : -1.f) * wx * wz;
+            gp[2] += dot * ((k & 4) ? 1.f : -1.f) * wx * wy;
+          }
+#pragma unroll
+          for (int q = 0; q < 3; ++q) g_u[q] = fmaf(gp[q], (float)N, g_u[q]);
+        }
+        float g_xs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float ur = (st.xs[q] - a.f.gmin[q]) * a.f.gscale[q];
+          g_xs[q] = (ur > 0.f && ur < 1.f) ? g_u[q] * a.f.gscale[q] : 0.f;
+        }
+
+        // ---- 4. skinning adjoint ------------------------------------------------------
+        const bool above = st.L > EPS_L;
+        const float invL = 1.f / (above ? st.L : EPS_L);
+#pragma unroll 1
+        for (int b = 0; b < a.m.n_bones; ++b) {
+          float y[3];
+          bone_apply(a.G[b], st.x, y);
+          const float dx = above ? y[0] - st.xs[0] : y[0];
+          const float dy = above ? y[1] - st.xs[1] : y[1];
+          const float dz = above ? y[2] - st.xs[2] : y[2];
+          const float gw = (g_xs[0] * dx + g_xs[1] * dy + g_xs[2] * dz) * invL + g_L;
+          const Tri t = tri_cell((y[0] - a.m.mmin[0]) * a.m.mscale[0], (y[1] - a.m.mmin[1]) * a.m.mscale[1],
+                                 (y[2] - a.m.mmin[2]) * a.m.mscale[2]);
+          float* gplane = a.grad_weights + b * plane;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int ix = t.i0[0] + (k & 1), iy = t.i0[1] + ((k >> 1) & 1), iz = t.i0[2] + (k >> 2);
+            if ((unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R) {
+              const float wk = ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
+                               ((k & 4) ? t.f[2] : 1.f - t.f[2]);
+              unsafeAtomicAdd(gplane + ((size_t)iz * R + iy) * R + ix, gw * wk);
+            }
+          }
+        }
+      }
+      wave_sync_lds();
+    }
+  }
+  __syncthreads();
+  // flush the block's MLP weight gradients
+  const int n_first = HIDDEN * IN_FEAT, n_hid = HIDDEN * HIDDEN;
+  for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) {
+    const float v = dw[i];
+    if (v == 0.f) continue;
+    if (i < n_first) {
+      unsafeAtomicAdd(a.grad_w[0] + i, v);
+    } else if (i < n_first + NHH * n_hid) {
+      const int l = (i - n_first) / n_hid;
+      unsafeAtomicAdd(a.grad_w[1 + l] + (i - n_first - l * n_hid), v);
+    } else {
+      unsafeAtomicAdd(a.grad_w[1 + NHH] + (i - n_first - NHH * n_hid), v);
+    }
+  }
+}
+
+template <typename TableT, int P, int NHH>
+static hipError_t launch_bwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+  constexpr int NW = (P == MNR_F32) ? 1 : 4;
+  const int lds = BwdShape<P>::lds_bytes(NHH, NW);
+  auto kern = render_bwd_kernel<TableT, P, NHH, NW>;
+  static int max_blocks = 0;
+  if (max_blocks == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64 * NW, lds);
+    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  const int need = (n_slots + NW - 1) / NW;
+  int grid = need < max_blocks ? need : max_blocks;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, st, a, n_slots);
+  return hipGetLastError();
+}
+
+template <int P, int NHH>
+static hipError_t launch_bwd_p(const RenderArgs& a, int n_slots, mnr_dtype tdt, hipStream_t st) {
+  if (tdt == MNR_F16) return launch_bwd_t<_Float16, P, NHH>(a, n_slots, st);
+  return launch_bwd_t<float, P, NHH>(a, n_slots, st);
+}
+
+hipError_t launch_render_bwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
+                             hipStream_t st) {
+  if (mlp_dt == MNR_BF16) {
+    switch (nhh) {
+      case 0: return launch_bwd_p<MNR_BF16, 0>(a, n_slots, table_dt, st);
+      case 1: return launch_bwd_p<MNR_BF16, 1>(a, n_slots, table_dt, st);
+      default: return launch_bwd_p<MNR_BF16, 2>(a, n_slots, table_dt, st);
+    }
+  }
+  switch (nhh) {
+    case 0: return launch_bwd_p<MNR_F32, 0>(a, n_slots, table_dt, st);
+    case 1: return launch_bwd_p<MNR_F32, 1>(a, n_slots, table_dt, st);
+    default: return launch_bwd_p<MNR_F32, 2>(a, n_slots, table_dt, st);
+  }
+}
+
+}  // namespace mnr

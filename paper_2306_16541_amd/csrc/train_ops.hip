@@ -1,0 +1,128 @@
+// Elementwise and small-reduction kernels of the training step (Sec. 5.2):
+// the squared-error loss (MSE term of Eq. 14), the per-voxel softmax that
+// turns free logits into canonical blend weights W^c (Sec. 4.2) and its
+// adjoint, Adam (beta1 = 0.9, beta2 = 0.99 in the paper), precision
+// conversion of parameter copies, and a kernel fill.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace mnr {
+
+static inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (int)(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+
+// Single block: deterministic reduction order.
+__global__ void __launch_bounds__(1024) mse_kernel(const float* __restrict__ rgba, const float* __restrict__ tgt, int n,
+                                                   float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ float part[1024 / 64];
+  const float scale = 1.0f / (3.0f * (float)n);
+  float acc = 0.f;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const f4 c = *(const f4*)(rgba + 4 * (size_t)r);
+    const float e0 = c[0] - tgt[3 * (size_t)r], e1 = c[1] - tgt[3 * (size_t)r + 1], e2 = c[2] - tgt[3 * (size_t)r + 2];
+    acc += e0 * e0 + e1 * e1 + e2 * e2;
+    *(f4*)(grad + 4 * (size_t)r) = f4{2.f * scale * e0, 2.f * scale * e1, 2.f * scale * e2, 0.f};
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) {
+    float s = 0.f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += part[i];
+    loss[0] = s * scale;
+  }
+}
+
+hipError_t launch_mse(const float* rgba, const float* target, int n, float* grad, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, rgba, target, n, grad, loss);
+  return hipGetLastError();
+}
+
+__global__ void softmax_fwd_kernel(const float* __restrict__ x, float* __restrict__ w, int C, int64_t V) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x) {
+    float mx = -INFINITY;
+    for (int c = 0; c < C; ++c) mx = fmaxf(mx, x[c * V + v]);
+    float s = 0.f;
+    for (int c = 0; c < C; ++c) s += expf(x[c * V + v] - mx);
+    const float inv = 1.0f / s;
+    for (int c = 0; c < C; ++c) w[c * V + v] = expf(x[c * V + v] - mx) * inv;
+  }
+}
+
+hipError_t launch_softmax_fwd(const float* logits, float* w, int C, int64_t V, hipStream_t st) {
+  hipLaunchKernelGGL(softmax_fwd_kernel, dim3(grid_for(V, 256)), dim3(256), 0, st, logits, w, C, V);
+  return hipGetLastError();
+}
+
+__global__ void softmax_bwd_kernel(const float* __restrict__ w, const float* __restrict__ g, float* __restrict__ gl,
+                                   int C, int64_t V) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += (int64_t)gridDim.x * blockDim.x) {
+    float dot = 0.f;
+    for (int c = 0; c < C; ++c) dot += w[c * V + v] * g[c * V + v];
+    for (int c = 0; c < C; ++c) gl[c * V + v] += w[c * V + v] * (g[c * V + v] - dot);
+  }
+}
+
+hipError_t launch_softmax_bwd(const float* w, const float* g, float* gl, int C, int64_t V, hipStream_t st) {
+  hipLaunchKernelGGL(softmax_bwd_kernel, dim3(grid_for(V, 256)), dim3(256), 0, st, w, g, gl, C, V);
+  return hipGetLastError();
+}
+
+template <typename LowT>
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                            float bc2, LowT* __restrict__ low) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    if (low) low[i] = (LowT)pi;
+  }
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                       int step, void* lowp, mnr_dtype dt, hipStream_t st) {
+  const float bc1 = 1.f - (float)std::pow((double)b1, (double)step);
+  const float bc2 = 1.f - (float)std::pow((double)b2, (double)step);
+  const dim3 grid(grid_for(n, 256));
+  if (lowp && dt == MNR_BF16)
+    hipLaunchKernelGGL(adam_kernel<__bf16>, grid, dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2,
+                       (__bf16*)lowp);
+  else
+    hipLaunchKernelGGL(adam_kernel<_Float16>, grid, dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2,
+                       (_Float16*)lowp);
+  return hipGetLastError();
+}
+
+template <typename LowT>
+__global__ void convert_kernel(const float* __restrict__ s, LowT* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (LowT)s[i];
+}
+
+hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st) {
+  if (dt == MNR_BF16)
+    hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(grid_for(n, 256)), dim3(256), 0, st, src, (__bf16*)dst, n);
+  else
+    hipLaunchKernelGGL(convert_kernel<_Float16>, dim3(grid_for(n, 256)), dim3(256), 0, st, src, (_Float16*)dst, n);
+  return hipGetLastError();
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ d, int64_t n_words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = 0u;
+}
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 4);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (uint32_t*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace mnr

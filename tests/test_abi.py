@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, host FK matches the oracle, and invalid calls are rejected
+on the host before any launch."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2306_16541_amd as m
+    return m
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b(mnr_\w+)\s*\(", txt))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    m = _lib()
+    names = _declared()
+    assert "mnr_render" in names and "mnr_train_step" in names
+    for n in sorted(names):
+        assert hasattr(m.lib, n), n
+    assert set(m.EXPORTED) <= names
+
+
+def test_host_fk_matches_oracle():
+    m = _lib()
+    parents, rest = scenes.skeleton()
+    for seed in (1, 2, 3):
+        aa = scenes.pose(seed, 0.3)
+        G = m.fk_bones(m.PoseHost(parents, rest, aa))
+        Go = oracle.bone_transforms(parents, rest, aa).numpy()
+        assert np.abs(G - Go).max() < 2e-7
+
+
+def _args(sc):
+    m = _lib()
+    f = m.Field()
+    f.n_levels, f.n_feat, f.log2_T = 16, 2, sc.log2_T
+    f.level_res[:16] = [int(v) for v in sc.level_res]
+    f.box_min[:], f.box_max[:] = [-0.5] * 3, [0.5] * 3
+    f.table_dtype, f.table = 0, 0x1000                # never dereferenced: rejected first
+    f.n_layers = len(sc.mlp)
+    widths = [32] + [w.shape[0] for w in sc.mlp]
+    f.width[: len(widths)] = widths
+    f.mlp_dtype = 0
+    for k in range(len(sc.mlp)):
+        f.w[k] = 0x2000
+    mo = m.Motion(24, sc.res, (C.c_float * 3)(-0.5, -0.5, -0.5), (C.c_float * 3)(0.5, 0.5, 0.5), 0x3000)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    return m, f, mo, pose, cam
+
+
+def _render(m, f, mo, pose, cam, H=8, W=8, spp=8, opts=None, pid=None, n=64, out=0x4000):
+    return m.lib.mnr_render(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), H, W, spp,
+                            None if opts is None else C.byref(opts), pid, n, out, None, None, None)
+
+
+def test_invalid_calls_are_rejected_before_launch():
+    sc = scenes.scene_small(H=8, W=8, spp=8)
+    m, f, mo, pose, cam = _args(sc)
+    assert _render(m, f, mo, pose, cam, spp=0) == -2
+    assert _render(m, f, mo, pose, cam, spp=2000) == -2
+    assert _render(m, f, mo, pose, cam, n=63) == -2                       # full frame needs H*W rays
+    assert _render(m, f, mo, pose, cam, out=None) == -1
+    f.width[1] = 48
+    assert _render(m, f, mo, pose, cam) == -2
+    assert "hidden width" in m.lib.mnr_last_error().decode()
+    f.width[1] = 64
+    f.mlp_dtype = 1                                                        # F16 MLP: unsupported
+    assert _render(m, f, mo, pose, cam) == -3
+    f.mlp_dtype = 0
+    bad = sc.axis_angle.copy(); bad[3, 1] = math.nan
+    assert _render(m, f, mo, m.PoseHost(sc.parents, sc.rest_joints, bad), cam) == -1
+    mo.n_bones = 23
+    assert _render(m, f, mo, pose, cam) == -2
+    mo.n_bones = 24
+    cam.fx = -1.0
+    assert _render(m, f, mo, pose, cam) == -1
+    opts = m.make_opts(ert_tau=-1.0)
+    cam.fx = 16.0
+    assert _render(m, f, mo, pose, cam, opts=opts) == -1
+    assert m.lib.mnr_zero(None, 16, None) == -1
+    assert m.lib.mnr_convert(None, None, 1, 4, None) == -1
+    assert m.lib.mnr_adam_step(None, None, None, None, 4, 1e-3, 0.9, 0.99, 1e-8, 1, None, 0, None) == -1
+
+
+def test_status_strings():
+    m = _lib()
+    for s, txt in [(0, "ok"), (-1, "invalid argument"), (-6, "busy")]:
+        assert m.lib.mnr_status_str(s).decode() == txt
