@@ -146,13 +146,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
+    ap.add_argument("--mixed-only", action="store_true", help="the mixed-precision 512x512 frame only (profiling)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="plain 1 GiB device-to-device copy, for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every ray is independent and the whole frame fits one MI355X; "
               "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_per_launch": src.numel() * 4, "launches": args.steps}))
+        return
     sc = scenes.scene_body()                              # 512x512, 128 spp
+    if args.mixed_only:
+        res = render_bench(sc, m.F16, m.BF16, args.steps, args.warmup)
+        print(json.dumps({"mixed_512_kernel_ms": res["kernel_ms"], "evaluated_samples": res["n_eval"]}))
+        return
     fp32 = render_bench(sc, m.F32, m.F32, args.steps, args.warmup)
     widths = [32] + [w.shape[0] for w in sc.mlp]
     roof, roof2 = roofline(fp32, sc, "f32", "f32", widths)

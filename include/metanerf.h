@@ -111,9 +111,10 @@ typedef struct {
   float box_min[3], box_max[3];
 } mnr_camera;
 
-/* Render options.  ert_tau: a ray stops after the 64-sample chunk in which
- * its transmittance drops below ert_tau (0 disables early termination; the
- * colour then differs from the full sum by at most ert_tau * (1 + |bg|)).
+/* Render options.  ert_tau: early ray termination.  A ray stops once its
+ * transmittance is below ert_tau: checked after every sample for full
+ * frames, after every 64-sample chunk for ray lists (0 disables it).  The
+ * colour then differs from the full sum by at most ert_tau * (1 + |bg|).
  * stratified = 0 samples stratum midpoints; 1 draws the jitter xi of sample
  * i of ray b from SplitMix64: output n = b*spp + i of the stream seeded with
  * `seed`, xi = (out >> 40) * 2^-24. */
@@ -139,10 +140,11 @@ mnr_status mnr_fk_bones(const mnr_pose* pose, float* G_out);
  * row-major order (then n_rays must equal H*W).  Ids outside [0, H*W)
  * render as misses.  out_rgba: dev float [n_rays][4] = (r, g, b, opacity);
  * rays that miss the box get (bg, 0).
- * t_chunks (optional, dev float [n_rays][ceil(spp/64)]): transmittance at
- * the start of each 64-sample chunk the ray processed, -1 for chunks it
- * skipped after early termination (and for missed rays); the adjoint
- * needs it.  n_evaluated (optional, dev uint64, accumulated with atomics)
+ * t_chunks (optional, dev float [n_rays][ceil(spp/64) + 1]): the state the
+ * adjoint needs -- transmittance at the start of each 64-sample chunk the
+ * ray reached (-1 for chunks it never reached), then the number of samples
+ * it processed.  Missed rays leave their rows untouched; the adjoint skips
+ * them.  n_evaluated (optional, dev uint64, accumulated with atomics)
  * counts the samples actually evaluated. */
 mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
                       const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
@@ -208,7 +210,7 @@ typedef struct {
   float* logits; float* logits_grad; float* logits_m; float* logits_v;    /* [(n_bones+1)*res^3] */
   float* weights_grad;                                                    /* dL/dW^c scratch */
   float* rgba; float* grad_rgba;                                          /* [n_rays][4] scratch */
-  float* t_chunks;                                          /* [n_rays][ceil(spp/64)] scratch */
+  float* t_chunks;                                    /* [n_rays][ceil(spp/64) + 1] scratch */
   float* loss;                                                            /* [1] */
   float lr_field, lr_motion, beta1, beta2, eps;
   int32_t step;                                                           /* 1-based */

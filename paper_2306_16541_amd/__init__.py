@@ -229,6 +229,12 @@ def n_chunks(spp: int) -> int:
     return (spp + 63) // 64
 
 
+def saved_size(spp: int) -> int:
+    """Floats per ray of the forward's saved state (t_chunks): transmittance
+    at each 64-sample chunk start plus the processed-sample count."""
+    return n_chunks(spp) + 1
+
+
 def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts] = None,
            pixel_ids: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
            counter: Optional[torch.Tensor] = None, t_chunks: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -275,7 +281,7 @@ class RenderFn(torch.autograd.Function):
         *mlp, cfg = mlp_and_cfg
         field, pose, cam, H, W, spp, opts, pixel_ids = cfg
         n = H * W if pixel_ids is None else int(pixel_ids.numel())
-        tch = torch.empty((n, n_chunks(spp)), dtype=torch.float32, device=table.device)
+        tch = torch.empty((n, saved_size(spp)), dtype=torch.float32, device=table.device)
         out = render(field, pose, cam, H, W, spp, opts, pixel_ids, t_chunks=tch)
         ctx.cfg = cfg
         ctx.save_for_backward(tch)
@@ -319,7 +325,7 @@ class Trainer:
             "logits_grad": z(self.logits), "logits_m": z(self.logits), "logits_v": z(self.logits),
             "weights_grad": z(self.logits),
             "rgba": torch.zeros(max_rays, 4, device=dev), "grad_rgba": torch.zeros(max_rays, 4, device=dev),
-            "t_chunks": torch.zeros(max_rays * n_chunks(spp), device=dev), "loss": torch.zeros(1, device=dev),
+            "t_chunks": torch.zeros(max_rays * saved_size(spp), device=dev), "loss": torch.zeros(1, device=dev),
         }
         self.max_rays, self.max_spp = max_rays, spp
         s = TrainState()
@@ -379,3 +385,73 @@ class Trainer:
         for w32, w in zip(self.mlp32, self.mlp):
             if w is not w32:
                 check(lib.mnr_convert(_ptr(w32), _ptr(w), self.field.c.mlp_dtype, w32.numel(), _stream()), "convert")
+
+
+# ---------------------------------------------------------------------------
+# Render server (include/metanerf_server.h).
+# ---------------------------------------------------------------------------
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("ticks", C.c_uint64), ("tiles", C.c_uint64), ("queued", C.c_int32), ("admitted", C.c_int32),
+                ("resident_bytes", C.c_uint64), ("inflight_bytes", C.c_uint64)]
+
+
+_sig("mnr_server_create", C.c_int, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)])
+_sig("mnr_server_add_user", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Field), C.POINTER(Motion)])
+_sig("mnr_server_submit", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Pose), C.POINTER(Camera), C.c_int32, C.c_int32,
+                                    C.c_int32, C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_uint64)])
+_sig("mnr_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_void_p])
+_sig("mnr_server_wait", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p])
+_sig("mnr_server_get_stats", C.c_int, [C.c_void_p, C.POINTER(ServerStats)])
+_sig("mnr_server_destroy", C.c_int, [C.c_void_p])
+EXPORTED += ["mnr_server_create", "mnr_server_add_user", "mnr_server_submit", "mnr_server_poll", "mnr_server_wait",
+             "mnr_server_get_stats", "mnr_server_destroy"]
+
+
+class Server:
+    """Continuous-batching render server with per-user resident fields."""
+
+    def __init__(self, mem_budget: int, max_slots: int = 32, tiles_per_tick: int = 1024):
+        h = C.c_void_p()
+        check(lib.mnr_server_create(int(mem_budget), int(max_slots), int(tiles_per_tick), C.byref(h)), "server_create")
+        self.h = h
+        self._keep = {}
+
+    def add_user(self, user: int, field: DeviceField) -> None:
+        check(lib.mnr_server_add_user(self.h, int(user), C.byref(field.c), C.byref(field.m)), "server_add_user")
+        self._keep[("user", user)] = field
+
+    def submit(self, user: int, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, out: torch.Tensor,
+               opts: Optional[Opts] = None) -> int:
+        t = C.c_uint64()
+        check(lib.mnr_server_submit(self.h, int(user), C.byref(pose.c), C.byref(cam), H, W, spp,
+                                    None if opts is None else C.byref(opts), _ptr(out), C.byref(t)), "server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        done = C.c_int32()
+        ts = (C.c_int64 * 4)()
+        check(lib.mnr_server_poll(self.h, C.c_uint64(ticket), C.byref(done), ts), "server_poll")
+        return bool(done.value), list(ts)
+
+    def wait(self, ticket: int, timeout_ms: int = 60000):
+        ts = (C.c_int64 * 4)()
+        check(lib.mnr_server_wait(self.h, C.c_uint64(ticket), int(timeout_ms), ts), "server_wait")
+        return list(ts)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(lib.mnr_server_get_stats(self.h, C.byref(s)), "server_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if self.h:
+            check(lib.mnr_server_destroy(self.h), "server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

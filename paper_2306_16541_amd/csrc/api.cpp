@@ -36,7 +36,7 @@ static mnr_status check_box(const float* lo, const float* hi, const char* who) {
   return MNR_OK;
 }
 
-static mnr_status validate_field(const mnr_field* f) {
+mnr_status validate_field(const mnr_field* f) {
   if (!f || !f->table) return fail(MNR_E_INVALID, "field: null pointer");
   if (f->n_feat != 2) return fail(MNR_E_SHAPE, "field: n_feat must be 2, got %d", f->n_feat);
   if (f->n_levels < 1 || f->n_levels > MNR_MAX_LEVELS || f->n_levels * f->n_feat != 32)
@@ -58,7 +58,7 @@ static mnr_status validate_field(const mnr_field* f) {
   return check_box(f->box_min, f->box_max, "field");
 }
 
-static mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
+mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
                                   int H, int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays,
                                   const void* out) {
   if (mnr_status s = validate_field(f)) return s;
@@ -84,7 +84,7 @@ static mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const
   return MNR_OK;
 }
 
-static void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
+void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
                       int H, int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays) {
   std::memset(&a, 0, sizeof(a));
   a.f.table = f->table;
@@ -132,7 +132,7 @@ static void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, co
   }
 }
 
-static int slot_count(int H, int W, const int32_t* pixel_ids, int n_rays) {
+int slot_count(int H, int W, const int32_t* pixel_ids, int n_rays) {
   if (pixel_ids) return n_rays;
   return ((W + 15) / 16) * ((H + 15) / 16) * 256;
 }

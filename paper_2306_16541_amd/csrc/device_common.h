@@ -76,6 +76,17 @@ struct RenderArgs {
   float* grad_weights;
 };
 
+// Server tick work table (device memory, uploaded per tick).
+struct WorkItem {
+  int32_t slot, tile;
+};
+struct WorkTable {
+  int32_t counter;  // next item; 0 at upload
+  int32_t n_items;
+  int32_t pad[2];
+  WorkItem items[1];  // n_items entries (allocated for the tick capacity)
+};
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // SplitMix64 output n of the stream seeded with `seed`.

@@ -1,8 +1,8 @@
 // Per-sample stages of the posed-body renderer, as device functions shared by
 // the forward and adjoint kernels:
 //   warp_sample   inverse linear blend skinning (Sec. 4.2, Eq. 7-9)
-//   encode_level  one level of the multiresolution grid encoding of the
-//                 canonical field's input (Sec. 4.4, Eq. 13)
+//   encode_all    the multiresolution grid encoding of the canonical
+//                 field's input (Sec. 4.4, Eq. 13)
 //   stage_weights / mlp_tile  the bias-free MLP of Eq. 13 on MFMA
 #pragma once
 #include "device_common.h"
@@ -27,20 +27,37 @@ __device__ __forceinline__ Tri tri_cell(float qx, float qy, float qz) {
   return t;
 }
 
-// Trilinear sample of one channel plane [R^3] with zero padding.
-__device__ __forceinline__ float tri_sample(const float* __restrict__ plane, int R, const Tri& t) {
-  float v[8];
+// Raw buffer resources (gfx9 family: dword3 = 0x00020000, stride 0).  A
+// read whose byte offset is >= num_records returns 0; OOB_OFFSET is used
+// for trilinear corners that lie outside the volume, which gives the
+// zero padding without a branch.
+constexpr uint32_t OOB_OFFSET = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Byte offsets of the 8 corners of a trilinear cell in an R^3 plane; corners
+// outside [0, R-1]^3 get OOB_OFFSET.
+__device__ __forceinline__ void tri_offsets(const Tri& t, int R, uint32_t off[8]) {
+  const bool okx0 = (unsigned)t.i0[0] < (unsigned)R, okx1 = (unsigned)(t.i0[0] + 1) < (unsigned)R;
+  const bool oky0 = (unsigned)t.i0[1] < (unsigned)R, oky1 = (unsigned)(t.i0[1] + 1) < (unsigned)R;
+  const bool okz0 = (unsigned)t.i0[2] < (unsigned)R, okz1 = (unsigned)(t.i0[2] + 1) < (unsigned)R;
+  const uint32_t base = (((uint32_t)t.i0[2] * R + (uint32_t)t.i0[1]) * R + (uint32_t)t.i0[0]) * 4u;
+  const uint32_t sy = (uint32_t)R * 4u, sz = (uint32_t)(R * R) * 4u;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    const int ix = t.i0[0] + (c & 1), iy = t.i0[1] + ((c >> 1) & 1), iz = t.i0[2] + (c >> 2);
-    const bool ok = (unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R;
-    v[c] = ok ? plane[((size_t)iz * R + iy) * R + ix] : 0.0f;
+    const bool ok = ((c & 1) ? okx1 : okx0) && ((c & 2) ? oky1 : oky0) && ((c & 4) ? okz1 : okz0);
+    const uint32_t o = base + ((c & 1) ? 4u : 0u) + ((c & 2) ? sy : 0u) + ((c & 4) ? sz : 0u);
+    off[c] = ok ? o : OOB_OFFSET;
   }
-  const float fx = t.f[0], fy = t.f[1], fz = t.f[2];
-  const float x00 = v[0] + fx * (v[1] - v[0]), x10 = v[2] + fx * (v[3] - v[2]);
-  const float x01 = v[4] + fx * (v[5] - v[4]), x11 = v[6] + fx * (v[7] - v[6]);
-  const float y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
-  return y0 + fz * (y1 - y0);
+}
+
+__device__ __forceinline__ float trilerp(const float v[8], const float f[3]) {
+  const float x00 = v[0] + f[0] * (v[1] - v[0]), x10 = v[2] + f[0] * (v[3] - v[2]);
+  const float x01 = v[4] + f[0] * (v[5] - v[4]), x11 = v[6] + f[0] * (v[7] - v[6]);
+  const float y0 = x00 + f[1] * (x10 - x00), y1 = x01 + f[1] * (x11 - x01);
+  return y0 + f[2] * (y1 - y0);
 }
 
 __device__ __forceinline__ void bone_apply(const float* __restrict__ g, const float x[3], float y[3]) {
@@ -49,22 +66,50 @@ __device__ __forceinline__ void bone_apply(const float* __restrict__ g, const fl
   y[2] = fmaf(g[8], x[0], fmaf(g[9], x[1], fmaf(g[10], x[2], g[11])));
 }
 
+// Cell of a canonical point in the weight volume.  Grid coordinates are
+// clamped to [-2, R+1] first (every corner of such a cell is outside the
+// volume anyway), so the float-to-int conversion is always in range.
+__device__ __forceinline__ Tri bone_cell(const MotionArgs& m, const float y[3]) {
+  const float hi = (float)(m.res + 1);
+  return tri_cell(fminf(fmaxf((y[0] - m.mmin[0]) * m.mscale[0], -2.f), hi),
+                  fminf(fmaxf((y[1] - m.mmin[1]) * m.mscale[1], -2.f), hi),
+                  fminf(fmaxf((y[2] - m.mmin[2]) * m.mscale[2], -2.f), hi));
+}
+
+// Bones are processed BG at a time so that BG x 8 gathers are in flight
+// before the first one is consumed.
+constexpr int BG = 4;
+
 __device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G)[12], const float x[3],
                                             float xs[3], float& L) {
   const int R = m.res;
-  const size_t plane = (size_t)R * R * R;
+  const uint32_t plane = (uint32_t)(R * R * R);
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, sum = 0.f;
 #pragma unroll 1
-  for (int b = 0; b < m.n_bones; ++b) {
-    float y[3];
-    bone_apply(G[b], x, y);
-    const Tri t = tri_cell((y[0] - m.mmin[0]) * m.mscale[0], (y[1] - m.mmin[1]) * m.mscale[1],
-                           (y[2] - m.mmin[2]) * m.mscale[2]);
-    const float w = tri_sample(m.weights + b * plane, R, t);
-    sum += w;
-    acc0 = fmaf(w, y[0], acc0);
-    acc1 = fmaf(w, y[1], acc1);
-    acc2 = fmaf(w, y[2], acc2);
+  for (int b0 = 0; b0 < m.n_bones; b0 += BG) {
+    float v[BG][8], y[BG][3];
+    Tri t[BG];
+#pragma unroll
+    for (int u = 0; u < BG; ++u) {
+      const int b = b0 + u < m.n_bones ? b0 + u : m.n_bones - 1;
+      bone_apply(G[b], x, y[u]);
+      t[u] = bone_cell(m, y[u]);
+      uint32_t off[8];
+      tri_offsets(t[u], R, off);
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.weights + (size_t)b * plane, plane * 4u);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[u][c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off[c], 0, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < BG; ++u) {
+      if (b0 + u < m.n_bones) {
+        const float w = trilerp(v[u], t[u].f);
+        sum += w;
+        acc0 = fmaf(w, y[u][0], acc0);
+        acc1 = fmaf(w, y[u][1], acc1);
+        acc2 = fmaf(w, y[u][2], acc2);
+      }
+    }
   }
   L = sum;
   const float inv = 1.0f / fmaxf(sum, EPS_L);
@@ -75,16 +120,23 @@ __device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G
 // Grid encoding of one level.
 // ---------------------------------------------------------------------------
 
+// One table row (n_feat = 2 features) through a per-level buffer resource.
 template <typename TableT>
-__device__ __forceinline__ f2 load_feat2(const TableT* __restrict__ p);
+__device__ __forceinline__ f2 load_row(__amdgpu_buffer_rsrc_t rs, uint32_t row);
 template <>
-__device__ __forceinline__ f2 load_feat2<float>(const float* __restrict__ p) {
-  return *(const f2*)p;
+__device__ __forceinline__ f2 load_row<float>(__amdgpu_buffer_rsrc_t rs, uint32_t row) {
+  return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, row * 8u, 0, 0));
 }
 template <>
-__device__ __forceinline__ f2 load_feat2<_Float16>(const _Float16* __restrict__ p) {
-  const h2 v = *(const h2*)p;
+__device__ __forceinline__ f2 load_row<_Float16>(__amdgpu_buffer_rsrc_t rs, uint32_t row) {
+  const h2 v = __builtin_bit_cast(h2, __builtin_amdgcn_raw_buffer_load_b32(rs, row * 4u, 0, 0));
   return f2{(float)v[0], (float)v[1]};
+}
+
+template <typename TableT>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t level_rsrc(const FieldArgs& f, int l) {
+  const uint32_t T = 1u << f.log2_T;
+  return make_rsrc((const TableT*)f.table + (size_t)l * T * 2, T * 2u * (uint32_t)sizeof(TableT));
 }
 
 // Cell of point u (in [0,1]^3) at resolution N: i0 = min(floor(uN), N-1).
@@ -116,18 +168,37 @@ __device__ __forceinline__ uint32_t grid_row(const GridCell& c, int N, bool dens
   return (x * 1u ^ y * 2654435761u ^ z * 805459861u) & mask;
 }
 
-template <typename TableT>
-__device__ __forceinline__ f2 encode_level(const TableT* __restrict__ level_table, const float u[3], int N,
-                                           bool dense, uint32_t mask) {
-  const GridCell c = grid_cell(u, N);
-  f2 v[8];
+__device__ __forceinline__ f2 trilerp2(const f2 v[8], const float f[3]) {
+  const f2 x00 = v[0] + f[0] * (v[1] - v[0]), x10 = v[2] + f[0] * (v[3] - v[2]);
+  const f2 x01 = v[4] + f[0] * (v[5] - v[4]), x11 = v[6] + f[0] * (v[7] - v[6]);
+  const f2 y0 = x00 + f[1] * (x10 - x00), y1 = x01 + f[1] * (x11 - x01);
+  return y0 + f[2] * (y1 - y0);
+}
+
+// Levels are encoded LG at a time so that LG x 8 row gathers are in flight
+// before the first one is consumed.  Calls store(l, feature pair).
+constexpr int LG = 2;
+
+template <typename TableT, typename Store>
+__device__ __forceinline__ void encode_all(const FieldArgs& f, const float u[3], bool live, Store store) {
+  const uint32_t mask = (1u << f.log2_T) - 1u;
+#pragma unroll 1
+  for (int l0 = 0; l0 < f.n_levels; l0 += LG) {
+    f2 v[LG][8];
+    GridCell c[LG];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = load_feat2(level_table + 2 * (size_t)grid_row(c, N, dense, mask, k));
-  const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
-  const f2 x00 = v[0] + fx * (v[1] - v[0]), x10 = v[2] + fx * (v[3] - v[2]);
-  const f2 x01 = v[4] + fx * (v[5] - v[4]), x11 = v[6] + fx * (v[7] - v[6]);
-  const f2 y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
-  return y0 + fz * (y1 - y0);
+    for (int q = 0; q < LG; ++q) {
+      const int l = l0 + q;
+      const int N = f.level_res[l];
+      const bool dense = (f.dense_mask >> l) & 1u;
+      c[q] = grid_cell(u, N);
+      const __amdgpu_buffer_rsrc_t rs = level_rsrc<TableT>(f, l);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[q][k] = load_row<TableT>(rs, grid_row(c[q], N, dense, mask, k));
+    }
+#pragma unroll
+    for (int q = 0; q < LG; ++q) store(l0 + q, live ? trilerp2(v[q], c[q].f) : f2{0.f, 0.f});
+  }
 }
 
 __device__ __forceinline__ void unit_coords(const FieldArgs& f, const float xs[3], float u[3]) {
@@ -299,12 +370,12 @@ __device__ __forceinline__ f4 mlp_tile(const char* wl, const char* feat, int nt,
 }
 
 // ---------------------------------------------------------------------------
-// One 64-sample chunk of a ray: sample position, inverse LBS, encoding (into
-// the wave's LDS feature buffer) and the MLP.  Lane i handles sample
-// 64*ch + i.  Returns the ballot of live lanes (valid sample with L > 0);
-// when it is zero nothing else was computed.  On return, lane i holds its
-// sample's raw MLP outputs in `out` (the per-wave scratch `obuf`, 64 x f4,
-// is used for the lane transpose).
+// Field evaluation of one sample per lane: inverse LBS, encoding (into the
+// wave's LDS feature buffer) and the MLP.  Lanes with valid == false (or
+// L == 0) are not live.  Returns the ballot of live lanes; when it is zero
+// nothing else was computed.  On return lane i holds its sample's raw MLP
+// outputs in `out` (the per-wave scratch `obuf`, 64 x f4, carries the lane
+// transpose).  MLP tiles (16 lanes) without a live lane are skipped.
 // ---------------------------------------------------------------------------
 
 struct SampleState {
@@ -312,19 +383,17 @@ struct SampleState {
   bool live;
 };
 
+// Stratified offset of sample i of ray b: SplitMix64 output b*spp + i of the
+// stream seeded with `seed`, top 24 bits as a fraction; 0.5 (stratum
+// midpoint) when jitter is off.
+__device__ __forceinline__ float sample_jitter(const RayArgs& r, int ray_index, int i) {
+  if (!r.stratified) return 0.5f;
+  return (float)(splitmix64(r.seed, (uint64_t)ray_index * r.spp + i) >> 40) * 0x1p-24f;
+}
+
 template <typename TableT, int P, int NHH>
-__device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySetup& rs, int ray_index, int ch,
-                                               int lane, const char* wl, char* feat, f4* obuf, SampleState& st,
-                                               f4& out) {
-  const int S_ = a.r.spp;
-  const int i = ch * 64 + lane;
-  const bool valid = i < S_;
-  float xi = 0.5f;
-  if (a.r.stratified) xi = (float)(splitmix64(a.r.seed, (uint64_t)ray_index * S_ + i) >> 40) * 0x1p-24f;
-  const float s = ((float)i + xi) * rs.delta;
-  st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
-  st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
-  st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+__device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, int lane, const char* wl, char* feat,
+                                               f4* obuf, SampleState& st, f4& out) {
   st.L = 0.f;
   st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
   if (valid) warp_sample(a.m, a.G, st.x, st.xs, st.L);
@@ -332,30 +401,100 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
   const uint64_t live_mask = __ballot(st.live);
   if (live_mask == 0) return 0;
 
-  const TableT* table = (const TableT*)a.f.table;
-  const size_t T = (size_t)1 << a.f.log2_T;
-  const uint32_t mask = (uint32_t)T - 1u;
   float u[3];
   unit_coords(a.f, st.xs, u);
-#pragma unroll 1
-  for (int l = 0; l < a.f.n_levels; ++l) {
-    f2 v = {0.f, 0.f};
-    if (st.live)
-      v = encode_level<TableT>(table + (size_t)l * T * 2, u, a.f.level_res[l], (a.f.dense_mask >> l) & 1u, mask);
-    store_feat2<P>(feat, lane, 2 * l, v);
-  }
+  encode_all<TableT>(a.f, u, st.live, [&](int l, f2 v) { store_feat2<P>(feat, lane, 2 * l, v); });
   wave_sync_lds();
-  f4 o[4];
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) o[nt] = mlp_tile<P, NHH>(wl, feat, nt, lane);
-  if (lane < 16) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) obuf[nt * 16 + lane] = o[nt];
+  // Tile nt's outputs go to obuf[16 nt ..]; when obuf aliases the feature
+  // buffer those bytes belong to tile 0, whose features are already consumed.
+#pragma unroll 1
+  for (int nt = 0; nt < 4; ++nt) {
+    f4 o = {0.f, 0.f, 0.f, 0.f};
+    if ((live_mask >> (16 * nt)) & 0xFFFFull) o = mlp_tile<P, NHH>(wl, feat, nt, lane);
+    wave_sync_lds();
+    if (lane < 16) obuf[nt * 16 + lane] = o;
   }
   wave_sync_lds();
   out = obuf[lane];
   wave_sync_lds();
   return live_mask;
+}
+
+// One 64-sample chunk of a ray (lane i: sample 64 ch + i).
+template <typename TableT, int P, int NHH>
+__device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySetup& rs, int ray_index, int ch,
+                                               int lane, const char* wl, char* feat, f4* obuf, SampleState& st,
+                                               f4& out) {
+  const int i = ch * 64 + lane;
+  const bool valid = i < a.r.spp;
+  const float s = ((float)i + sample_jitter(a.r, ray_index, i)) * rs.delta;
+  st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+  st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+  st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+  return field_eval<TableT, P, NHH>(a, valid, lane, wl, feat, obuf, st, out);
+}
+
+// ---------------------------------------------------------------------------
+// One 8x8 ray packet (packet `wave` of 16x16 tile `tile` of the frame): each
+// lane owns one pixel's ray and the 64 rays march in lockstep, one sample
+// per iteration.  Compositing is the per-lane recurrence
+//   alpha = 1 - exp(-sigma delta), alpha' = alpha min(L, 1),
+//   C += T alpha' c, T *= 1 - alpha'
+// and a ray stops once T < ert_tau.  Writes RGBA, optionally the adjoint's
+// saved state, and counts evaluated samples.
+// ---------------------------------------------------------------------------
+template <typename TableT, int P, int NHH>
+__device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile, int wave, int lane, const char* wl,
+                                                   char* feat) {
+  const int S_ = a.r.spp;
+  const int nchunks = (S_ + 63) >> 6;
+  const int u = (tile % a.r.tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+  const int v = (tile / a.r.tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+  const bool in_image = u < a.r.W && v < a.r.H;
+  const int pix = in_image ? v * a.r.W + u : 0;
+  RaySetup rs;
+  bool act = in_image && setup_ray(a.r, pix, rs);
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;
+  int n_done = 0;
+  unsigned live_count = 0;
+  for (int i = 0;; ++i) {
+    if (__ballot(act) == 0) break;
+    if (a.t_chunks && act && (i & 63) == 0) a.t_chunks[(size_t)pix * (nchunks + 1) + (i >> 6)] = Tr;
+    SampleState st;
+    if (act) {
+      const float s = ((float)i + sample_jitter(a.r, pix, i)) * rs.delta;
+      st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+      st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+      st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+    }
+    f4 out;
+    const uint64_t live_mask = field_eval<TableT, P, NHH>(a, act, lane, wl, feat, (f4*)feat, st, out);
+    if (live_mask) {
+      live_count += __popcll(live_mask);
+      if (st.live) {
+        const float sigma = fmaxf(out[3], 0.f);
+        const float ap = -expm1f(-sigma * rs.delta) * fminf(st.L, 1.f);
+        const float w = Tr * ap;
+        C0 = fmaf(w, 1.f / (1.f + expf(-out[0])), C0);
+        C1 = fmaf(w, 1.f / (1.f + expf(-out[1])), C1);
+        C2 = fmaf(w, 1.f / (1.f + expf(-out[2])), C2);
+        Tr *= 1.f - ap;
+      }
+    }
+    if (act) {
+      n_done = i + 1;
+      if (Tr < a.r.ert_tau || i + 1 >= S_) act = false;
+    }
+  }
+  if (in_image) {
+    *(f4*)(a.out + (size_t)pix * 4) = f4{C0 + Tr * a.r.bg[0], C1 + Tr * a.r.bg[1], C2 + Tr * a.r.bg[2], 1.f - Tr};
+    if (a.t_chunks) {
+      float* tc = a.t_chunks + (size_t)pix * (nchunks + 1);
+      for (int ch = (n_done + 63) >> 6; ch < nchunks; ++ch) tc[ch] = -1.f;
+      tc[nchunks] = (float)n_done;
+    }
+  }
+  if (a.n_eval && lane == 0 && live_count) atomicAdd(a.n_eval, (unsigned long long)live_count);
 }
 
 }  // namespace mnr

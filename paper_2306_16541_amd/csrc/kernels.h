@@ -15,6 +15,10 @@ hipError_t launch_render_fwd(const RenderArgs& a, int n_slots, mnr_dtype table_d
 hipError_t launch_render_bwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
                              hipStream_t st);
 
+// Server tick: render the (slot, tile) items of wt with the requests' descriptors.
+hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
+                        hipStream_t st);
+
 hipError_t launch_mse(const float* rgba, const float* target, int n, float* grad, float* loss, hipStream_t st);
 hipError_t launch_softmax_fwd(const float* logits, float* w, int C, int64_t V, hipStream_t st);
 hipError_t launch_softmax_bwd(const float* w, const float* g, float* gl, int C, int64_t V, hipStream_t st);

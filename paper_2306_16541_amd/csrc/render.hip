@@ -1,14 +1,23 @@
-// Fused forward renderer (Sec. 4, Fig. 2): one wavefront owns one ray at a
-// time and walks it in chunks of 64 samples, one sample per lane:
+// Fused forward renderers (Sec. 4, Fig. 2).
+//
+// render_fwd_kernel (ray lists, e.g. training batches): one wavefront owns
+// one ray at a time and walks it in chunks of 64 samples, one per lane:
 //   sample inside the body box (Sec. 4.4) -> inverse LBS (Eq. 7-9)
 //   -> grid encoding -> MLP on MFMA (Eq. 13) -> front-to-back compositing
 //   with the likelihood augmentation (Eq. 3, Sec. 4.4) as a wave
 //   prefix-product; transmittance is carried across chunks and the ray stops
 //   after the chunk where it falls below ert_tau.
-// Persistent grid: blocks stage the MLP weights into LDS once and loop over
-// rays.  Rays are grouped in 16x16-pixel tiles dealt round-robin to the
-// eight XCDs (block b runs on XCD b % 8), so each XCD's L2 sees spatially
-// coherent gathers.
+// render_packet_kernel (full frames): one wavefront owns an 8x8 block of
+// neighbouring pixels, one ray per lane, and marches the 64 rays in
+// lockstep, one sample per iteration.  The 64 samples of an iteration lie
+// within a few voxels of each other, so the skinning-volume and grid
+// gathers of a wave share cache lines; compositing is a per-lane
+// recurrence and each ray stops as soon as its transmittance is below
+// ert_tau.  A block's four waves cover one 16x16 tile.
+// Both use a persistent grid: blocks stage the MLP weights into LDS once
+// and loop over work; 16x16-pixel tiles (or 256-ray groups) are dealt
+// round-robin to the eight XCDs (block b runs on XCD b % 8), so each XCD's
+// L2 sees spatially coherent gathers.
 #include "field_device.h"
 #include "kernels.h"
 
@@ -59,7 +68,7 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, i
     int done = 0;  // chunks processed
     if (hit) {
       for (int ch = 0; ch < nchunks; ++ch) {
-        if (a.t_chunks && lane == 0) a.t_chunks[(size_t)orow * nchunks + ch] = Tr;
+        if (a.t_chunks && lane == 0) a.t_chunks[(size_t)orow * (nchunks + 1) + ch] = Tr;
         done = ch + 1;
         SampleState st;
         f4 out;
@@ -88,8 +97,10 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, i
         if (Tr < a.r.ert_tau) break;
       }
     }
-    if (a.t_chunks)
-      for (int ch = done + lane; ch < nchunks; ch += 64) a.t_chunks[(size_t)orow * nchunks + ch] = -1.f;
+    if (a.t_chunks) {
+      for (int ch = done + lane; ch < nchunks; ch += 64) a.t_chunks[(size_t)orow * (nchunks + 1) + ch] = -1.f;
+      if (lane == 0) a.t_chunks[(size_t)orow * (nchunks + 1) + nchunks] = (float)min(done * 64, S_);
+    }
     if (lane == 0) {
       f4 res = {C0 + Tr * a.r.bg[0], C1 + Tr * a.r.bg[1], C2 + Tr * a.r.bg[2], 1.f - Tr};
       *(f4*)(a.out + (size_t)orow * 4) = res;
@@ -98,22 +109,57 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, i
   }
 }
 
+
 template <typename TableT, int P, int NHH>
-static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+__global__ void __launch_bounds__(BLOCK) render_packet_kernel(const RenderArgs a, int n_tiles) {
   using S = MlpShape<P>;
-  const int lds = S::bytes_total(NHH) + WAVES_PER_BLOCK * S::feat_bytes_per_wave();
-  auto kern = render_fwd_kernel<TableT, P, NHH>;
-  static int max_blocks = 0;  // per instantiation
-  if (max_blocks == 0) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  char* wl = lds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* feat = lds + S::bytes_total(NHH) + wave * S::feat_bytes_per_wave();
+
+  stage_weights<P, NHH>(wl, a.f);
+  __syncthreads();
+  const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
+  const int nb = ((int)gridDim.x - xcd + 7) >> 3;  // blocks on this XCD
+  for (int k = lb;; k += nb) {
+    const int tile = k * 8 + xcd;
+    if (tile >= n_tiles) break;
+    render_tile_packet<TableT, P, NHH>(a, tile, wave, lane, wl, feat);
+  }
+}
+
+template <typename KernelT>
+static int persistent_blocks(KernelT kern, int lds, int* cache) {
+  if (*cache == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds);
-    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
+    *cache = cus * (per_cu > 0 ? per_cu : 1);
   }
+  return *cache;
+}
+
+template <typename TableT, int P, int NHH>
+static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+  using S = MlpShape<P>;
+  const int lds = S::bytes_total(NHH) + WAVES_PER_BLOCK * S::feat_bytes_per_wave();
+  if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, one 16x16 tile per block
+    auto kern = render_packet_kernel<TableT, P, NHH>;
+    static int max_blocks = 0;
+    const int n_tiles = n_slots / 256;
+    const int mb = persistent_blocks(kern, lds, &max_blocks);
+    const int grid = n_tiles < mb ? n_tiles : mb;
+    hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(BLOCK), lds, st, a, n_tiles);
+    return hipGetLastError();
+  }
+  auto kern = render_fwd_kernel<TableT, P, NHH>;
+  static int max_blocks = 0;
+  const int mb = persistent_blocks(kern, lds, &max_blocks);
   const int need = (n_slots + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  int grid = need < max_blocks ? need : max_blocks;
+  int grid = need < mb ? need : mb;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, st, a, n_slots);
   return hipGetLastError();

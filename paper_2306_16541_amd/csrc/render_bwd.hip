@@ -197,7 +197,6 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) dw[i] = 0.f;
   __syncthreads();
 
-  const TableT* table = (const TableT*)a.f.table;
   const size_t T = (size_t)1 << a.f.log2_T;
   const uint32_t tmask = (uint32_t)T - 1u;
   const int S_ = a.r.spp;
@@ -218,13 +217,20 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
     if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) continue;
     const f4 gout = *(const f4*)(a.grad_rgba + (size_t)orow * 4);
     float Sc[4] = {a.r.bg[0], a.r.bg[1], a.r.bg[2], 0.f};  // S after the last processed sample
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    const int n_done = (int)tc[nchunks];  // samples the forward pass processed
     for (int ch = nchunks - 1; ch >= 0; --ch) {
-      const float T0 = a.t_chunks[(size_t)orow * nchunks + ch];
-      if (T0 < 0.f) continue;  // not reached by the forward pass
+      const float T0 = tc[ch];
+      if (T0 < 0.f || ch * 64 >= n_done) continue;  // not reached by the forward pass
       SampleState st;
       f4 out;
+      const int i = ch * 64 + lane;
+      const float s = ((float)i + sample_jitter(a.r, orow, i)) * rs.delta;
+      st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+      st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+      st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
       const uint64_t live_mask =
-          chunk_eval<TableT, P, NHH>(a, rs, orow, ch, lane, wl, feat, (f4*)dfeat, st, out);
+          field_eval<TableT, P, NHH>(a, i < n_done, lane, wl, feat, (f4*)dfeat, st, out);
       if (live_mask == 0) continue;  // alpha' = 0 everywhere: S passes through unchanged
 
       // ---- 1. compositing adjoint -------------------------------------------------
@@ -299,7 +305,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           const bool dense = (a.f.dense_mask >> l) & 1u;
           const GridCell gc = grid_cell(u, N);
           const float d0 = df[2 * l], d1 = df[2 * l + 1];
-          const TableT* lt = table + (size_t)l * T * 2;
+          const __amdgpu_buffer_rsrc_t lrs = level_rsrc<TableT>(a.f, l);
           float* gt = a.grad_table + (size_t)l * T * 2;
           float gp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -311,7 +317,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
             const float wk = wx * wy * wz;
             unsafeAtomicAdd(gt + 2 * (size_t)row, wk * d0);
             unsafeAtomicAdd(gt + 2 * (size_t)row + 1, wk * d1);
-            const f2 v = load_feat2(lt + 2 * (size_t)row);
+            const f2 v = load_row<TableT>(lrs, row);
             const float dot = d0 * v[0] + d1 * v[1];
             gp[0] += dot * ((k & 1) ? 1.f : -1.f) * wy * wz;
             gp[1] += dot * ((k & 2) ? 1.f : -1.f) * wx * wz;
@@ -338,8 +344,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           const float dy = above ? y[1] - st.xs[1] : y[1];
           const float dz = above ? y[2] - st.xs[2] : y[2];
           const float gw = (g_xs[0] * dx + g_xs[1] * dy + g_xs[2] * dz) * invL + g_L;
-          const Tri t = tri_cell((y[0] - a.m.mmin[0]) * a.m.mscale[0], (y[1] - a.m.mmin[1]) * a.m.mscale[1],
-                                 (y[2] - a.m.mmin[2]) * a.m.mscale[2]);
+          const Tri t = bone_cell(a.m, y);
           float* gplane = a.grad_weights + b * plane;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {

@@ -107,3 +107,16 @@ def test_full_size_body_frame_sampled():
     o = oracle_render(sc, pixel_ids=pid)
     assert _report("512x512 sampled", g[pid], o) <= FP32_TOL
     assert 0.27 <= (g[:, 3] > 0.5).mean() <= 0.33
+
+
+def test_frame_and_ray_list_kernels_agree():
+    # Full frames go through the 8x8 ray-packet kernel, explicit ray lists
+    # through the per-ray chunk kernel; the two agree within the early
+    # termination bound (they stop at different granularity).
+    sc = scenes.scene_body(H=40, W=56, spp=128)
+    frame = gpu_render(sc)
+    listed = gpu_render(sc, pixel_ids=np.arange(40 * 56, dtype=np.int32))
+    assert np.abs(frame - listed).max() <= 4e-6
+    off_f = gpu_render(sc, ert_tau=0.0)
+    off_l = gpu_render(sc, pixel_ids=np.arange(40 * 56, dtype=np.int32), ert_tau=0.0)
+    assert np.abs(off_f - off_l).max() <= 2e-6

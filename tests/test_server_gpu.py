@@ -1,0 +1,97 @@
+"""Render server on the GPU: continuous batching of mixed-resolution,
+multi-user requests; results identical alone and in the mix (and to
+mnr_render); memory admission; rejection of invalid requests."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _user(seed, table_dt=1, mlp_dt=2):
+    import paper_2306_16541_amd as m
+    sc = scenes.scene_body(H=64, W=64, spp=64, res=32, log2_T=16, seed=seed)
+    fld, _ = m.upload_scene(sc, "cuda", table_dt, mlp_dt)
+    return sc, fld
+
+
+def _req(sc, seed, H, W):
+    import paper_2306_16541_amd as m
+    aa = scenes.pose(seed, 0.3)
+    return m.PoseHost(sc.parents, sc.rest_joints, aa), m.make_camera(scenes.camera(H, W, yaw=0.3 * seed)), H, W
+
+
+def test_alone_equals_mix_equals_render():
+    import paper_2306_16541_amd as m
+    users = [_user(16541 + 50 + u) for u in range(3)]
+    srv = m.Server(mem_budget=4 << 30, max_slots=8, tiles_per_tick=64)   # small ticks: frames span ticks
+    for u, (_, fld) in enumerate(users):
+        srv.add_user(u, fld)
+    spp = 64
+    sc0, fld0 = users[0]
+    pose, cam, H, W = _req(sc0, 1, 160, 128)
+    alone = torch.full((H * W, 4), -1.0, device="cuda")
+    srv.wait(srv.submit(0, pose, cam, H, W, spp, alone))
+    ref = m.render(fld0, pose, cam, H, W, spp, m.make_opts()).clone()
+    # the same request inside a mix of other users and sizes, several ticks deep
+    outs, tickets = [], []
+    sizes = [(64, 64), (256, 192), (96, 96), (32, 200), (128, 128)]
+    for k, (h, w) in enumerate(sizes):
+        u = (k + 1) % 3
+        p, c, hh, ww = _req(users[u][0], 10 + k, h, w)
+        o = torch.zeros(hh * ww, 4, device="cuda")
+        tickets.append(srv.submit(u, p, c, hh, ww, spp, o))
+        outs.append((u, p, c, hh, ww, o))
+        if k == 2:
+            mixed = torch.full((H * W, 4), -2.0, device="cuda")
+            t_mix = srv.submit(0, pose, cam, H, W, spp, mixed)
+    srv.wait(t_mix)
+    for t in tickets:
+        srv.wait(t)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, ref)
+    assert torch.equal(mixed, alone)
+    for u, p, c, hh, ww, o in outs:     # every mixed request equals its own plain render
+        r = m.render(users[u][1], p, c, hh, ww, spp, m.make_opts())
+        assert torch.equal(o, r)
+    st = srv.stats()
+    print("server stats", st)
+    assert st["completed"] == 7 and st["ticks"] >= 7
+    srv.close()
+
+
+def test_memory_admission_and_rejections():
+    import math
+    import paper_2306_16541_amd as m
+    sc, fld = _user(16541 + 60)
+    resident = (16 * (1 << 16) * 2 * 2 + sum(w.size for w in sc.mlp) * 2 + 25 * 32 ** 3 * 4)
+    frame = 64 * 64 * 16
+    srv = m.Server(mem_budget=resident + frame + 100, max_slots=4)      # room for one 64x64 output
+    srv.add_user(0, fld)
+    with pytest.raises(m.MnrError, match="already"):
+        srv.add_user(0, fld)
+    _, fld2 = _user(16541 + 61)
+    with pytest.raises(m.MnrError, match="over memory budget"):
+        srv.add_user(1, fld2)
+    pose, cam, H, W = _req(sc, 3, 64, 64)
+    big = torch.zeros(128 * 128, 4, device="cuda")
+    with pytest.raises(m.MnrError, match="over memory budget"):
+        srv.submit(0, *_req(sc, 3, 128, 128)[:2], 128, 128, 64, big)
+    bad = sc.axis_angle.copy(); bad[5, 0] = math.nan
+    with pytest.raises(m.MnrError, match="invalid"):
+        srv.submit(0, m.PoseHost(sc.parents, sc.rest_joints, bad), cam, H, W, 64, big)
+    with pytest.raises(m.MnrError, match="invalid"):
+        srv.submit(7, pose, cam, H, W, 64, big)
+    outs = [torch.zeros(H * W, 4, device="cuda") for _ in range(5)]
+    tickets = [srv.submit(0, pose, cam, H, W, 64, o) for o in outs]
+    ts = [srv.wait(t) for t in tickets]
+    # only one output fits: each request is admitted after the previous one completed
+    for a, b in zip(ts[:-1], ts[1:]):
+        assert b[1] >= a[3]
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    st = srv.stats()
+    assert st["rejected"] >= 3 and st["completed"] == 5
+    srv.close()
