@@ -139,6 +139,72 @@ def train_bench(steps, warmup):
             "dtype": "fp32 table/adam, bf16 MLP"}
 
 
+def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=0.5, window_s=(4.0, 4.0, 2.0, 2.0)):
+    """Poisson arrivals from U users at rate_hz each; resolutions uniform over
+    {256^2, 512^2, 1024^2}; per-user fields resident (FP16 table, BF16 MLP);
+    per-frame pose ~ N(0, 0.3).  Latency = completion - arrival."""
+    import threading
+    sizes = (256, 512, 1024)
+    fields = []
+    for u in range(max(user_counts)):
+        sc = scenes.scene_body(H=512, W=512, spp=spp, seed=16541 + 5 + 1000 * u)
+        fld, _ = m.upload_scene(sc, "cuda", m.F16, m.BF16)
+        fields.append((sc, fld))
+    pool = {n: [torch.empty(n * n, 4, device="cuda") for _ in range(48)] for n in sizes}
+    results = []
+    for U, window in zip(user_counts, window_s):
+        srv = m.Server(mem_budget=8 << 30, max_slots=32, tiles_per_tick=1024)
+        for u in range(U):
+            srv.add_user(u, fields[u][1])
+        g = np.random.default_rng(U)
+        arrivals = []
+        for u in range(U):
+            t = g.exponential(1.0 / rate_hz)
+            while t < warmup_s + window:
+                arrivals.append((t, u))
+                t += g.exponential(1.0 / rate_hz)
+        arrivals.sort()
+        reqs = []
+        for k, (t, u) in enumerate(arrivals):
+            n = sizes[g.integers(3)]
+            sc = fields[u][0]
+            pose = m.PoseHost(sc.parents, sc.rest_joints, scenes.pose(7 * k + u, 0.3))
+            cam = m.make_camera(scenes.camera(n, n, yaw=float(g.uniform(0, 2 * np.pi))))
+            reqs.append((t, u, n, pose, cam, pool[n][k % len(pool[n])]))
+        tickets = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+
+        def producer():
+            for t, u, n, pose, cam, out in reqs:
+                dt = t0 + t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append((t, n, srv.submit(u, pose, cam, n, n, spp, out)))
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        lat = {n: [] for n in sizes}
+        done_times = []
+        for t, n, tk in tickets:
+            ts = srv.wait(tk, 600000)
+            if t >= warmup_s:
+                lat[n].append((ts[3] - ts[0]) / 1e6)
+                done_times.append(ts[3])
+        st = srv.stats()
+        srv.close()
+        every = [v for n in sizes for v in lat[n]]
+        span = (max(done_times) - min(done_times)) / 1e9 if len(done_times) > 1 else float("nan")
+        q = lambda v, p: float(np.percentile(v, p)) if v else None
+        results.append({"users": U, "offered_frames_per_s": U * rate_hz, "window_s": window,
+                        "frames": len(every), "completed_frames_per_s": len(every) / span,
+                        "p50_ms": q(every, 50), "p99_ms": q(every, 99),
+                        "p50_ms_512": q(lat[512], 50), "p99_ms_512": q(lat[512], 99),
+                        "p99_ms_256": q(lat[256], 99), "p99_ms_1024": q(lat[1024], 99),
+                        "ticks": st["ticks"], "tiles": st["tiles"]})
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +213,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
     ap.add_argument("--mixed-only", action="store_true", help="the mixed-precision 512x512 frame only (profiling)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="plain 1 GiB device-to-device copy, for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
@@ -162,6 +230,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_per_launch": src.numel() * 4, "launches": args.steps}))
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serve_bench()}))
         return
     sc = scenes.scene_body()                              # 512x512, 128 spp
     if args.mixed_only:
@@ -205,6 +276,8 @@ def main():
             "evaluated_Msamples_per_s": big["n_eval"] / (big["kernel_ms"] * 1e-3) / 1e6}
         del big
         line["train_step_8192x128"] = train_bench(max(3, args.steps // 2), 2)
+        if not args.no_serve:
+            line["serving"] = serve_bench()
     cpu, par = oracle_sample(sc, fp32["img"], None if mixed is None else mixed["img"], args.cpu_budget)
     line["cpu_baseline"] = cpu
     line["parity_vs_oracle"] = par

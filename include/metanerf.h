@@ -40,6 +40,12 @@ extern "C" {
 #define MNR_MAX_LEVELS 16
 #define MNR_MAX_LAYERS 4
 #define MNR_MAX_SPP 1024
+/* Bytes of the optional device workspace of the render entry points: eight
+ * per-XCD work-queue counters (zeroed by the library on the call's stream
+ * before use).  With a workspace, waves pull work dynamically and balance
+ * the very uneven per-ray cost; without one (NULL) work is split
+ * statically.  Concurrent calls need distinct workspaces. */
+#define MNR_WORKSPACE_BYTES 64
 
 typedef enum {
   MNR_OK = 0,
@@ -150,7 +156,7 @@ mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mn
                       const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
                       const mnr_opts* opts, const int32_t* pixel_ids, int32_t n_rays,
                       float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
-                      void* stream);
+                      void* workspace, void* stream);
 
 /* Adjoint of mnr_render (hand-written; recomputes per-sample activations
  * instead of storing them).  Given t_chunks written by mnr_render with the
@@ -166,7 +172,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
                                int32_t n_rays, const float* t_chunks, const float* grad_rgba,
                                float* grad_table, float* const* grad_w, float* grad_weights,
-                               void* stream);
+                               void* workspace, void* stream);
 
 /* Squared-error loss of Eq. 14's MSE term over RGB: loss = mean over rays
  * and channels of (rgb - target)^2.  target: dev [n_rays][3].  Writes
@@ -212,6 +218,7 @@ typedef struct {
   float* rgba; float* grad_rgba;                                          /* [n_rays][4] scratch */
   float* t_chunks;                                    /* [n_rays][ceil(spp/64) + 1] scratch */
   float* loss;                                                            /* [1] */
+  void* workspace;                                           /* MNR_WORKSPACE_BYTES, or NULL */
   float lr_field, lr_motion, beta1, beta2, eps;
   int32_t step;                                                           /* 1-based */
   int32_t train_motion;                                                   /* 0 = logits frozen */

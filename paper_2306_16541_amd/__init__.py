@@ -75,6 +75,7 @@ class TrainState(C.Structure):
                  ("w_v", _FP * MAX_LAYERS)] +
                 [("logits", _FP), ("logits_grad", _FP), ("logits_m", _FP), ("logits_v", _FP),
                  ("weights_grad", _FP), ("rgba", _FP), ("grad_rgba", _FP), ("t_chunks", _FP), ("loss", _FP),
+                 ("workspace", _FP),
                  ("lr_field", C.c_float), ("lr_motion", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                  ("eps", C.c_float), ("step", C.c_int32), ("train_motion", C.c_int32)])
 
@@ -91,9 +92,9 @@ _sig("mnr_version", C.c_char_p, [])
 _sig("mnr_fk_bones", C.c_int, [C.POINTER(Pose), C.c_void_p])
 _RENDER_COMMON = [C.POINTER(Field), C.POINTER(Motion), C.POINTER(Pose), C.POINTER(Camera), C.c_int32, C.c_int32,
                   C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_int32]
-_sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_render_backward", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
-                                                       C.c_void_p])
+                                                       C.c_void_p, C.c_void_p])
 _sig("mnr_mse_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_softmax_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
 _sig("mnr_softmax_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
@@ -120,6 +121,19 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+WORKSPACE_BYTES = 64
+_WS = {}
+
+
+def _workspace(device) -> torch.Tensor:
+    """Work-queue counters for the render entry points, one buffer per
+    (device, stream) so that calls on different streams never share one."""
+    key = (torch.device(device).index, torch.cuda.current_stream(device).cuda_stream)
+    if key not in _WS:
+        _WS[key] = torch.zeros(WORKSPACE_BYTES // 4, dtype=torch.int32, device=device)
+    return _WS[key]
 
 
 def version() -> str:
@@ -237,14 +251,16 @@ def saved_size(spp: int) -> int:
 
 def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts] = None,
            pixel_ids: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-           counter: Optional[torch.Tensor] = None, t_chunks: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """RGBA [n_rays, 4] (full frame: [H*W, 4], row-major pixels)."""
+           counter: Optional[torch.Tensor] = None, t_chunks: Optional[torch.Tensor] = None,
+           dynamic: bool = True) -> torch.Tensor:
+    """RGBA [n_rays, 4] (full frame: [H*W, 4], row-major pixels).  dynamic:
+    pass a work-queue workspace (dynamic load balancing) or not (static split)."""
     n = H * W if pixel_ids is None else int(pixel_ids.numel())
     if out is None:
         out = torch.empty((n, 4), dtype=torch.float32, device=field.table.device)
     check(lib.mnr_render(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                          None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(out), _ptr(t_chunks),
-                         _ptr(counter), _stream()), "render")
+                         _ptr(counter), _ptr(_workspace(out.device)) if dynamic else None, _stream()), "render")
     return out
 
 
@@ -255,7 +271,8 @@ def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: 
     gw = (C.c_void_p * len(grad_w))(*[g.data_ptr() for g in grad_w])
     check(lib.mnr_render_backward(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                                   None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(t_chunks),
-                                  _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights), _stream()),
+                                  _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights),
+                                  _ptr(_workspace(grad_table.device)), _stream()),
           "render_backward")
 
 
@@ -326,6 +343,7 @@ class Trainer:
             "weights_grad": z(self.logits),
             "rgba": torch.zeros(max_rays, 4, device=dev), "grad_rgba": torch.zeros(max_rays, 4, device=dev),
             "t_chunks": torch.zeros(max_rays * saved_size(spp), device=dev), "loss": torch.zeros(1, device=dev),
+            "workspace": torch.zeros(WORKSPACE_BYTES // 4, dtype=torch.int32, device=dev),
         }
         self.max_rays, self.max_spp = max_rays, spp
         s = TrainState()
@@ -339,6 +357,7 @@ class Trainer:
         s.logits_m, s.logits_v = b["logits_m"].data_ptr(), b["logits_v"].data_ptr()
         s.weights_grad, s.rgba, s.grad_rgba = b["weights_grad"].data_ptr(), b["rgba"].data_ptr(), b["grad_rgba"].data_ptr()
         s.t_chunks, s.loss = b["t_chunks"].data_ptr(), b["loss"].data_ptr()
+        s.workspace = b["workspace"].data_ptr()
         s.lr_field, s.lr_motion, s.beta1, s.beta2, s.eps = lr_field, lr_motion, beta1, beta2, eps
         s.step, s.train_motion = 0, int(bool(train_motion))
         self.state = s

@@ -164,7 +164,7 @@ const char* mnr_version(void) { return "metanerf-gfx950 0.1"; }
 mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose, const mnr_camera* cam,
                       int32_t H, int32_t W, int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
                       int32_t n_rays, float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
-                      void* stream) {
+                      void* workspace, void* stream) {
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba)) return s;
   if (n_rays == 0) return MNR_OK;
@@ -173,6 +173,10 @@ mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mn
   a.out = out_rgba;
   a.t_chunks = t_chunks;
   a.n_eval = n_evaluated;
+  a.queues = (int32_t*)workspace;
+  if (workspace) {
+    if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, (hipStream_t)stream), "workspace")) return s;
+  }
   return hip_status(launch_render_fwd(a, slot_count(H, W, pixel_ids, n_rays), field->table_dtype, field->mlp_dtype,
                                       field->n_layers - 2, (hipStream_t)stream),
                     "render launch");
@@ -182,7 +186,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
                                const int32_t* pixel_ids, int32_t n_rays, const float* t_chunks,
                                const float* grad_rgba, float* grad_table, float* const* grad_w, float* grad_weights,
-                               void* stream) {
+                               void* workspace, void* stream) {
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
   if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
@@ -196,6 +200,10 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
   a.grad_table = grad_table;
   for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = grad_w[k];
   a.grad_weights = grad_weights;
+  a.queues = (int32_t*)workspace;
+  if (workspace) {
+    if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, (hipStream_t)stream), "workspace")) return s;
+  }
   return hip_status(launch_render_bwd(a, slot_count(H, W, pixel_ids, n_rays), field->table_dtype, field->mlp_dtype,
                                       field->n_layers - 2, (hipStream_t)stream),
                     "backward launch");
@@ -296,12 +304,15 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   const int slots = slot_count(H, W, pixel_ids, n_rays);
   a.out = st->rgba;
   a.t_chunks = st->t_chunks;
+  a.queues = (int32_t*)st->workspace;
+  if (st->workspace) ok(launch_zero(st->workspace, MNR_WORKSPACE_BYTES, s));
   ok(launch_render_fwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
   ok(launch_mse(st->rgba, target, n_rays, st->grad_rgba, st->loss, s));
   a.grad_rgba = st->grad_rgba;
   a.grad_table = st->table_grad;
   for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = st->w_grad[k];
   a.grad_weights = st->weights_grad;
+  if (st->workspace) ok(launch_zero(st->workspace, MNR_WORKSPACE_BYTES, s));
   ok(launch_render_bwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
   ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
                  st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,

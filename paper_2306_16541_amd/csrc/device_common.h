@@ -69,6 +69,7 @@ struct RenderArgs {
   float* out;                        // [n_rays][4]
   float* t_chunks;                   // [n_rays][nchunks] (forward writes, adjoint reads)
   unsigned long long* n_eval;        // optional counter
+  int32_t* queues;                   // optional: 8 per-XCD work counters, zero at launch
   // adjoint only
   const float* grad_rgba;            // [n_rays][4]
   float* grad_table;
@@ -164,6 +165,24 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int k = WAVE / 2; k > 0; k >>= 1) v += __shfl_xor(v, k, WAVE);
   return v;
+}
+
+// Dynamic work pulling for one wave.  Work units come in groups of GROUP
+// consecutive units; group g belongs to the queue of XCD g % 8, so each
+// XCD works through its own spatially coherent groups first and then
+// steals from the others.  q starts at the wave's XCD (blockIdx.x % 8).
+// Returns the next unit, or -1 once every queue is exhausted.
+template <int GROUP>
+__device__ __forceinline__ int pull_unit(int32_t* queues, int n_units, int& q, int& tried) {
+  for (;;) {
+    int local = 0;
+    if (__lane_id() == 0) local = atomicAdd(queues + q, 1);
+    local = __builtin_amdgcn_readfirstlane(local);
+    const int unit = (q + 8 * (local / GROUP)) * GROUP + local % GROUP;
+    if (unit < n_units) return unit;  // a queue's units only grow, so >= n_units means exhausted
+    if (++tried >= 8) return -1;
+    q = (q + 1) & 7;
+  }
 }
 
 __device__ __forceinline__ void wave_sync_lds() {

@@ -193,8 +193,10 @@ __device__ __forceinline__ void encode_all(const FieldArgs& f, const float u[3],
       const bool dense = (f.dense_mask >> l) & 1u;
       c[q] = grid_cell(u, N);
       const __amdgpu_buffer_rsrc_t rs = level_rsrc<TableT>(f, l);
+      if (live) {  // one exec-masked region: dead lanes issue no gathers
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[q][k] = load_row<TableT>(rs, grid_row(c[q], N, dense, mask, k));
+        for (int k = 0; k < 8; ++k) v[q][k] = load_row<TableT>(rs, grid_row(c[q], N, dense, mask, k));
+      }
     }
 #pragma unroll
     for (int q = 0; q < LG; ++q) store(l0 + q, live ? trilerp2(v[q], c[q].f) : f2{0.f, 0.f});

@@ -23,25 +23,34 @@
 
 namespace mnr {
 
+// Waves per block of the frame and ray-list kernels: the MLP weights in LDS
+// are shared by the block, so bigger blocks leave more LDS per CU for the
+// per-wave feature buffers (FP32: 44 KiB + 12 x 8 KiB fits one block, three
+// waves per SIMD).
+template <int P>
+constexpr int block_waves() { return P == MNR_F32 ? 12 : 8; }
+
 // Ray slot handled by iteration `it` of wave `w` of block `blk`.
+template <int NW>
 __device__ __forceinline__ int ray_slot(int blk, int nblk, int w, int it, int n_slots) {
   const int xcd = blk & 7, lb = blk >> 3;
   const int nb = (nblk - xcd + 7) >> 3;  // blocks on this XCD
-  const int k = (it * nb + lb) * WAVES_PER_BLOCK + w;  // k-th ray of this XCD
+  const int k = (it * nb + lb) * NW + w;  // k-th ray of this XCD
   const int slot = ((k >> 8) * 8 + xcd) * 256 + (k & 255);
   return slot < n_slots ? slot : -1;
 }
 
+template <int NW>
 __device__ __forceinline__ int n_iters(int nblk, int n_slots) {
   // Enough iterations for the least-loaded XCD to cover its tiles.
   const int tiles = (n_slots + 255) >> 8;
   const int tiles_per_xcd = (tiles + 7) >> 3;
   const int nb_min = nblk >> 3 > 0 ? nblk >> 3 : 1;
-  return (tiles_per_xcd * 256 + nb_min * WAVES_PER_BLOCK - 1) / (nb_min * WAVES_PER_BLOCK);
+  return (tiles_per_xcd * 256 + nb_min * NW - 1) / (nb_min * NW);
 }
 
-template <typename TableT, int P, int NHH>
-__global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, int n_slots) {
+template <typename TableT, int P, int NHH, int NW>
+__global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a, int n_slots) {
   using S = MlpShape<P>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* wl = lds;
@@ -53,11 +62,19 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, i
 
   const int S_ = a.r.spp;
   const int nchunks = (S_ + 63) >> 6;
-  const int iters = n_iters(gridDim.x, n_slots);
+  const int iters = n_iters<NW>(gridDim.x, n_slots);
 
-  for (int it = 0; it < iters; ++it) {
-    const int slot = ray_slot(blockIdx.x, gridDim.x, wave, it, n_slots);
-    if (slot < 0) continue;
+  int q = blockIdx.x & 7, tried = 0;
+  for (int it = 0;; ++it) {
+    int slot;
+    if (a.queues) {  // dynamic: pull rays (groups of 256) from per-XCD queues
+      slot = pull_unit<256>(a.queues, n_slots, q, tried);
+      if (slot < 0) break;
+    } else {
+      if (it >= iters) break;
+      slot = ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
+      if (slot < 0) continue;
+    }
     const int pix = ray_pixel(a.r, slot);
     if (!a.r.pixel_ids && pix < 0) continue;  // tile slot outside the image
     const int orow = a.r.pixel_ids ? slot : pix;
@@ -110,9 +127,12 @@ __global__ void __launch_bounds__(BLOCK) render_fwd_kernel(const RenderArgs a, i
 }
 
 
-template <typename TableT, int P, int NHH>
-__global__ void __launch_bounds__(BLOCK) render_packet_kernel(const RenderArgs a, int n_tiles) {
+// NW / 4 consecutive 16x16 tiles per block iteration (four 8x8 packets
+// each); tile groups are dealt round-robin to the XCDs.
+template <typename TableT, int P, int NHH, int NW>
+__global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs a, int n_tiles) {
   using S = MlpShape<P>;
+  constexpr int TPB = NW / 4;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* wl = lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -120,23 +140,34 @@ __global__ void __launch_bounds__(BLOCK) render_packet_kernel(const RenderArgs a
 
   stage_weights<P, NHH>(wl, a.f);
   __syncthreads();
+  if (a.queues) {  // dynamic: each wave pulls 8x8 packets (4 per tile) from per-XCD queues
+    int q = blockIdx.x & 7, tried = 0;
+    for (;;) {
+      const int unit = pull_unit<4>(a.queues, n_tiles * 4, q, tried);
+      if (unit < 0) break;
+      render_tile_packet<TableT, P, NHH>(a, unit >> 2, unit & 3, lane, wl, feat);
+    }
+    return;
+  }
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
   const int nb = ((int)gridDim.x - xcd + 7) >> 3;  // blocks on this XCD
+  const int n_groups = (n_tiles + TPB - 1) / TPB;
   for (int k = lb;; k += nb) {
-    const int tile = k * 8 + xcd;
-    if (tile >= n_tiles) break;
-    render_tile_packet<TableT, P, NHH>(a, tile, wave, lane, wl, feat);
+    const int group = k * 8 + xcd;
+    if (group >= n_groups) break;
+    const int tile = group * TPB + (wave >> 2);
+    if (tile < n_tiles) render_tile_packet<TableT, P, NHH>(a, tile, wave & 3, lane, wl, feat);
   }
 }
 
 template <typename KernelT>
-static int persistent_blocks(KernelT kern, int lds, int* cache) {
+static int persistent_blocks(KernelT kern, int threads, int lds, int* cache) {
   if (*cache == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, threads, lds);
     *cache = cus * (per_cu > 0 ? per_cu : 1);
   }
   return *cache;
@@ -145,23 +176,25 @@ static int persistent_blocks(KernelT kern, int lds, int* cache) {
 template <typename TableT, int P, int NHH>
 static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
   using S = MlpShape<P>;
-  const int lds = S::bytes_total(NHH) + WAVES_PER_BLOCK * S::feat_bytes_per_wave();
-  if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, one 16x16 tile per block
-    auto kern = render_packet_kernel<TableT, P, NHH>;
+  constexpr int NW = block_waves<P>();
+  const int lds = S::bytes_total(NHH) + NW * S::feat_bytes_per_wave();
+  if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, NW/4 16x16 tiles per block
+    auto kern = render_packet_kernel<TableT, P, NHH, NW>;
     static int max_blocks = 0;
     const int n_tiles = n_slots / 256;
-    const int mb = persistent_blocks(kern, lds, &max_blocks);
-    const int grid = n_tiles < mb ? n_tiles : mb;
-    hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(BLOCK), lds, st, a, n_tiles);
+    const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
+    const int groups = a.queues ? (n_tiles * 4 + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
+    const int grid = groups < mb ? groups : mb;
+    hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
     return hipGetLastError();
   }
-  auto kern = render_fwd_kernel<TableT, P, NHH>;
+  auto kern = render_fwd_kernel<TableT, P, NHH, NW>;
   static int max_blocks = 0;
-  const int mb = persistent_blocks(kern, lds, &max_blocks);
-  const int need = (n_slots + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
+  const int need = (n_slots + NW - 1) / NW;
   int grid = need < mb ? need : mb;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, st, a, n_slots);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, st, a, n_slots);
   return hipGetLastError();
 }
 

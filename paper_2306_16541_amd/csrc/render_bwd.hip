@@ -207,9 +207,17 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   const int nb_min = (gridDim.x >> 3) > 0 ? (gridDim.x >> 3) : 1;
   const int iters = (((tiles + 7) >> 3) * 256 + nb_min * NW - 1) / (nb_min * NW);
 
-  for (int it = 0; it < iters; ++it) {
-    const int slot = bwd_ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
-    if (slot < 0) continue;
+  int q = blockIdx.x & 7, tried = 0;
+  for (int it = 0;; ++it) {
+    int slot;
+    if (a.queues) {  // dynamic: pull rays (groups of 256) from per-XCD queues
+      slot = pull_unit<256>(a.queues, n_slots, q, tried);
+      if (slot < 0) break;
+    } else {
+      if (it >= iters) break;
+      slot = bwd_ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
+      if (slot < 0) continue;
+    }
     const int pix = ray_pixel(a.r, slot);
     if (!a.r.pixel_ids && pix < 0) continue;
     const int orow = a.r.pixel_ids ? slot : pix;

@@ -286,7 +286,10 @@ mnr_status mnr_server_submit(mnr_server* s, int32_t user, const mnr_pose* pose, 
   {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->users.find(user);
-    if (it == s->users.end()) return fail(MNR_E_INVALID, "server: unknown user %d", user);
+    if (it == s->users.end()) {
+      s->st.rejected++;
+      return fail(MNR_E_INVALID, "server: unknown user %d", user);
+    }
     u = it->second;
   }
   if (mnr_status st = validate_common(&u.field, &u.motion, pose, cam, H, W, spp, opts, nullptr, H * W, out_rgba)) {

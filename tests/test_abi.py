@@ -69,7 +69,7 @@ def _args(sc):
 
 def _render(m, f, mo, pose, cam, H=8, W=8, spp=8, opts=None, pid=None, n=64, out=0x4000):
     return m.lib.mnr_render(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), H, W, spp,
-                            None if opts is None else C.byref(opts), pid, n, out, None, None, None)
+                            None if opts is None else C.byref(opts), pid, n, out, None, None, None, None)
 
 
 def test_invalid_calls_are_rejected_before_launch():
