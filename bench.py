@@ -34,6 +34,34 @@ BYTES_WARP = 24 * 8 * 4                        # per evaluated sample: 24 bones 
 BYTES_ENC = {"f32": 16 * 8 * 2 * 4, "f16": 16 * 8 * 2 * 2}   # 16 levels x 8 corners x 2 features
 
 
+def sources_digest():
+    """SHA-256 over the kernel sources and headers (identifies the build the
+    counter-based traffic figures were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d, exts in ((os.path.join(ROOT, "paper_2306_16541_amd", "csrc"), (".hip", ".h", ".cpp")),
+                    (os.path.join(ROOT, "include"), (".h",))):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(exts):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, scaled by the copy calibration; None if the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("sources_sha256") != sources_digest() or key not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][key]
+    return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
+
+
 def mlp_flops(widths):
     return 2 * sum(a * b for a, b in zip(widths[:-1], widths[1:]))
 
@@ -214,10 +242,14 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
     ap.add_argument("--mixed-only", action="store_true", help="the mixed-precision 512x512 frame only (profiling)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--digest", action="store_true", help="print the kernel-source digest and exit")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="plain 1 GiB device-to-device copy, for scaling FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.digest:
+        print(sources_digest())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every ray is independent and the whole frame fits one MI355X; "
               "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
@@ -242,6 +274,7 @@ def main():
     fp32 = render_bench(sc, m.F32, m.F32, args.steps, args.warmup)
     widths = [32] + [w.shape[0] for w in sc.mlp]
     roof, roof2 = roofline(fp32, sc, "f32", "f32", widths)
+    roof["traffic"] = measured_traffic("render_fwd_fp32_512x512x128")
     nominal = sc.H * sc.W * sc.spp
     line = {
         "metric": METRIC,
@@ -267,7 +300,8 @@ def main():
         line["mixed_512"] = {
             "Msamples_per_s": nominal / (mixed["kernel_ms"] * 1e-3) / 1e6, "frames_per_s": 1e3 / mixed["kernel_ms"],
             "speedup_vs_fp32": fp32["kernel_ms"] / mixed["kernel_ms"], "dtype": "fp16 table, bf16 MLP (fp32 acc)",
-            "roofline": roofline(mixed, sc, "f16", "bf16", widths)[0]}
+            "roofline": dict(roofline(mixed, sc, "f16", "bf16", widths)[0],
+                             traffic=measured_traffic("render_fwd_mixed_512x512x128"))}
         sc3 = scenes.scene_body(H=1024, W=1024, spp=192)
         big = render_bench(sc3, m.F16, m.BF16, max(3, args.steps // 4), 1)
         line["mixed_1024_192spp"] = {

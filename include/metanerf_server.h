@@ -18,14 +18,17 @@
  *     tick k runs);
  *   - per-request timestamps (arrival, admission, first tick, completion)
  *     give p50/p99 latency.
- * A request's pixels are computed by the same device code as mnr_render for
- * a full frame, with a fixed ray-to-lane mapping and no atomics, so a
- * request's image is bitwise identical whether it is rendered alone, in a
- * mix, or by mnr_render.
+ * A request's pixels are computed with a fixed ray-to-lane mapping and no
+ * atomics, so its image is bitwise identical whether it is rendered alone
+ * or in a mix; it is the same device code as mnr_render's full-frame path
+ * (inlined into another kernel) and matches it to within 1e-6.
  *
  * All calls are thread-safe.  Device memory: the server allocates its
  * request slots and tile tables; users' fields and request outputs are
- * caller-owned and must stay valid while in use.
+ * caller-owned and must stay valid while in use.  The server works on its
+ * own stream, unordered with the caller's streams: a field or output
+ * buffer must have no pending work on other streams when it is registered
+ * or submitted, and must not be reused until the request has completed.
  */
 #ifndef METANERF_SERVER_H
 #define METANERF_SERVER_H

@@ -36,8 +36,13 @@ def test_alone_equals_mix_equals_render():
     sc0, fld0 = users[0]
     pose, cam, H, W = _req(sc0, 1, 160, 128)
     alone = torch.full((H * W, 4), -1.0, device="cuda")
+    # The server renders on its own stream: buffers handed to it must have no
+    # pending work on torch's stream, and torch must not recycle memory the
+    # server may still write (synchronise before submitting).
+    torch.cuda.synchronize()
     srv.wait(srv.submit(0, pose, cam, H, W, spp, alone))
     ref = m.render(fld0, pose, cam, H, W, spp, m.make_opts()).clone()
+    torch.cuda.synchronize()
     # the same request inside a mix of other users and sizes, several ticks deep
     outs, tickets = [], []
     sizes = [(64, 64), (256, 192), (96, 96), (32, 200), (128, 128)]
@@ -45,10 +50,12 @@ def test_alone_equals_mix_equals_render():
         u = (k + 1) % 3
         p, c, hh, ww = _req(users[u][0], 10 + k, h, w)
         o = torch.zeros(hh * ww, 4, device="cuda")
+        torch.cuda.synchronize()
         tickets.append(srv.submit(u, p, c, hh, ww, spp, o))
         outs.append((u, p, c, hh, ww, o))
         if k == 2:
             mixed = torch.full((H * W, 4), -2.0, device="cuda")
+            torch.cuda.synchronize()
             t_mix = srv.submit(0, pose, cam, H, W, spp, mixed)
     srv.wait(t_mix)
     for t in tickets:
@@ -93,6 +100,7 @@ def test_memory_admission_and_rejections():
     with pytest.raises(m.MnrError, match="invalid"):
         srv.submit(7, pose, cam, H, W, 64, big)
     outs = [torch.zeros(H * W, 4, device="cuda") for _ in range(5)]
+    torch.cuda.synchronize()
     tickets = [srv.submit(0, pose, cam, H, W, 64, o) for o in outs]
     ts = [srv.wait(t) for t in tickets]
     # only one output fits: each request is admitted after the previous one completed
