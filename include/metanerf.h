@@ -88,12 +88,29 @@ typedef struct {
 /* Canonical blend-weight volume W^c (Sec. 4.2, Eq. 9-10): dev float
  * [n_bones + 1][res^3], voxel (x,y,z) at x + res*(y + res*z), channel
  * n_bones = background.  Vertex-aligned over [box_min, box_max]; trilinear
- * samples treat vertices outside the volume as zero. */
+ * samples treat vertices outside the volume as zero.
+ * packed (optional, NULL = unused): a copy of the bone channels written by
+ * mnr_motion_pack in which the four x-y corners of every trilinear cell are
+ * adjacent, so that one bone's sample takes two 16-byte loads instead of
+ * eight 4-byte gathers.  The renderer reads it instead of `weights` when
+ * present (bitwise identical results); the caller re-packs after changing
+ * `weights` (mnr_train_step does so itself). */
 typedef struct {
   int32_t n_bones, res;
   float box_min[3], box_max[3];
   const float* weights;
+  const float* packed;
 } mnr_motion;
+
+/* Size in bytes of the packed copy: n_bones * res * (res+1)^2 * 16
+ * (layout [bone][z][y+1][x+1] of float4 {W(x,y,z), W(x+1,y,z), W(x,y+1,z),
+ * W(x+1,y+1,z)}, zero for vertices outside the volume, x, y in [-1, res-1]).
+ * 0 for invalid sizes. */
+uint64_t mnr_motion_packed_bytes(int32_t res, int32_t n_bones);
+/* Write motion->packed (dev, mnr_motion_packed_bytes bytes, caller-owned)
+ * from motion->weights on `stream`.  MNR_E_INVALID for a NULL or misaligned
+ * (16 B) packed pointer or bad sizes. */
+mnr_status mnr_motion_pack(const mnr_motion* motion, void* stream);
 
 /* Body pose (Sec. 4.1-4.2): host arrays.  parent[j] < j (root: -1), rest
  * joints [n][3] in the canonical (rest) pose, axis-angle [n][3] of the

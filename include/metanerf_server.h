@@ -8,10 +8,11 @@
  * as they arrive:
  *   - admission: a queued request is admitted when a slot is free and the
  *     memory budget (resident users + outputs of admitted requests) allows;
- *   - continuous batching: each GPU tick renders 16x16-pixel tiles of all
- *     admitted requests, oldest first, up to a tile budget; requests that
- *     arrive while a tick runs join the next tick; large frames span
- *     several ticks;
+ *   - continuous batching: each GPU tick renders 16x16-pixel tiles of the
+ *     admitted requests up to a tile budget -- a quarter of it for the
+ *     oldest unfinished request, the rest shortest-remaining-first -- so
+ *     requests that arrive while a tick runs join the next one and small
+ *     frames overtake large ones; large frames span several ticks;
  *   - one persistent kernel per tick pulls tiles from a device-side table;
  *     the per-tick work (table upload + kernel) is replayed from captured
  *     hipGraphs (two, double-buffered, so the host prepares tick k+1 while

@@ -47,7 +47,7 @@ class Field(C.Structure):
 
 class Motion(C.Structure):
     _fields_ = [("n_bones", C.c_int32), ("res", C.c_int32), ("box_min", C.c_float * 3),
-                ("box_max", C.c_float * 3), ("weights", C.c_void_p)]
+                ("box_max", C.c_float * 3), ("weights", C.c_void_p), ("packed", C.c_void_p)]
 
 
 class Pose(C.Structure):
@@ -102,11 +102,13 @@ _sig("mnr_adam_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
                                 C.c_float, C.c_float, C.c_int32, C.c_void_p, C.c_int, C.c_void_p])
 _sig("mnr_convert", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p])
 _sig("mnr_zero", C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p])
+_sig("mnr_motion_packed_bytes", C.c_uint64, [C.c_int32, C.c_int32])
+_sig("mnr_motion_pack", C.c_int, [C.POINTER(Motion), C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
-            "mnr_train_step"]
+            "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -176,10 +178,12 @@ def fk_bones(pose: PoseHost) -> np.ndarray:
 
 class DeviceField:
     """A canonical field resident on the GPU: grid table + MLP weights (in
-    the dtypes the renderer reads) and the motion-weight volume."""
+    the dtypes the renderer reads) and the motion-weight volume, with its
+    packed copy (packed=True) that the renderer reads instead; call repack()
+    after changing `weights` in place."""
 
     def __init__(self, table: torch.Tensor, mlp: Sequence[torch.Tensor], weights: torch.Tensor, level_res,
-                 box_min=(-0.5,) * 3, box_max=(0.5,) * 3, n_feat: int = 2):
+                 box_min=(-0.5,) * 3, box_max=(0.5,) * 3, n_feat: int = 2, packed: bool = True):
         self.table, self.mlp, self.weights = table, list(mlp), weights
         dt = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
         f = Field()
@@ -199,7 +203,19 @@ class DeviceField:
         m.n_bones, m.res = int(weights.shape[0]) - 1, int(weights.shape[-1])
         m.box_min[:], m.box_max[:] = list(box_min), list(box_max)
         m.weights = weights.data_ptr()
+        self.packed = None
+        if packed:
+            nb = int(lib.mnr_motion_packed_bytes(m.res, m.n_bones))
+            if nb == 0:
+                raise MnrError(f"no packed copy for res {m.res}, {m.n_bones} bones")
+            self.packed = torch.empty(nb // 4, dtype=torch.float32, device=weights.device)
+            m.packed = self.packed.data_ptr()
         self.m = m
+        self.repack()
+
+    def repack(self) -> None:
+        if self.packed is not None:
+            check(lib.mnr_motion_pack(C.byref(self.m), _stream()), "motion_pack")
 
 
 def softmax_fwd(logits: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -225,7 +241,7 @@ def zero_(t: torch.Tensor) -> torch.Tensor:
     return t
 
 
-def upload_scene(sc, device="cuda", table_dtype: int = F32, mlp_dtype: int = F32):
+def upload_scene(sc, device="cuda", table_dtype: int = F32, mlp_dtype: int = F32, packed: bool = True):
     """Copy a scenes.Scene's arrays to the GPU and build a DeviceField
     (softmax and precision conversion run in the library's kernels).
     Returns (DeviceField, fp32 masters dict)."""
@@ -235,7 +251,7 @@ def upload_scene(sc, device="cuda", table_dtype: int = F32, mlp_dtype: int = F32
     weights = softmax_fwd(logits)
     table = table32 if table_dtype == F32 else convert(table32, table_dtype)
     mlp = w32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in w32]
-    fld = DeviceField(table, mlp, weights, sc.level_res, sc.box_min, sc.box_max)
+    fld = DeviceField(table, mlp, weights, sc.level_res, sc.box_min, sc.box_max, packed=packed)
     return fld, {"table": table32, "mlp": w32, "logits": logits}
 
 
@@ -299,6 +315,7 @@ class RenderFn(torch.autograd.Function):
         field, pose, cam, H, W, spp, opts, pixel_ids = cfg
         n = H * W if pixel_ids is None else int(pixel_ids.numel())
         tch = torch.empty((n, saved_size(spp)), dtype=torch.float32, device=table.device)
+        field.repack()  # weights may have changed since the last call
         out = render(field, pose, cam, H, W, spp, opts, pixel_ids, t_chunks=tch)
         ctx.cfg = cfg
         ctx.save_for_backward(tch)
@@ -398,6 +415,7 @@ class Trainer:
                 t.copy_(v)
         self.state.step = int(sd["step"])
         softmax_fwd(self.logits, out=self.weights)
+        self.field.repack()
         if self.table is not self.table32:
             check(lib.mnr_convert(_ptr(self.table32), _ptr(self.table), self.field.c.table_dtype, self.table32.numel(),
                                   _stream()), "convert")

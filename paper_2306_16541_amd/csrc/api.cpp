@@ -67,6 +67,9 @@ mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_po
   if (m->n_bones != p->n_joints) return fail(MNR_E_SHAPE, "motion: n_bones %d != pose joints %d", m->n_bones, p->n_joints);
   if (m->res < 2 || m->res > 512) return fail(MNR_E_SHAPE, "motion: res must be in [2, 512], got %d", m->res);
   if (mnr_status s = check_box(m->box_min, m->box_max, "motion")) return s;
+  if (m->packed && m->res > MAX_PACKED_RES)
+    return fail(MNR_E_SHAPE, "motion: packed copy needs res <= %d, got %d", MAX_PACKED_RES, m->res);
+  if (m->packed && ((uintptr_t)m->packed & 15)) return fail(MNR_E_INVALID, "motion: packed copy not 16-byte aligned");
   if (!c) return fail(MNR_E_INVALID, "camera: null pointer");
   if (!(c->fx > 0) || !(c->fy > 0) || !std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) ||
       !std::isfinite(c->cy))
@@ -105,6 +108,7 @@ void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr
     a.m.mscale[i] = (float)((m->res - 1) / ((double)m->box_max[i] - m->box_min[i]));
   }
   a.m.weights = m->weights;
+  a.m.packed = (const f4*)m->packed;
   a.m.res = m->res;
   a.m.n_bones = m->n_bones;
   double G[MNR_MAX_BONES * 12];
@@ -226,6 +230,21 @@ mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channe
   return hip_status(launch_softmax_fwd(logits, weights, n_channels, n_voxels, (hipStream_t)stream), "softmax launch");
 }
 
+uint64_t mnr_motion_packed_bytes(int32_t res, int32_t n_bones) {
+  if (res < 2 || res > MAX_PACKED_RES || n_bones < 1 || n_bones > MNR_MAX_BONES) return 0;
+  return (uint64_t)n_bones * res * (res + 1) * (res + 1) * sizeof(f4);
+}
+
+mnr_status mnr_motion_pack(const mnr_motion* m, void* stream) {
+  clear_error();
+  if (!m || !m->weights || !m->packed) return fail(MNR_E_INVALID, "motion_pack: null pointer");
+  if (((uintptr_t)m->packed & 15)) return fail(MNR_E_INVALID, "motion_pack: packed copy not 16-byte aligned");
+  if (mnr_motion_packed_bytes(m->res, m->n_bones) == 0)
+    return fail(MNR_E_SHAPE, "motion_pack: res %d / n_bones %d out of range", m->res, m->n_bones);
+  return hip_status(launch_pack_motion(m->weights, (f4*)m->packed, m->n_bones, m->res, (hipStream_t)stream),
+                    "motion_pack launch");
+}
+
 mnr_status mnr_softmax_bwd(const float* weights, const float* grad_weights, float* grad_logits, int32_t n_channels,
                            int64_t n_voxels, void* stream) {
   clear_error();
@@ -327,6 +346,8 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
     ok(launch_adam(st->logits, st->logits_grad, st->logits_m, st->logits_v, n_wc, st->lr_motion, st->beta1,
                    st->beta2, st->eps, st->step, nullptr, MNR_F32, s));
     ok(launch_softmax_fwd(st->logits, (float*)motion->weights, motion->n_bones + 1, n_vox, s));
+    if (motion->packed)
+      ok(launch_pack_motion(motion->weights, (f4*)motion->packed, motion->n_bones, motion->res, s));
   }
   return hip_status(e, "train_step launch");
 }

@@ -41,8 +41,13 @@ struct FieldArgs {
   float gmin[3], gscale[3];  // u = (x - gmin) * gscale
 };
 
+// Largest volume resolution with a packed copy: one bone's packed plane
+// (R (R+1)^2 float4) must stay below the 2^31-byte buffer-offset range.
+constexpr int MAX_PACKED_RES = 256;
+
 struct MotionArgs {
   const float* weights;
+  const f4* packed;  // optional packed copy of the bone channels (NULL: gather from weights)
   int32_t res, n_bones;
   float mmin[3], mscale[3];  // q = (y - mmin) * mscale, in voxel units
 };

@@ -76,14 +76,44 @@ __device__ __forceinline__ Tri bone_cell(const MotionArgs& m, const float y[3]) 
                   fminf(fmaxf((y[2] - m.mmin[2]) * m.mscale[2], -2.f), hi));
 }
 
-// Bones are processed BG at a time so that BG x 8 gathers are in flight
-// before the first one is consumed.
+// The 8 corner weights of bone b's trilinear cell, corner c at
+// (x0 + (c&1), y0 + (c>>1 & 1), z0 + (c>>2)).  Plain volume: eight 4-byte
+// gathers.  Packed copy (float4 of the 2x2 x-y corners at [b][z][y0+1][x0+1]):
+// two 16-byte loads, planes z0 and z0+1.  Corners outside the volume read 0
+// through out-of-range offsets in both layouts, so the values are identical.
+__device__ __forceinline__ void bone_corners(const MotionArgs& m, int b, const Tri& t, float v[8]) {
+  const int R = m.res;
+  if (m.packed) {
+    const uint32_t R1 = (uint32_t)R + 1u, zstride = R1 * R1 * 16u;
+    const uint32_t cx = (uint32_t)(t.i0[0] + 1), cy = (uint32_t)(t.i0[1] + 1), z = (uint32_t)t.i0[2];
+    const bool okxy = cx <= (uint32_t)R && cy <= (uint32_t)R;
+    const uint32_t o = ((z * R1 + cy) * R1 + cx) * 16u;  // modulo 2^32; only used when z or z+1 is in range
+    const uint32_t o0 = (okxy && z < (uint32_t)R) ? o : OOB_OFFSET;
+    const uint32_t o1 = (okxy && z + 1u < (uint32_t)R) ? o + zstride : OOB_OFFSET;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.packed + (size_t)b * R * R1 * R1, (uint32_t)R * zstride);
+    const f4 lo = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o0, 0, 0));
+    const f4 hi = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o1, 0, 0));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { v[c] = lo[c]; v[4 + c] = hi[c]; }
+  } else {
+    const uint32_t plane = (uint32_t)(R * R * R);
+    uint32_t off[8];
+    tri_offsets(t, R, off);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.weights + (size_t)b * plane, plane * 4u);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off[c], 0, 0));
+  }
+}
+
+// Bones are processed BG at a time so that all their corner loads are in
+// flight before the first one is consumed.
 constexpr int BG = 4;
 
-__device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G)[12], const float x[3],
-                                            float xs[3], float& L) {
-  const int R = m.res;
-  const uint32_t plane = (uint32_t)(R * R * R);
+// The layout test is a uniform branch per bone rather than two copies of
+// this loop: with two loops the compiler copied the kernel's argument block
+// to scratch memory.
+__device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G)[12], const float x[3], float xs[3],
+                                            float& L) {
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, sum = 0.f;
 #pragma unroll 1
   for (int b0 = 0; b0 < m.n_bones; b0 += BG) {
@@ -94,11 +124,7 @@ __device__ __forceinline__ void warp_sample(const MotionArgs& m, const float (*G
       const int b = b0 + u < m.n_bones ? b0 + u : m.n_bones - 1;
       bone_apply(G[b], x, y[u]);
       t[u] = bone_cell(m, y[u]);
-      uint32_t off[8];
-      tri_offsets(t[u], R, off);
-      const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.weights + (size_t)b * plane, plane * 4u);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) v[u][c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off[c], 0, 0));
+      bone_corners(m, b, t[u], v[u]);
     }
 #pragma unroll
     for (int u = 0; u < BG; ++u) {
@@ -177,7 +203,7 @@ __device__ __forceinline__ f2 trilerp2(const f2 v[8], const float f[3]) {
 
 // Levels are encoded LG at a time so that LG x 8 row gathers are in flight
 // before the first one is consumed.  Calls store(l, feature pair).
-constexpr int LG = 2;
+constexpr int LG = 4;
 
 template <typename TableT, typename Store>
 __device__ __forceinline__ void encode_all(const FieldArgs& f, const float u[3], bool live, Store store) {

@@ -26,5 +26,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float eps, int step, void* lowp, mnr_dtype dt, hipStream_t st);
 hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st);
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
+// Packed copy of the bone channels of a blend-weight volume (2x2 x-y corners
+// per float4; layout in mnr_motion_packed_bytes' declaration).
+hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hipStream_t st);
 
 }  // namespace mnr

@@ -5,7 +5,8 @@
 // admits queued requests (free slot + memory budget), and launches the next
 // tick whenever fewer than two are in flight.  A tick renders up to
 // tiles_per_tick 16x16 tiles taken from admitted requests oldest first; a
-// request completes with the tick that renders its last tile.  Ticks are
+// request completes with the tick that renders its last tile (tick
+// composition: see launch_locked).  Ticks are
 // replayed from two captured hipGraphs (tile-table upload + tick kernel),
 // alternating between two tile tables so the host can fill one while the
 // GPU reads the other.
@@ -60,6 +61,7 @@ static uint64_t field_bytes(const mnr_field& f, const mnr_motion& m) {
   uint64_t b = (uint64_t)f.n_levels * ((uint64_t)1 << f.log2_T) * f.n_feat * el;
   for (int k = 0; k < f.n_layers; ++k) b += (uint64_t)f.width[k] * f.width[k + 1] * wl;
   b += (uint64_t)(m.n_bones + 1) * m.res * m.res * m.res * 4;
+  if (m.packed) b += mnr_motion_packed_bytes(m.res, m.n_bones);
   return b;
 }
 
@@ -158,16 +160,33 @@ bool mnr_server::launch_locked() {
   WorkTable* w = h_wt[buf];
   int n = 0;
   const int64_t tn = now_ns();
+  // Tick composition: the oldest unfinished request first takes up to a
+  // quarter of the tile budget (no request starves), then the rest of the
+  // budget goes to requests with the fewest remaining tiles, so small
+  // frames overtake large ones instead of queueing behind them.
+  std::vector<Request*> cand;
   for (uint64_t id : active) {
-    if (n >= tick_cap) break;
     Request& r = reqs[id];
-    if (r.next_tile >= r.n_tiles) continue;  // all tiles launched, awaiting completion
+    if (r.next_tile < r.n_tiles) cand.push_back(&r);  // else: launched, awaiting completion
+  }
+  auto take_from = [&](Request& r, int budget) {
+    const int take = std::min(r.n_tiles - r.next_tile, budget);
+    if (take <= 0) return;
     if (r.next_tile == 0) r.t[2] = tn;
-    const int take = std::min(r.n_tiles - r.next_tile, tick_cap - n);
     for (int k = 0; k < take; ++k) w->items[n + k] = WorkItem{r.slot, r.next_tile + k};
     n += take;
     r.next_tile += take;
-    if (r.next_tile == r.n_tiles) t.finishing.push_back(id);
+    if (r.next_tile == r.n_tiles) t.finishing.push_back(r.ticket);
+  };
+  if (!cand.empty()) {
+    take_from(*cand.front(), std::max(tick_cap / 4, 1));
+    std::stable_sort(cand.begin(), cand.end(), [](const Request* a, const Request* b) {
+      return a->n_tiles - a->next_tile < b->n_tiles - b->next_tile;
+    });
+    for (Request* r : cand) {
+      if (n >= tick_cap) break;
+      take_from(*r, tick_cap - n);
+    }
   }
   if (n == 0) return false;
   w->counter = 0;

@@ -2,7 +2,8 @@
 // the squared-error loss (MSE term of Eq. 14), the per-voxel softmax that
 // turns free logits into canonical blend weights W^c (Sec. 4.2) and its
 // adjoint, Adam (beta1 = 0.9, beta2 = 0.99 in the paper), precision
-// conversion of parameter copies, and a kernel fill.
+// conversion of parameter copies, the packed copy of the blend-weight
+// volume read by the renderer, and a kernel fill.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -117,6 +118,25 @@ hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, 
 __global__ void zero_kernel(uint32_t* __restrict__ d, int64_t n_words) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
     d[i] = 0u;
+}
+
+// One float4 per (bone, z, y+1, x+1): the blend weights of the cell's four
+// x-y corners in plane z, zero for corners outside the volume.
+__global__ void pack_motion_kernel(const float* __restrict__ w, f4* __restrict__ packed, int R, int64_t n) {
+  const int64_t R1 = R + 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int x0 = (int)(e % R1) - 1, y0 = (int)((e / R1) % R1) - 1;
+    const int64_t zb = e / (R1 * R1);  // bone * R + z
+    const float* plane = w + zb * R * R;  // plane z of bone b: channels are contiguous R^3 blocks
+    auto at = [&](int x, int y) { return ((unsigned)x < (unsigned)R && (unsigned)y < (unsigned)R) ? plane[y * R + x] : 0.f; };
+    packed[e] = f4{at(x0, y0), at(x0 + 1, y0), at(x0, y0 + 1), at(x0 + 1, y0 + 1)};
+  }
+}
+
+hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hipStream_t st) {
+  const int64_t n = (int64_t)n_bones * R * (R + 1) * (R + 1);
+  hipLaunchKernelGGL(pack_motion_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, w, packed, R, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {

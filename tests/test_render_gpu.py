@@ -139,3 +139,40 @@ def test_static_and_dynamic_scheduling_agree_bitwise():
         torch.cuda.synchronize()
         assert torch.equal(dyn, sta)
         assert torch.equal(dyn_l, sta_l)
+
+
+def _packed_reference(weights, n_bones):
+    # Layout of the packed blend-weight copy, written out from its definition:
+    # [bone][z][y+1][x+1] -> (W(x,y,z), W(x+1,y,z), W(x,y+1,z), W(x+1,y+1,z)),
+    # zero outside the volume, x, y in [-1, R-1].
+    R = weights.shape[-1]
+    pad = np.zeros((n_bones, R, R + 2, R + 2), np.float32)
+    pad[:, :, 1:R + 1, 1:R + 1] = weights[:n_bones]
+    out = np.zeros((n_bones, R, R + 1, R + 1, 4), np.float32)
+    for c, (dx, dy) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1)]):
+        out[..., c] = pad[:, :, dy:dy + R + 1, dx:dx + R + 1]
+    return out
+
+
+def test_packed_weight_copy_layout_and_bitwise_render():
+    # The packed copy holds exactly the plain volume's values, and rendering
+    # from it changes no pixel (frame kernel and ray-list kernel).
+    import paper_2306_16541_amd as m
+    for sc, tdt, mdt in [(scenes.scene_small(H=40, W=24, spp=64), 0, 0),
+                         (scenes.scene_body(H=48, W=64, spp=128), 0, 0),
+                         (scenes.scene_body(H=48, W=64, spp=96), 1, 2)]:
+        packed, _ = m.upload_scene(sc, "cuda", tdt, mdt, packed=True)
+        plain, _ = m.upload_scene(sc, "cuda", tdt, mdt, packed=False)
+        nb = sc.parents.shape[0]
+        R = sc.res
+        got = packed.packed.view(nb, R, R + 1, R + 1, 4).cpu().numpy()
+        want = _packed_reference(packed.weights.view(nb + 1, R, R, R).cpu().numpy(), nb)
+        assert np.array_equal(got, want)
+        pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+        cam = m.make_camera(sc.cam)
+        pid = torch.as_tensor(np.random.default_rng(3).integers(0, sc.H * sc.W, 777).astype(np.int32), device="cuda")
+        for ids in (None, pid):
+            a = m.render(packed, pose, cam, sc.H, sc.W, sc.spp, m.make_opts(), ids).clone()
+            b = m.render(plain, pose, cam, sc.H, sc.W, sc.spp, m.make_opts(), ids).clone()
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)

@@ -81,7 +81,8 @@ def test_memory_admission_and_rejections():
     import math
     import paper_2306_16541_amd as m
     sc, fld = _user(16541 + 60)
-    resident = (16 * (1 << 16) * 2 * 2 + sum(w.size for w in sc.mlp) * 2 + 25 * 32 ** 3 * 4)
+    resident = (16 * (1 << 16) * 2 * 2 + sum(w.size for w in sc.mlp) * 2 + 25 * 32 ** 3 * 4
+                + 24 * 32 * 33 * 33 * 16)   # + the packed copy of the bone channels
     frame = 64 * 64 * 16
     srv = m.Server(mem_budget=resident + frame + 100, max_slots=4)      # room for one 64x64 output
     srv.add_user(0, fld)
