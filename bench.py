@@ -81,7 +81,9 @@ def timed_launches(fn, steps, warmup):
         b.record(st)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    return wall, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ks = [a.elapsed_time(b) for a, b in evs]
+    timed_launches.last_median = float(np.median(ks))
+    return wall, float(np.mean(ks))
 
 
 def psnr(a, b):
@@ -101,7 +103,8 @@ def render_bench(sc, table_dt, mlp_dt, steps, warmup):
     n_eval = int(cnt.item())
     wall, kern = timed_launches(lambda: m.render(fld, pose, cam, sc.H, sc.W, sc.spp, opts, out=out), steps, warmup)
     img = out.cpu().numpy()
-    return {"wall_ms": wall, "kernel_ms": kern, "n_eval": n_eval, "img": img}
+    return {"wall_ms": wall, "kernel_ms": kern, "kernel_ms_median": timed_launches.last_median, "n_eval": n_eval,
+            "img": img}
 
 
 def roofline(res, sc, enc_key, mlp_key, widths):
@@ -147,6 +150,50 @@ def oracle_sample(sc, img_fp32, img_mixed, budget_s):
     return out, par
 
 
+def oracle_one_thread(sc, budget_s):
+    """The same oracle restricted to one CPU thread, on a short sample."""
+    import oracle
+    n0 = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        order = np.random.default_rng(1).permutation(sc.H * sc.W)
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s and done < order.size:
+            oracle.render_image(sc, pixel_ids=order[done:done + 256])
+            done += 256
+        el = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(n0)
+    return {"value": done * sc.spp / el / 1e6, "unit": "Msamples/s (nominal)", "cores": 1,
+            "sample": f"{done} random pixels, {el:.1f} s"}
+
+
+def ceilings(reps=5):
+    """Measured machine ceilings: random small gathers from tables of the
+    grid's sizes (uniform, and within a 4 KiB window per wave as neighbouring
+    rays do) and dense MFMA loops, each the median of `reps` launches."""
+    out = {}
+    n_lanes, per_lane = 1 << 20, 64
+    for rb, mib, name in ((4, 32, "fp16_table_rows"), (8, 64, "fp32_table_rows"), (16, 104, "packed_weight_cells")):
+        table = torch.zeros((mib << 20) // 4, dtype=torch.float32, device="cuda")
+        res = {}
+        for win, key in ((0, "uniform"), (4096, "window_4KiB")):
+            buf = torch.empty(n_lanes, dtype=torch.float32, device="cuda")
+            timed_launches(lambda: m.probe_gather(table, rb, win, per_lane, n_lanes, out=buf), reps, 2)
+            ms = timed_launches.last_median
+            g = n_lanes * per_lane / (ms * 1e-3)
+            res[key] = {"Ggathers_per_s": g / 1e9, "useful_GB_per_s": g * rb / 1e9}
+        out[f"gather_{rb}B_{name}_{mib}MiB"] = res
+        del table
+    n_blocks, iters = 2048, 4000
+    buf = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda")
+    for dt, name, flop in ((m.F32, "mfma_f32_16x16x4", 2048), (m.BF16, "mfma_bf16_16x16x32", 16384)):
+        timed_launches(lambda: m.probe_mfma(dt, iters, n_blocks, out=buf), reps, 2)
+        ms = timed_launches.last_median
+        out[name] = {"TFLOP_per_s": n_blocks * 4 * iters * 4 * flop / (ms * 1e-3) / 1e12}
+    return out
+
+
 def train_bench(steps, warmup):
     sc = scenes.scene_body()
     dev = "cuda"
@@ -162,12 +209,38 @@ def train_bench(steps, warmup):
         k[0] += 1
         tr.step(pose, cam, sc.H, sc.W, sc.spp, pid, tgt, seed=k[0])
     wall, _ = timed_launches(step, steps, warmup)
-    return {"ms_per_step": wall, "steps_per_s": 1e3 / wall, "rays": 8192, "spp": sc.spp,
-            "Msamples_per_s": 8192 * sc.spp / wall / 1e3, "loss": tr.loss(),
-            "dtype": "fp32 table/adam, bf16 MLP"}
+    res = {"ms_per_step": wall, "steps_per_s": 1e3 / wall, "rays": 8192, "spp": sc.spp,
+           "Msamples_per_s": 8192 * sc.spp / wall / 1e3, "loss": tr.loss(),
+           "dtype": "fp32 table/adam, bf16 MLP"}
+    # Time split: the same kernels called one at a time (forward with saved
+    # state, adjoint into zeroed gradients); the rest of a step is the loss,
+    # softmax adjoint/forward, Adam and the gradient fills.
+    opts = m.make_opts(stratified=True, seed=1)
+    rgba, g_rgba = tr.buf["rgba"], tr.buf["grad_rgba"]
+    tch = tr.buf["t_chunks"][: 8192 * m.saved_size(sc.spp)].view(8192, -1)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    m.render(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, out=rgba, counter=cnt, t_chunks=tch)
+    torch.cuda.synchronize()
+    n_eval = int(cnt.item())
+    _, fwd_ms = timed_launches(lambda: m.render(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, out=rgba,
+                                                t_chunks=tch), steps, 1)
+    m.mse_loss(rgba, tgt, g_rgba)
+    b = tr.buf
+
+    def bwd():
+        m.render_backward(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, g_rgba, b["table_grad"],
+                          b["w_grad"], b["weights_grad"])
+    for t in [b["table_grad"], b["weights_grad"]] + b["w_grad"]:
+        t.zero_()
+    _, bwd_ms = timed_launches(bwd, steps, 1)
+    atomics = n_eval * (16 * 8 * 2 + 24 * 8)
+    res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
+    res["evaluated_samples"] = n_eval
+    res["adjoint_atomics_per_s_upper"] = atomics / (bwd_ms * 1e-3)
+    return res
 
 
-def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=0.5, window_s=(4.0, 4.0, 2.0, 2.0)):
+def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 2.0, 2.0)):
     """Poisson arrivals from U users at rate_hz each; resolutions uniform over
     {256^2, 512^2, 1024^2}; per-user fields resident (FP16 table, BF16 MLP);
     per-frame pose ~ N(0, 0.3).  Latency = completion - arrival."""
@@ -242,6 +315,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
     ap.add_argument("--mixed-only", action="store_true", help="the mixed-precision 512x512 frame only (profiling)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--train-only", action="store_true", help="the 8192-ray training step only (profiling)")
     ap.add_argument("--digest", action="store_true", help="print the kernel-source digest and exit")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--copy-calib", action="store_true",
@@ -262,6 +336,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes_per_launch": src.numel() * 4, "launches": args.steps}))
+        return
+    if args.train_only:
+        print(json.dumps({"train_step_8192x128": train_bench(args.steps, args.warmup)}))
         return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench()}))
@@ -289,6 +366,7 @@ def main():
                    "H": sc.H, "W": sc.W, "spp": sc.spp},
         "frames_per_s": 1e3 / fp32["wall_ms"],
         "kernel_ms": fp32["kernel_ms"],
+        "kernel_ms_median": fp32["kernel_ms_median"],
         "evaluated_Msamples_per_s": fp32["n_eval"] / (fp32["kernel_ms"] * 1e-3) / 1e6,
         "evaluated_samples": fp32["n_eval"],
         "roofline": roof,
@@ -310,10 +388,13 @@ def main():
             "evaluated_Msamples_per_s": big["n_eval"] / (big["kernel_ms"] * 1e-3) / 1e6}
         del big
         line["train_step_8192x128"] = train_bench(max(3, args.steps // 2), 2)
+        line["ceilings"] = ceilings()
         if not args.no_serve:
             line["serving"] = serve_bench()
     cpu, par = oracle_sample(sc, fp32["img"], None if mixed is None else mixed["img"], args.cpu_budget)
     line["cpu_baseline"] = cpu
+    if not args.quick:
+        line["cpu_baseline_1thread"] = oracle_one_thread(sc, min(5.0, args.cpu_budget))
     line["parity_vs_oracle"] = par
     print(json.dumps(line))
 

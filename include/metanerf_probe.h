@@ -1,0 +1,43 @@
+/*
+ * metanerf_probe.h -- machine-ceiling probes.
+ *
+ * Not part of the rendering path: two micro-kernels that measure what the
+ * GPU sustains for the two kinds of work the renderer is made of, so that
+ * the renderer's rates can be read against measured ceilings as well as
+ * the published peaks:
+ *   - small random gathers from a table of the grid encoding's size
+ *     (the warp and encoding steps, Sec. 4.2 Eq. 9 and Sec. 4.4 Eq. 13);
+ *   - a dense MFMA loop in the MLP's arithmetic types (the MLP of Eq. 13).
+ * Both run on the caller's stream; time them with events around the call.
+ */
+#ifndef METANERF_PROBE_H
+#define METANERF_PROBE_H
+
+#include "metanerf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Each of n_lanes lanes (a multiple of 256) reads gathers_per_lane (a
+ * multiple of 8, >= 8) rows of row_bytes (4, 8 or 16) from the dev table of
+ * table_bytes (row_bytes .. 2^31-1 bytes), eight loads in flight at a time,
+ * and writes the float sum of what it read to out[lane] (dev float
+ * [n_lanes]).  window_bytes = 0: rows uniform over the table.  Otherwise
+ * the 64 lanes of a wave draw their rows from one window of that many bytes
+ * (a fresh random window per gather), the access pattern of neighbouring
+ * rays.  Row choice is a fixed hash of (seed, lane, k).  Gathers issued =
+ * n_lanes * gathers_per_lane. */
+mnr_status mnr_probe_gather(const void* table, uint64_t table_bytes, int32_t row_bytes, uint32_t window_bytes,
+                            int32_t gathers_per_lane, int32_t n_lanes, uint32_t seed, float* out, void* stream);
+
+/* n_blocks blocks of 4 waves each run `iters` iterations of 4 independent
+ * MFMA chains: F32 -> v_mfma_f32_16x16x4f32 (2048 FLOP each), BF16 ->
+ * v_mfma_f32_16x16x32_bf16 (16384 FLOP each).  FLOP issued = n_blocks * 4
+ * waves * iters * 4 * (FLOP per MFMA).  out: dev float [n_blocks * 256]. */
+mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_blocks, float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* METANERF_PROBE_H */

@@ -104,11 +104,14 @@ _sig("mnr_convert", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_vo
 _sig("mnr_zero", C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p])
 _sig("mnr_motion_packed_bytes", C.c_uint64, [C.c_int32, C.c_int32])
 _sig("mnr_motion_pack", C.c_int, [C.POINTER(Motion), C.c_void_p])
+_sig("mnr_probe_gather", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_uint32,
+                                   C.c_void_p, C.c_void_p])
+_sig("mnr_probe_mfma", C.c_int, [C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
-            "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack"]
+            "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_probe_gather", "mnr_probe_mfma"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -228,6 +231,22 @@ def softmax_fwd(logits: torch.Tensor, out: Optional[torch.Tensor] = None) -> tor
 def softmax_bwd(weights, grad_weights, grad_logits) -> None:
     check(lib.mnr_softmax_bwd(_ptr(weights), _ptr(grad_weights), _ptr(grad_logits), int(weights.shape[0]),
                               int(weights[0].numel()), _stream()), "softmax_bwd")
+
+
+def probe_gather(table: torch.Tensor, row_bytes: int, window_bytes: int, gathers_per_lane: int, n_lanes: int,
+                 seed: int = 1, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Random-gather ceiling probe (include/metanerf_probe.h)."""
+    out = torch.empty(n_lanes, dtype=torch.float32, device=table.device) if out is None else out
+    check(lib.mnr_probe_gather(_ptr(table), table.numel() * table.element_size(), row_bytes, window_bytes,
+                               gathers_per_lane, n_lanes, seed, _ptr(out), _stream()), "probe_gather")
+    return out
+
+
+def probe_mfma(dtype: int, iters: int, n_blocks: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Dense MFMA-loop ceiling probe (include/metanerf_probe.h)."""
+    out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda") if out is None else out
+    check(lib.mnr_probe_mfma(dtype, iters, n_blocks, _ptr(out), _stream()), "probe_mfma")
+    return out
 
 
 def convert(src: torch.Tensor, dtype: int) -> torch.Tensor:

@@ -172,19 +172,20 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Dynamic work pulling for one wave.  Work units come in groups of GROUP
-// consecutive units; group g belongs to the queue of XCD g % 8, so each
-// XCD works through its own spatially coherent groups first and then
-// steals from the others.  q starts at the wave's XCD (blockIdx.x % 8).
-// Returns the next unit, or -1 once every queue is exhausted.
-template <int GROUP>
+// Dynamic work pulling for one wave.  The units are split into 8 contiguous
+// ranges, one per XCD queue; units close in index are close in the image,
+// so each XCD's L2 serves a compact band of the frame (and the part of the
+// body seen there).  A wave starts on its own XCD's range (q = blockIdx.x %
+// 8), then steals from the next ones.  Returns the next unit, or -1 once
+// every range is exhausted.
 __device__ __forceinline__ int pull_unit(int32_t* queues, int n_units, int& q, int& tried) {
+  const int per = (n_units + 7) >> 3;
   for (;;) {
     int local = 0;
     if (__lane_id() == 0) local = atomicAdd(queues + q, 1);
     local = __builtin_amdgcn_readfirstlane(local);
-    const int unit = (q + 8 * (local / GROUP)) * GROUP + local % GROUP;
-    if (unit < n_units) return unit;  // a queue's units only grow, so >= n_units means exhausted
+    const int unit = q * per + local;
+    if (local < per && unit < n_units) return unit;
     if (++tried >= 8) return -1;
     q = (q + 1) & 7;
   }

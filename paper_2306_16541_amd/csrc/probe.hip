@@ -1,0 +1,125 @@
+// Machine-ceiling probes: a random-gather kernel and a dense MFMA loop
+// (declared in metanerf_probe.h).  They share nothing with the renderer but
+// the buffer-resource helper.
+#include <hip/hip_runtime.h>
+
+#include "../../include/metanerf_probe.h"
+#include "field_device.h"  // make_rsrc
+#include "host_common.h"
+
+namespace mnr {
+
+__device__ __forceinline__ uint32_t mix32(uint32_t a, uint32_t b, uint32_t seed) {
+  uint32_t h = a * 0x9E3779B9u + b * 0x85EBCA6Bu + seed;
+  h ^= h >> 16; h *= 0x7FEB352Du;
+  h ^= h >> 15; h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  return h;
+}
+
+template <int RB>
+__device__ __forceinline__ float load_sum(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (RB == 4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  } else if constexpr (RB == 8) {
+    const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    return v[0] + v[1];
+  } else {
+    const f4 v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    return (v[0] + v[1]) + (v[2] + v[3]);
+  }
+}
+
+template <int RB>
+__global__ void __launch_bounds__(256) probe_gather_kernel(const void* table, uint32_t n_rows, uint32_t win_rows,
+                                                           int G, uint32_t seed, float* __restrict__ out) {
+  const uint32_t gid = blockIdx.x * 256u + threadIdx.x, wave = gid >> 6;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(table, n_rows * (uint32_t)RB);
+  const uint32_t span = win_rows ? n_rows - win_rows + 1u : 0u;
+  float acc = 0.f;
+  for (int k0 = 0; k0 < G; k0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t k = (uint32_t)(k0 + j);
+      uint32_t row;
+      if (win_rows) {
+        const uint32_t base = __umulhi(mix32(wave, k, seed ^ 0xA511E9B3u), span);
+        row = base + __umulhi(mix32(gid, k, seed), win_rows);
+      } else {
+        row = __umulhi(mix32(gid, k, seed), n_rows);
+      }
+      v[j] = load_sum<RB>(rs, row * (uint32_t)RB);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  out[gid] = acc;
+}
+
+template <bool BF16>
+__global__ void __launch_bounds__(256) probe_mfma_kernel(int iters, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = c0, c2 = c0, c3 = c0;
+  if constexpr (BF16) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      a[i] = (__bf16)(1e-3f * (float)(lane + i));
+      b[i] = (__bf16)(1e-3f * (float)(lane - i));
+    }
+    for (int it = 0; it < iters; ++it) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, a, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, b, c3, 0, 0, 0);
+    }
+  } else {
+    const float a = 1e-3f * (float)lane, b = 1e-3f * (float)(63 - lane);
+    for (int it = 0; it < iters; ++it) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, a, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(b, b, c3, 0, 0, 0);
+    }
+  }
+  out[blockIdx.x * 256u + threadIdx.x] = (c0[0] + c1[1]) + (c2[2] + c3[3]);
+}
+
+}  // namespace mnr
+
+using namespace mnr;
+
+extern "C" mnr_status mnr_probe_gather(const void* table, uint64_t table_bytes, int32_t row_bytes,
+                                       uint32_t window_bytes, int32_t gathers_per_lane, int32_t n_lanes,
+                                       uint32_t seed, float* out, void* stream) {
+  clear_error();
+  if (!table || !out) return fail(MNR_E_INVALID, "probe_gather: null pointer");
+  if (row_bytes != 4 && row_bytes != 8 && row_bytes != 16) return fail(MNR_E_SHAPE, "probe_gather: row_bytes 4, 8 or 16");
+  if (table_bytes < (uint64_t)row_bytes || table_bytes > 0x7FFFFFFFull)
+    return fail(MNR_E_SHAPE, "probe_gather: table_bytes out of range");
+  if (gathers_per_lane < 8 || gathers_per_lane % 8 || n_lanes < 256 || n_lanes % 256)
+    return fail(MNR_E_SHAPE, "probe_gather: gathers_per_lane must be a multiple of 8, n_lanes of 256");
+  const uint32_t n_rows = (uint32_t)(table_bytes / (uint64_t)row_bytes);
+  const uint32_t win_rows = window_bytes ? window_bytes / (uint32_t)row_bytes : 0u;
+  if (window_bytes && (win_rows < 1 || win_rows > n_rows)) return fail(MNR_E_SHAPE, "probe_gather: bad window");
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 grid(n_lanes / 256), block(256);
+  if (row_bytes == 4) hipLaunchKernelGGL(probe_gather_kernel<4>, grid, block, 0, st, table, n_rows, win_rows, gathers_per_lane, seed, out);
+  else if (row_bytes == 8) hipLaunchKernelGGL(probe_gather_kernel<8>, grid, block, 0, st, table, n_rows, win_rows, gathers_per_lane, seed, out);
+  else hipLaunchKernelGGL(probe_gather_kernel<16>, grid, block, 0, st, table, n_rows, win_rows, gathers_per_lane, seed, out);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_gather launch: %s", hipGetErrorString(e));
+}
+
+extern "C" mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_blocks, float* out, void* stream) {
+  clear_error();
+  if (!out) return fail(MNR_E_INVALID, "probe_mfma: null pointer");
+  if (dtype != MNR_F32 && dtype != MNR_BF16) return fail(MNR_E_DTYPE, "probe_mfma: F32 or BF16");
+  if (iters < 1 || n_blocks < 1) return fail(MNR_E_SHAPE, "probe_mfma: iters and n_blocks must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == MNR_BF16) hipLaunchKernelGGL(probe_mfma_kernel<true>, dim3(n_blocks), dim3(256), 0, st, iters, out);
+  else hipLaunchKernelGGL(probe_mfma_kernel<false>, dim3(n_blocks), dim3(256), 0, st, iters, out);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_mfma launch: %s", hipGetErrorString(e));
+}

@@ -15,9 +15,10 @@
 // recurrence and each ray stops as soon as its transmittance is below
 // ert_tau.  A block's four waves cover one 16x16 tile.
 // Both use a persistent grid: blocks stage the MLP weights into LDS once
-// and loop over work; 16x16-pixel tiles (or 256-ray groups) are dealt
-// round-robin to the eight XCDs (block b runs on XCD b % 8), so each XCD's
-// L2 sees spatially coherent gathers.
+// and loop over work.  With a workspace, waves pull work from per-XCD
+// queues over contiguous bands of the frame (block b runs on XCD b % 8),
+// so each XCD's L2 sees spatially coherent gathers; without one, 16x16
+// tiles (or 256-ray groups) are dealt round-robin to the XCDs.
 #include "field_device.h"
 #include "kernels.h"
 
@@ -67,8 +68,8 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
   int q = blockIdx.x & 7, tried = 0;
   for (int it = 0;; ++it) {
     int slot;
-    if (a.queues) {  // dynamic: pull rays (groups of 256) from per-XCD queues
-      slot = pull_unit<256>(a.queues, n_slots, q, tried);
+    if (a.queues) {  // dynamic: pull rays from per-XCD queues
+      slot = pull_unit(a.queues, n_slots, q, tried);
       if (slot < 0) break;
     } else {
       if (it >= iters) break;
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
 
 
 // NW / 4 consecutive 16x16 tiles per block iteration (four 8x8 packets
-// each); tile groups are dealt round-robin to the XCDs.
+// each); without a workspace, tile groups are dealt round-robin to the XCDs.
 template <typename TableT, int P, int NHH, int NW>
 __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs a, int n_tiles) {
   using S = MlpShape<P>;
@@ -143,7 +144,7 @@ __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs
   if (a.queues) {  // dynamic: each wave pulls 8x8 packets (4 per tile) from per-XCD queues
     int q = blockIdx.x & 7, tried = 0;
     for (;;) {
-      const int unit = pull_unit<4>(a.queues, n_tiles * 4, q, tried);
+      const int unit = pull_unit(a.queues, n_tiles * 4, q, tried);
       if (unit < 0) break;
       render_tile_packet<TableT, P, NHH>(a, unit >> 2, unit & 3, lane, wl, feat);
     }

@@ -15,6 +15,7 @@
 //      fragments, dW = dY X^T accumulated per block in LDS float atomics;
 //   3. encoding adjoint: scatter-add into the table gradient and the
 //      encoding's spatial derivative back to the skinned point x_skel;
+//      consecutive samples in the same cell are summed in the wave first;
 //   4. skinning adjoint (Eq. 7, 9): dx_skel/dw_i = (y_i - x_skel)/L and the
 //      likelihood term dalpha'/dL = alpha [L < 1], scattered through the
 //      trilinear weights into dL/dW^c.
@@ -22,6 +23,59 @@
 #include "kernels.h"
 
 namespace mnr {
+
+// Gradient scatter with fewer atomics.  The 64 lanes of a wave are 64
+// consecutive samples of one ray, so at coarse grid levels (and in the
+// blend-weight volume) neighbouring lanes often fall in the same cell and
+// would add to the same addresses.  Such runs are summed across the wave
+// first and only the first lane of a run issues the atomics.  Global float
+// atomics are executed at the memory side on this GPU (its eight L2s are
+// not coherent with each other), so their count bounds the adjoint.
+struct CellRuns {
+  int seg;    // run index of the lane (number of run starts at lanes <= lane)
+  int steps;  // suffix-scan steps needed to sum the longest run
+  bool head;  // first lane of its run
+};
+
+__device__ __forceinline__ CellRuns cell_runs(bool live, int x, int y, int z) {
+  const int lane = lane_id();
+  const int px = __shfl_up(x, 1, WAVE), py = __shfl_up(y, 1, WAVE), pz = __shfl_up(z, 1, WAVE);
+  const int plive = __shfl_up(live ? 1 : 0, 1, WAVE);
+  CellRuns r;
+  r.head = !live || lane == 0 || !plive || px != x || py != y || pz != z;
+  const uint64_t heads = __ballot(r.head);
+  r.seg = (int)__popcll(heads & (~0ull >> (63 - lane)));
+  // Longest run: a run of length >= 2^j + 1 needs 2^j non-start lanes in a
+  // row after its start; count the doublings (bits past lane 63 are starts).
+  uint64_t z0 = ~heads;
+  int steps = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    if (z0 == 0) break;
+    ++steps;
+    z0 &= z0 >> (1 << j);
+  }
+  r.steps = steps;
+  return r;
+}
+
+// In-run suffix sums: afterwards the first lane of every run holds the sum
+// of the run's values (segmented Hillis-Steele scan over the wave).
+template <int NV>
+__device__ __forceinline__ void run_sums(const CellRuns& r, float (&v)[NV]) {
+  const int lane = lane_id();
+#pragma unroll 1
+  for (int j = 0; j < r.steps; ++j) {
+    const int d = 1 << j;
+    const int seg_d = __shfl_down(r.seg, d, WAVE);
+    const bool same = lane + d < WAVE && seg_d == r.seg;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const float o = __shfl_down(v[k], d, WAVE);
+      v[k] += same ? o : 0.f;
+    }
+  }
+}
 
 template <int P>
 struct BwdShape {
@@ -210,8 +264,8 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   int q = blockIdx.x & 7, tried = 0;
   for (int it = 0;; ++it) {
     int slot;
-    if (a.queues) {  // dynamic: pull rays (groups of 256) from per-XCD queues
-      slot = pull_unit<256>(a.queues, n_slots, q, tried);
+    if (a.queues) {  // dynamic: pull rays from per-XCD queues
+      slot = pull_unit(a.queues, n_slots, q, tried);
       if (slot < 0) break;
     } else {
       if (it >= iters) break;
@@ -303,29 +357,34 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       wave_sync_lds();
 
       // ---- 3. encoding adjoint ------------------------------------------------------
-      if (st.live) {
-        float u[3], g_u[3] = {0.f, 0.f, 0.f};
-        unit_coords(a.f, st.xs, u);
-        const float* df = dfeat + lane * IN_FEAT;
+      // All lanes take part (the run detection shuffles across the wave);
+      // lanes that are not live contribute zeros and issue nothing.
+      const bool live = st.live;
+      float u[3], g_u[3] = {0.f, 0.f, 0.f};
+      unit_coords(a.f, st.xs, u);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) u[q] = live ? u[q] : 0.f;
+      const float* df = dfeat + lane * IN_FEAT;
 #pragma unroll 1
-        for (int l = 0; l < a.f.n_levels; ++l) {
-          const int N = a.f.level_res[l];
-          const bool dense = (a.f.dense_mask >> l) & 1u;
-          const GridCell gc = grid_cell(u, N);
-          const float d0 = df[2 * l], d1 = df[2 * l + 1];
+      for (int l = 0; l < a.f.n_levels; ++l) {
+        const int N = a.f.level_res[l];
+        const bool dense = (a.f.dense_mask >> l) & 1u;
+        const GridCell gc = grid_cell(u, N);
+        const float d0 = live ? df[2 * l] : 0.f, d1 = live ? df[2 * l + 1] : 0.f;
+        float wk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          wk[k] = ((k & 1) ? gc.f[0] : 1.f - gc.f[0]) * ((k & 2) ? gc.f[1] : 1.f - gc.f[1]) *
+                  ((k & 4) ? gc.f[2] : 1.f - gc.f[2]);
+        if (live) {  // spatial derivative of the encoding (reads only)
           const __amdgpu_buffer_rsrc_t lrs = level_rsrc<TableT>(a.f, l);
-          float* gt = a.grad_table + (size_t)l * T * 2;
           float gp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            const uint32_t row = grid_row(gc, N, dense, tmask, k);
+            const f2 v = load_row<TableT>(lrs, grid_row(gc, N, dense, tmask, k));
             const float wx = (k & 1) ? gc.f[0] : 1.f - gc.f[0];
             const float wy = (k & 2) ? gc.f[1] : 1.f - gc.f[1];
             const float wz = (k & 4) ? gc.f[2] : 1.f - gc.f[2];
-            const float wk = wx * wy * wz;
-            unsafeAtomicAdd(gt + 2 * (size_t)row, wk * d0);
-            unsafeAtomicAdd(gt + 2 * (size_t)row + 1, wk * d1);
-            const f2 v = load_row<TableT>(lrs, row);
             const float dot = d0 * v[0] + d1 * v[1];
             gp[0] += dot * ((k & 1) ? 1.f : -1.f) * wy * wz;
             gp[1] += dot * ((k & 2) ? 1.f : -1.f) * wx * wz;
@@ -334,34 +393,57 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 #pragma unroll
           for (int q = 0; q < 3; ++q) g_u[q] = fmaf(gp[q], (float)N, g_u[q]);
         }
-        float g_xs[3];
+        // Table gradient: one atomic per corner and feature per run of
+        // consecutive samples in the same cell, carrying the run's sum.
+        float v[16];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const float ur = (st.xs[q] - a.f.gmin[q]) * a.f.gscale[q];
-          g_xs[q] = (ur > 0.f && ur < 1.f) ? g_u[q] * a.f.gscale[q] : 0.f;
+        for (int k = 0; k < 8; ++k) { v[2 * k] = wk[k] * d0; v[2 * k + 1] = wk[k] * d1; }
+        const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
+        run_sums<16>(cr, v);
+        if (live && cr.head) {
+          float* gt = a.grad_table + (size_t)l * T * 2;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t row = grid_row(gc, N, dense, tmask, k);
+            unsafeAtomicAdd(gt + 2 * (size_t)row, v[2 * k]);
+            unsafeAtomicAdd(gt + 2 * (size_t)row + 1, v[2 * k + 1]);
+          }
         }
+      }
+      float g_xs[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float ur = (st.xs[q] - a.f.gmin[q]) * a.f.gscale[q];
+        g_xs[q] = (live && ur > 0.f && ur < 1.f) ? g_u[q] * a.f.gscale[q] : 0.f;
+      }
 
-        // ---- 4. skinning adjoint ------------------------------------------------------
-        const bool above = st.L > EPS_L;
-        const float invL = 1.f / (above ? st.L : EPS_L);
+      // ---- 4. skinning adjoint ------------------------------------------------------
+      const bool above = st.L > EPS_L;
+      const float invL = 1.f / (above ? st.L : EPS_L);
+      const float gL = live ? g_L : 0.f;
 #pragma unroll 1
-        for (int b = 0; b < a.m.n_bones; ++b) {
-          float y[3];
-          bone_apply(a.G[b], st.x, y);
-          const float dx = above ? y[0] - st.xs[0] : y[0];
-          const float dy = above ? y[1] - st.xs[1] : y[1];
-          const float dz = above ? y[2] - st.xs[2] : y[2];
-          const float gw = (g_xs[0] * dx + g_xs[1] * dy + g_xs[2] * dz) * invL + g_L;
-          const Tri t = bone_cell(a.m, y);
+      for (int b = 0; b < a.m.n_bones; ++b) {
+        float y[3];
+        bone_apply(a.G[b], st.x, y);
+        const float dx = above ? y[0] - st.xs[0] : y[0];
+        const float dy = above ? y[1] - st.xs[1] : y[1];
+        const float dz = above ? y[2] - st.xs[2] : y[2];
+        const float gw = live ? (g_xs[0] * dx + g_xs[1] * dy + g_xs[2] * dz) * invL + gL : 0.f;
+        const Tri t = bone_cell(a.m, y);
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          v[k] = gw * ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
+                 ((k & 4) ? t.f[2] : 1.f - t.f[2]);
+        const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
+        run_sums<8>(cr, v);
+        if (live && cr.head) {
           float* gplane = a.grad_weights + b * plane;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const int ix = t.i0[0] + (k & 1), iy = t.i0[1] + ((k >> 1) & 1), iz = t.i0[2] + (k >> 2);
-            if ((unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R) {
-              const float wk = ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
-                               ((k & 4) ? t.f[2] : 1.f - t.f[2]);
-              unsafeAtomicAdd(gplane + ((size_t)iz * R + iy) * R + ix, gw * wk);
-            }
+            if ((unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R)
+              unsafeAtomicAdd(gplane + ((size_t)iz * R + iy) * R + ix, v[k]);
           }
         }
       }

@@ -99,6 +99,23 @@ def test_invalid_calls_are_rejected_before_launch():
     assert m.lib.mnr_zero(None, 16, None) == -1
     assert m.lib.mnr_convert(None, None, 1, 4, None) == -1
     assert m.lib.mnr_adam_step(None, None, None, None, 4, 1e-3, 0.9, 0.99, 1e-8, 1, None, 0, None) == -1
+    mo.packed = 0x5008                                                     # packed copy not 16-byte aligned
+    assert _render(m, f, mo, pose, cam) == -1
+    mo.packed = 0
+    assert m.lib.mnr_motion_pack(C.byref(mo), None) == -1                  # no packed buffer
+    assert m.lib.mnr_probe_gather(None, 64, 4, 0, 8, 256, 1, None, None) == -1
+    assert m.lib.mnr_probe_gather(0x1000, 64, 12, 0, 8, 256, 1, 0x2000, None) == -2
+    assert m.lib.mnr_probe_gather(0x1000, 64, 4, 0, 12, 256, 1, 0x2000, None) == -2
+    assert m.lib.mnr_probe_gather(0x1000, 64, 4, 128, 8, 256, 1, 0x2000, None) == -2   # window > table
+    assert m.lib.mnr_probe_mfma(1, 10, 1, 0x2000, None) == -3               # F16: unsupported
+
+
+def test_packed_motion_size():
+    m = _lib()
+    assert m.lib.mnr_motion_packed_bytes(32, 24) == 24 * 32 * 33 * 33 * 16
+    assert m.lib.mnr_motion_packed_bytes(256, 24) == 24 * 256 * 257 * 257 * 16
+    assert m.lib.mnr_motion_packed_bytes(257, 24) == 0                      # beyond the 32-bit offset range
+    assert m.lib.mnr_motion_packed_bytes(32, 0) == 0
 
 
 def test_status_strings():
