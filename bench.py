@@ -240,7 +240,8 @@ def train_bench(steps, warmup):
     return res
 
 
-def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 2.0, 2.0)):
+def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 2.0, 2.0),
+                tiles_per_tick=1024):
     """Poisson arrivals from U users at rate_hz each; resolutions uniform over
     {256^2, 512^2, 1024^2}; per-user fields resident (FP16 table, BF16 MLP);
     per-frame pose ~ N(0, 0.3).  Latency = completion - arrival."""
@@ -254,7 +255,7 @@ def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, w
     pool = {n: [torch.empty(n * n, 4, device="cuda") for _ in range(48)] for n in sizes}
     results = []
     for U, window in zip(user_counts, window_s):
-        srv = m.Server(mem_budget=8 << 30, max_slots=32, tiles_per_tick=1024)
+        srv = m.Server(mem_budget=8 << 30, max_slots=32, tiles_per_tick=tiles_per_tick)
         for u in range(U):
             srv.add_user(u, fields[u][1])
         g = np.random.default_rng(U)

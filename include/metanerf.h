@@ -71,6 +71,13 @@ typedef enum { MNR_F32 = 0, MNR_F16 = 1, MNR_BF16 = 2 } mnr_dtype;
  *     The encoding of point x is taken at u = clamp((x - box_min) /
  *     (box_max - box_min), 0, 1), p = u*N, cell min(floor(p), N-1).
  *   w[k]: dev row-major [width[k+1]][width[k]], dtype mlp_dtype (F32 or BF16).
+ *   dense_packed (optional, NULL = unused): a copy of the dense levels
+ *     written by mnr_field_pack in which the four x-y corners of every
+ *     cell are adjacent, so that a dense level's sample takes two (F16) or
+ *     four (F32) 16-byte loads instead of eight row gathers.  The renderer
+ *     reads it instead of `table` for dense levels when present (bitwise
+ *     identical results); re-pack after changing `table` (mnr_train_step
+ *     does so itself).
  * Supported: n_feat = 2, n_levels * n_feat = width[0] = 32, hidden widths
  * 64, width[n_layers] = 4, 2 <= n_layers <= 4, log2_T <= 24. */
 typedef struct {
@@ -83,7 +90,18 @@ typedef struct {
   int32_t width[MNR_MAX_LAYERS + 1];
   mnr_dtype mlp_dtype;
   const void* w[MNR_MAX_LAYERS];
+  const void* dense_packed;
 } mnr_field;
+
+/* Size in bytes of the packed copy of the dense levels: for every dense
+ * level in level order, [z in 0..N][y in 0..N-1][x in 0..N-1] groups of the
+ * rows of vertices (x,y,z), (x+1,y,z), (x,y+1,z), (x+1,y+1,z) (n_feat
+ * values each, table_dtype), N = level_res[l].  0 when no level is dense or
+ * the field is invalid. */
+uint64_t mnr_field_packed_bytes(const mnr_field* field);
+/* Write field->dense_packed (dev, mnr_field_packed_bytes bytes, 16-byte
+ * aligned, caller-owned) from field->table on `stream`. */
+mnr_status mnr_field_pack(const mnr_field* field, void* stream);
 
 /* Canonical blend-weight volume W^c (Sec. 4.2, Eq. 9-10): dev float
  * [n_bones + 1][res^3], voxel (x,y,z) at x + res*(y + res*z), channel

@@ -42,7 +42,8 @@ class Field(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_feat", C.c_int32), ("log2_T", C.c_int32),
                 ("level_res", C.c_int32 * MAX_LEVELS), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
                 ("table_dtype", C.c_int), ("table", C.c_void_p), ("n_layers", C.c_int32),
-                ("width", C.c_int32 * (MAX_LAYERS + 1)), ("mlp_dtype", C.c_int), ("w", C.c_void_p * MAX_LAYERS)]
+                ("width", C.c_int32 * (MAX_LAYERS + 1)), ("mlp_dtype", C.c_int), ("w", C.c_void_p * MAX_LAYERS),
+                ("dense_packed", C.c_void_p)]
 
 
 class Motion(C.Structure):
@@ -103,6 +104,8 @@ _sig("mnr_adam_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
 _sig("mnr_convert", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_void_p])
 _sig("mnr_zero", C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p])
 _sig("mnr_motion_packed_bytes", C.c_uint64, [C.c_int32, C.c_int32])
+_sig("mnr_field_packed_bytes", C.c_uint64, [C.POINTER(Field)])
+_sig("mnr_field_pack", C.c_int, [C.POINTER(Field), C.c_void_p])
 _sig("mnr_motion_pack", C.c_int, [C.POINTER(Motion), C.c_void_p])
 _sig("mnr_probe_gather", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_uint32,
                                    C.c_void_p, C.c_void_p])
@@ -111,7 +114,8 @@ _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainSta
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
-            "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_probe_gather", "mnr_probe_mfma"]
+            "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
+            "mnr_probe_gather", "mnr_probe_mfma"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -181,9 +185,10 @@ def fk_bones(pose: PoseHost) -> np.ndarray:
 
 class DeviceField:
     """A canonical field resident on the GPU: grid table + MLP weights (in
-    the dtypes the renderer reads) and the motion-weight volume, with its
-    packed copy (packed=True) that the renderer reads instead; call repack()
-    after changing `weights` in place."""
+    the dtypes the renderer reads) and the motion-weight volume.  With
+    packed=True it also holds the packed copies of the dense grid levels and
+    of the blend weights, which the renderer reads instead; call repack()
+    after changing `table` or `weights` in place."""
 
     def __init__(self, table: torch.Tensor, mlp: Sequence[torch.Tensor], weights: torch.Tensor, level_res,
                  box_min=(-0.5,) * 3, box_max=(0.5,) * 3, n_feat: int = 2, packed: bool = True):
@@ -201,6 +206,12 @@ class DeviceField:
         f.mlp_dtype = dt[self.mlp[0].dtype]
         for k, w in enumerate(self.mlp):
             f.w[k] = w.data_ptr()
+        self.dense_packed = None
+        if packed:
+            nb = int(lib.mnr_field_packed_bytes(C.byref(f)))
+            if nb > 0:
+                self.dense_packed = torch.empty(nb // 2, dtype=torch.float16, device=table.device)
+                f.dense_packed = self.dense_packed.data_ptr()
         self.c = f
         m = Motion()
         m.n_bones, m.res = int(weights.shape[0]) - 1, int(weights.shape[-1])
@@ -217,6 +228,8 @@ class DeviceField:
         self.repack()
 
     def repack(self) -> None:
+        if self.dense_packed is not None:
+            check(lib.mnr_field_pack(C.byref(self.c), _stream()), "field_pack")
         if self.packed is not None:
             check(lib.mnr_motion_pack(C.byref(self.m), _stream()), "motion_pack")
 
@@ -434,13 +447,13 @@ class Trainer:
                 t.copy_(v)
         self.state.step = int(sd["step"])
         softmax_fwd(self.logits, out=self.weights)
-        self.field.repack()
         if self.table is not self.table32:
             check(lib.mnr_convert(_ptr(self.table32), _ptr(self.table), self.field.c.table_dtype, self.table32.numel(),
                                   _stream()), "convert")
         for w32, w in zip(self.mlp32, self.mlp):
             if w is not w32:
                 check(lib.mnr_convert(_ptr(w32), _ptr(w), self.field.c.mlp_dtype, w32.numel(), _stream()), "convert")
+        self.field.repack()
 
 
 # ---------------------------------------------------------------------------

@@ -55,6 +55,8 @@ mnr_status validate_field(const mnr_field* f) {
     if (f->width[k] != 64) return fail(MNR_E_SHAPE, "field: hidden width %d must be 64", f->width[k]);
   for (int k = 0; k < f->n_layers; ++k)
     if (!f->w[k]) return fail(MNR_E_INVALID, "field: null weight pointer for layer %d", k);
+  if (f->dense_packed && ((uintptr_t)f->dense_packed & 15))
+    return fail(MNR_E_INVALID, "field: dense_packed not 16-byte aligned");
   return check_box(f->box_min, f->box_max, "field");
 }
 
@@ -87,23 +89,49 @@ mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_po
   return MNR_OK;
 }
 
+// Packed copy of one dense level: (N+1) z-planes of N x N groups of four
+// rows (2 features each).
+static uint64_t dense_level_bytes(int N, mnr_dtype dt) {
+  return (uint64_t)(N + 1) * N * N * 4 * 2 * (dt == MNR_F32 ? 4 : 2);
+}
+
+static bool level_is_dense(const mnr_field* f, int l) {
+  const int64_t n1 = f->level_res[l] + 1;
+  return n1 * n1 * n1 <= (int64_t(1) << f->log2_T);
+}
+
+void field_args(FieldArgs& F, const mnr_field* f) {
+  std::memset(&F, 0, sizeof(F));
+  F.table = f->table;
+  for (int k = 0; k < f->n_layers; ++k) F.w[k] = f->w[k];
+  F.dpk = (const char*)f->dense_packed;
+  uint64_t off = 0;
+  bool prefix = true;
+  for (int l = 0; l < f->n_levels; ++l) {
+    F.level_res[l] = f->level_res[l];
+    if (level_is_dense(f, l)) {
+      F.dense_mask |= 1u << l;
+      F.dpk_off[l] = off;
+      off += dense_level_bytes(f->level_res[l], f->table_dtype);
+      if (prefix && F.dpk) F.n_packed = l + 1;
+    } else {
+      prefix = false;
+    }
+  }
+  F.n_levels = f->n_levels;
+  F.log2_T = f->log2_T;
+  F.n_layers = f->n_layers;
+  for (int i = 0; i < 3; ++i) {
+    F.gmin[i] = f->box_min[i];
+    F.gscale[i] = (float)(1.0 / ((double)f->box_max[i] - f->box_min[i]));
+  }
+}
+
 void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
                       int H, int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays) {
   std::memset(&a, 0, sizeof(a));
-  a.f.table = f->table;
-  for (int k = 0; k < f->n_layers; ++k) a.f.w[k] = f->w[k];
-  const int64_t T = int64_t(1) << f->log2_T;
-  for (int l = 0; l < f->n_levels; ++l) {
-    a.f.level_res[l] = f->level_res[l];
-    const int64_t n1 = f->level_res[l] + 1;
-    if (n1 * n1 * n1 <= T) a.f.dense_mask |= 1u << l;
-  }
-  a.f.n_levels = f->n_levels;
-  a.f.log2_T = f->log2_T;
-  a.f.n_layers = f->n_layers;
+  field_args(a.f, f);
   for (int i = 0; i < 3; ++i) {
-    a.f.gmin[i] = f->box_min[i];
-    a.f.gscale[i] = (float)(1.0 / ((double)f->box_max[i] - f->box_min[i]));
     a.m.mmin[i] = m->box_min[i];
     a.m.mscale[i] = (float)((m->res - 1) / ((double)m->box_max[i] - m->box_min[i]));
   }
@@ -230,6 +258,25 @@ mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channe
   return hip_status(launch_softmax_fwd(logits, weights, n_channels, n_voxels, (hipStream_t)stream), "softmax launch");
 }
 
+uint64_t mnr_field_packed_bytes(const mnr_field* f) {
+  clear_error();
+  if (validate_field(f) != MNR_OK) return 0;
+  uint64_t b = 0;
+  for (int l = 0; l < f->n_levels; ++l)
+    if (level_is_dense(f, l)) b += dense_level_bytes(f->level_res[l], f->table_dtype);
+  return b;
+}
+
+mnr_status mnr_field_pack(const mnr_field* f, void* stream) {
+  clear_error();
+  if (mnr_status s = validate_field(f)) return s;
+  if (!f->dense_packed) return fail(MNR_E_INVALID, "field_pack: null dense_packed");
+  FieldArgs F;
+  field_args(F, f);
+  if (F.dense_mask == 0) return MNR_OK;
+  return hip_status(launch_pack_dense(F, f->table_dtype, (hipStream_t)stream), "field_pack launch");
+}
+
 uint64_t mnr_motion_packed_bytes(int32_t res, int32_t n_bones) {
   if (res < 2 || res > MAX_PACKED_RES || n_bones < 1 || n_bones > MNR_MAX_BONES) return 0;
   return (uint64_t)n_bones * res * (res + 1) * (res + 1) * sizeof(f4);
@@ -336,6 +383,7 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
                  st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
                  field->table_dtype, s));
+  if (field->dense_packed && a.f.dense_mask) ok(launch_pack_dense(a.f, field->table_dtype, s));
   for (int k = 0; k < field->n_layers; ++k)
     ok(launch_adam(st->w_master[k], st->w_grad[k], st->w_m[k], st->w_v[k],
                    (int64_t)field->width[k] * field->width[k + 1], st->lr_field, st->beta1, st->beta2, st->eps,

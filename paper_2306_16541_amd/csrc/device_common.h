@@ -39,6 +39,9 @@ struct FieldArgs {
   uint32_t dense_mask;  // bit l: level l stored densely
   int32_t n_levels, log2_T, n_layers;
   float gmin[3], gscale[3];  // u = (x - gmin) * gscale
+  const char* dpk;           // optional packed copy of the dense levels (NULL: gather from table)
+  uint64_t dpk_off[MNR_MAX_LEVELS];  // byte offset of each dense level in dpk
+  int32_t n_packed;          // leading dense levels read from dpk (0 without it)
 };
 
 // Largest volume resolution with a packed copy: one bone's packed plane

@@ -54,10 +54,10 @@ __device__ __forceinline__ void tri_offsets(const Tri& t, int R, uint32_t off[8]
 }
 
 __device__ __forceinline__ float trilerp(const float v[8], const float f[3]) {
-  const float x00 = v[0] + f[0] * (v[1] - v[0]), x10 = v[2] + f[0] * (v[3] - v[2]);
-  const float x01 = v[4] + f[0] * (v[5] - v[4]), x11 = v[6] + f[0] * (v[7] - v[6]);
-  const float y0 = x00 + f[1] * (x10 - x00), y1 = x01 + f[1] * (x11 - x01);
-  return y0 + f[2] * (y1 - y0);
+  const float x00 = __builtin_fmaf(f[0], v[1] - v[0], v[0]), x10 = __builtin_fmaf(f[0], v[3] - v[2], v[2]);
+  const float x01 = __builtin_fmaf(f[0], v[5] - v[4], v[4]), x11 = __builtin_fmaf(f[0], v[7] - v[6], v[6]);
+  const float y0 = __builtin_fmaf(f[1], x10 - x00, x00), y1 = __builtin_fmaf(f[1], x11 - x01, x01);
+  return __builtin_fmaf(f[2], y1 - y0, y0);
 }
 
 __device__ __forceinline__ void bone_apply(const float* __restrict__ g, const float x[3], float y[3]) {
@@ -172,6 +172,9 @@ struct GridCell {
 };
 
 __device__ __forceinline__ GridCell grid_cell(const float u[3], int N) {
+  // p is rounded before the fractional part is taken: left to itself the
+  // compiler fuses u*N - floor(p) into an FMA at some call sites only.
+#pragma clang fp contract(off)
   GridCell c;
   const float Nf = (float)N;
 #pragma unroll
@@ -194,38 +197,99 @@ __device__ __forceinline__ uint32_t grid_row(const GridCell& c, int N, bool dens
   return (x * 1u ^ y * 2654435761u ^ z * 805459861u) & mask;
 }
 
+// Explicit fused multiply-adds: the result must not depend on which code
+// path (gathered rows or packed groups) supplied the corners.
+__device__ __forceinline__ float lerp1(float a, float b, float t) { return __builtin_fmaf(t, b - a, a); }
+
 __device__ __forceinline__ f2 trilerp2(const f2 v[8], const float f[3]) {
-  const f2 x00 = v[0] + f[0] * (v[1] - v[0]), x10 = v[2] + f[0] * (v[3] - v[2]);
-  const f2 x01 = v[4] + f[0] * (v[5] - v[4]), x11 = v[6] + f[0] * (v[7] - v[6]);
-  const f2 y0 = x00 + f[1] * (x10 - x00), y1 = x01 + f[1] * (x11 - x01);
-  return y0 + f[2] * (y1 - y0);
+  f2 r;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const float x00 = lerp1(v[0][c], v[1][c], f[0]), x10 = lerp1(v[2][c], v[3][c], f[0]);
+    const float x01 = lerp1(v[4][c], v[5][c], f[0]), x11 = lerp1(v[6][c], v[7][c], f[0]);
+    r[c] = lerp1(lerp1(x00, x10, f[1]), lerp1(x01, x11, f[1]), f[2]);
+  }
+  return r;
 }
 
-// Levels are encoded LG at a time so that LG x 8 row gathers are in flight
-// before the first one is consumed.  Calls store(l, feature pair).
+// The 8 corner rows of a dense level's cell from the packed copy: groups of
+// the 4 x-y corners (2 features each) at [z][y0][x0], planes z0 and z0+1,
+// corner k at (x0 + (k&1), y0 + (k>>1 & 1), z0 + (k>>2)) as in grid_row.
+template <typename TableT>
+__device__ __forceinline__ void load_cell_packed(const FieldArgs& f, int l, const GridCell& c, int N, f2 v[8]) {
+  constexpr uint32_t EB = 8u * sizeof(TableT);  // bytes of one group
+  const uint32_t n = (uint32_t)N, zs = n * n * EB;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(f.dpk + f.dpk_off[l], (n + 1u) * zs);
+  const uint32_t o = (((uint32_t)c.i0[2] * n + (uint32_t)c.i0[1]) * n + (uint32_t)c.i0[0]) * EB;
+  if constexpr (sizeof(TableT) == 2) {
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    const h8 lo = __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    const h8 hi = __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rs, o + zs, 0, 0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = f2{(float)lo[2 * k], (float)lo[2 * k + 1]};
+      v[4 + k] = f2{(float)hi[2 * k], (float)hi[2 * k + 1]};
+    }
+  } else {
+    const f4 a = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    const f4 b = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0));
+    const f4 d = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + zs, 0, 0));
+    const f4 e = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + zs + 16u, 0, 0));
+    v[0] = f2{a[0], a[1]}; v[1] = f2{a[2], a[3]}; v[2] = f2{b[0], b[1]}; v[3] = f2{b[2], b[3]};
+    v[4] = f2{d[0], d[1]}; v[5] = f2{d[2], d[3]}; v[6] = f2{e[0], e[1]}; v[7] = f2{e[2], e[3]};
+  }
+}
+
+// Levels are encoded in groups whose loads are all in flight before the
+// first is consumed: the leading dense levels from the packed copy (when
+// present) PG at a time, then the remaining levels' row gathers LG at a
+// time.  Calls store(l, feature pair) for every level.
 constexpr int LG = 4;
+template <typename TableT>
+constexpr int packed_group() { return sizeof(TableT) == 2 ? 4 : 2; }  // 32 VGPRs of loads either way
 
 template <typename TableT, typename Store>
 __device__ __forceinline__ void encode_all(const FieldArgs& f, const float u[3], bool live, Store store) {
+  constexpr int PG = packed_group<TableT>();
   const uint32_t mask = (1u << f.log2_T) - 1u;
 #pragma unroll 1
-  for (int l0 = 0; l0 < f.n_levels; l0 += LG) {
+  for (int l0 = 0; l0 < f.n_packed; l0 += PG) {
+    f2 v[PG][8];
+    GridCell c[PG];
+#pragma unroll
+    for (int q = 0; q < PG; ++q) {
+      const int l = l0 + q;
+      if (l < f.n_packed) {  // uniform
+        const int N = f.level_res[l];
+        c[q] = grid_cell(u, N);
+        if (live) load_cell_packed<TableT>(f, l, c[q], N, v[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PG; ++q)
+      if (l0 + q < f.n_packed) store(l0 + q, live ? trilerp2(v[q], c[q].f) : f2{0.f, 0.f});
+  }
+#pragma unroll 1
+  for (int l0 = f.n_packed; l0 < f.n_levels; l0 += LG) {
     f2 v[LG][8];
     GridCell c[LG];
 #pragma unroll
     for (int q = 0; q < LG; ++q) {
       const int l = l0 + q;
-      const int N = f.level_res[l];
-      const bool dense = (f.dense_mask >> l) & 1u;
-      c[q] = grid_cell(u, N);
-      const __amdgpu_buffer_rsrc_t rs = level_rsrc<TableT>(f, l);
-      if (live) {  // one exec-masked region: dead lanes issue no gathers
+      if (l < f.n_levels) {  // uniform
+        const int N = f.level_res[l];
+        const bool dense = (f.dense_mask >> l) & 1u;
+        c[q] = grid_cell(u, N);
+        const __amdgpu_buffer_rsrc_t rs = level_rsrc<TableT>(f, l);
+        if (live) {  // one exec-masked region: dead lanes issue no gathers
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[q][k] = load_row<TableT>(rs, grid_row(c[q], N, dense, mask, k));
+          for (int k = 0; k < 8; ++k) v[q][k] = load_row<TableT>(rs, grid_row(c[q], N, dense, mask, k));
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < LG; ++q) store(l0 + q, live ? trilerp2(v[q], c[q].f) : f2{0.f, 0.f});
+    for (int q = 0; q < LG; ++q)
+      if (l0 + q < f.n_levels) store(l0 + q, live ? trilerp2(v[q], c[q].f) : f2{0.f, 0.f});
   }
 }
 

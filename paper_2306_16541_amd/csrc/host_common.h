@@ -13,6 +13,8 @@ mnr_status validate_pose(const mnr_pose* pose);
 void fk_bones_f64(const mnr_pose* pose, double* G);
 
 struct RenderArgs;
+struct FieldArgs;
+void field_args(FieldArgs& F, const mnr_field* f);
 mnr_status validate_field(const mnr_field* f);
 mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c, int H,
                            int W, int spp, const mnr_opts* o, const int32_t* pixel_ids, int n_rays, const void* out);

@@ -29,5 +29,8 @@ hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // Packed copy of the bone channels of a blend-weight volume (2x2 x-y corners
 // per float4; layout in mnr_motion_packed_bytes' declaration).
 hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hipStream_t st);
+// Packed copy of the dense grid levels (2x2 x-y corner groups; layout in
+// mnr_field_packed_bytes' declaration).  f.dpk and f.dpk_off must be set.
+hipError_t launch_pack_dense(const FieldArgs& f, mnr_dtype table_dt, hipStream_t st);
 
 }  // namespace mnr

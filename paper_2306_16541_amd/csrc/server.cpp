@@ -62,6 +62,7 @@ static uint64_t field_bytes(const mnr_field& f, const mnr_motion& m) {
   for (int k = 0; k < f.n_layers; ++k) b += (uint64_t)f.width[k] * f.width[k + 1] * wl;
   b += (uint64_t)(m.n_bones + 1) * m.res * m.res * m.res * 4;
   if (m.packed) b += mnr_motion_packed_bytes(m.res, m.n_bones);
+  if (f.dense_packed) b += mnr_field_packed_bytes(&f);
   return b;
 }
 

@@ -2,8 +2,9 @@
 // the squared-error loss (MSE term of Eq. 14), the per-voxel softmax that
 // turns free logits into canonical blend weights W^c (Sec. 4.2) and its
 // adjoint, Adam (beta1 = 0.9, beta2 = 0.99 in the paper), precision
-// conversion of parameter copies, the packed copy of the blend-weight
-// volume read by the renderer, and a kernel fill.
+// conversion of parameter copies, the packed copies of the blend-weight
+// volume and of the dense grid levels read by the renderer, and a kernel
+// fill.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -137,6 +138,41 @@ hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hi
   const int64_t n = (int64_t)n_bones * R * (R + 1) * (R + 1);
   hipLaunchKernelGGL(pack_motion_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, w, packed, R, n);
   return hipGetLastError();
+}
+
+// One group per (z, y, x) cell base of a dense level: the rows of its four
+// x-y corners in plane z, 2 features each, copied in the table's dtype.
+template <typename TableT>
+__global__ void pack_dense_kernel(const TableT* __restrict__ level, TableT* __restrict__ out, int N, int64_t n) {
+  const int64_t s = N + 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = e % N, y = (e / N) % N, z = e / ((int64_t)N * N);
+    const int64_t r0 = x + s * (y + s * z);
+    const int64_t rows[4] = {r0, r0 + 1, r0 + s, r0 + s + 1};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      out[e * 8 + 2 * c] = level[rows[c] * 2];
+      out[e * 8 + 2 * c + 1] = level[rows[c] * 2 + 1];
+    }
+  }
+}
+
+hipError_t launch_pack_dense(const FieldArgs& f, mnr_dtype dt, hipStream_t st) {
+  const size_t T = (size_t)1 << f.log2_T;
+  for (int l = 0; l < f.n_levels; ++l) {
+    if (!((f.dense_mask >> l) & 1u)) continue;
+    const int N = f.level_res[l];
+    const int64_t n = (int64_t)(N + 1) * N * N;
+    if (dt == MNR_F32)
+      hipLaunchKernelGGL(pack_dense_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st,
+                         (const float*)f.table + (size_t)l * T * 2, (float*)(f.dpk + f.dpk_off[l]), N, n);
+    else
+      hipLaunchKernelGGL(pack_dense_kernel<_Float16>, dim3(grid_for(n, 256)), dim3(256), 0, st,
+                         (const _Float16*)f.table + (size_t)l * T * 2, (_Float16*)(f.dpk + f.dpk_off[l]), N, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {

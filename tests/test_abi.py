@@ -103,6 +103,13 @@ def test_invalid_calls_are_rejected_before_launch():
     assert _render(m, f, mo, pose, cam) == -1
     mo.packed = 0
     assert m.lib.mnr_motion_pack(C.byref(mo), None) == -1                  # no packed buffer
+    assert m.lib.mnr_field_pack(C.byref(f), None) == -1                    # no dense_packed buffer
+    f.dense_packed = 0x6004                                                # not 16-byte aligned
+    assert _render(m, f, mo, pose, cam) == -1
+    assert m.lib.mnr_field_packed_bytes(C.byref(f)) == 0
+    f.dense_packed = 0
+    dense = sum((n + 1) * n * n * 32 for n in sc.level_res if (n + 1) ** 3 <= 1 << sc.log2_T)
+    assert dense > 0 and m.lib.mnr_field_packed_bytes(C.byref(f)) == dense   # F32 groups: 4 rows x 8 B
     assert m.lib.mnr_probe_gather(None, 64, 4, 0, 8, 256, 1, None, None) == -1
     assert m.lib.mnr_probe_gather(0x1000, 64, 12, 0, 8, 256, 1, 0x2000, None) == -2
     assert m.lib.mnr_probe_gather(0x1000, 64, 4, 0, 12, 256, 1, 0x2000, None) == -2

@@ -154,9 +154,25 @@ def _packed_reference(weights, n_bones):
     return out
 
 
+def _dense_packed_reference(table, level_res, log2_T):
+    # Packed dense levels, written out from their definition: for each dense
+    # level, [z][y][x] groups of the rows of (x,y,z), (x+1,y,z), (x,y+1,z),
+    # (x+1,y+1,z); rows are dense vertex indices x + (N+1)(y + (N+1)z).
+    out = []
+    for l, n in enumerate(level_res):
+        s = n + 1
+        if s ** 3 > (1 << log2_T):
+            continue
+        rows = table[l, : s ** 3].reshape(s, s, s, 2)       # [z][y][x][feat]
+        g = np.stack([rows[:, :n, :n], rows[:, :n, 1:], rows[:, 1:, :n], rows[:, 1:, 1:]], axis=3)
+        out.append(g.reshape(-1))
+    return np.concatenate(out)
+
+
 def test_packed_weight_copy_layout_and_bitwise_render():
-    # The packed copy holds exactly the plain volume's values, and rendering
-    # from it changes no pixel (frame kernel and ray-list kernel).
+    # The packed copies hold exactly the plain volume's and the dense levels'
+    # values, and rendering from them changes no pixel (frame kernel and
+    # ray-list kernel).
     import paper_2306_16541_amd as m
     for sc, tdt, mdt in [(scenes.scene_small(H=40, W=24, spp=64), 0, 0),
                          (scenes.scene_body(H=48, W=64, spp=128), 0, 0),
@@ -168,6 +184,8 @@ def test_packed_weight_copy_layout_and_bitwise_render():
         got = packed.packed.view(nb, R, R + 1, R + 1, 4).cpu().numpy()
         want = _packed_reference(packed.weights.view(nb + 1, R, R, R).cpu().numpy(), nb)
         assert np.array_equal(got, want)
+        dp = packed.dense_packed.view(packed.table.dtype).cpu().float().numpy()
+        assert np.array_equal(dp, _dense_packed_reference(packed.table.cpu().float().numpy(), sc.level_res, sc.log2_T))
         pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
         cam = m.make_camera(sc.cam)
         pid = torch.as_tensor(np.random.default_rng(3).integers(0, sc.H * sc.W, 777).astype(np.int32), device="cuda")

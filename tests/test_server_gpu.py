@@ -81,8 +81,9 @@ def test_memory_admission_and_rejections():
     import math
     import paper_2306_16541_amd as m
     sc, fld = _user(16541 + 60)
+    dense = sum((n + 1) * n * n * 16 for n in sc.level_res if (n + 1) ** 3 <= 1 << 16)
     resident = (16 * (1 << 16) * 2 * 2 + sum(w.size for w in sc.mlp) * 2 + 25 * 32 ** 3 * 4
-                + 24 * 32 * 33 * 33 * 16)   # + the packed copy of the bone channels
+                + 24 * 32 * 33 * 33 * 16 + dense)   # + the packed copies of the bone channels and dense levels
     frame = 64 * 64 * 16
     srv = m.Server(mem_budget=resident + frame + 100, max_slots=4)      # room for one 64x64 output
     srv.add_user(0, fld)
