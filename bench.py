@@ -34,17 +34,21 @@ BYTES_WARP = 24 * 8 * 4                        # per evaluated sample: 24 bones 
 BYTES_ENC = {"f32": 16 * 8 * 2 * 4, "f16": 16 * 8 * 2 * 2}   # 16 levels x 8 corners x 2 features
 
 
+# The files that define the frame kernels (and the arguments they are
+# launched with): a change to any of them invalidates the recorded counters.
+FRAME_KERNEL_SOURCES = ("paper_2306_16541_amd/csrc/render.hip", "paper_2306_16541_amd/csrc/field_device.h",
+                        "paper_2306_16541_amd/csrc/device_common.h", "paper_2306_16541_amd/csrc/kernels.h",
+                        "paper_2306_16541_amd/csrc/api.cpp", "include/metanerf.h")
+
+
 def sources_digest():
-    """SHA-256 over the kernel sources and headers (identifies the build the
+    """SHA-256 over the frame kernels' sources (identifies the build the
     counter-based traffic figures were taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for d, exts in ((os.path.join(ROOT, "paper_2306_16541_amd", "csrc"), (".hip", ".h", ".cpp")),
-                    (os.path.join(ROOT, "include"), (".h",))):
-        for f in sorted(os.listdir(d)):
-            if f.endswith(exts):
-                h.update(f.encode())
-                h.update(open(os.path.join(d, f), "rb").read())
+    for rel in FRAME_KERNEL_SOURCES:
+        h.update(rel.encode())
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
     return h.hexdigest()
 
 
@@ -171,7 +175,8 @@ def oracle_one_thread(sc, budget_s):
 def ceilings(reps=5):
     """Measured machine ceilings: random small gathers from tables of the
     grid's sizes (uniform, and within a 4 KiB window per wave as neighbouring
-    rays do) and dense MFMA loops, each the median of `reps` launches."""
+    rays do), scattered float atomics (alone, and 8 lanes per address) and
+    dense MFMA loops, each the median of `reps` launches."""
     out = {}
     n_lanes, per_lane = 1 << 20, 64
     for rb, mib, name in ((4, 32, "fp16_table_rows"), (8, 64, "fp32_table_rows"), (16, 104, "packed_weight_cells")):
@@ -185,6 +190,12 @@ def ceilings(reps=5):
             res[key] = {"Ggathers_per_s": g / 1e9, "useful_GB_per_s": g * rb / 1e9}
         out[f"gather_{rb}B_{name}_{mib}MiB"] = res
         del table
+    acc = torch.zeros(16 << 20, dtype=torch.float32, device="cuda")   # 64 MiB, the FP32 table's size
+    for run in (1, 8):
+        timed_launches(lambda: m.probe_atomic(acc, 128, 1 << 20, run), reps, 1)
+        ms = timed_launches.last_median
+        out[f"float_atomics_64MiB_run{run}"] = {"G_atomics_per_s": (1 << 20) * 128 / (ms * 1e-3) / 1e9}
+    del acc
     n_blocks, iters = 2048, 4000
     buf = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda")
     for dt, name, flop in ((m.F32, "mfma_f32_16x16x4", 2048), (m.BF16, "mfma_bf16_16x16x32", 16384)):

@@ -7,7 +7,8 @@
  * the published peaks:
  *   - small random gathers from a table of the grid encoding's size
  *     (the warp and encoding steps, Sec. 4.2 Eq. 9 and Sec. 4.4 Eq. 13);
- *   - a dense MFMA loop in the MLP's arithmetic types (the MLP of Eq. 13).
+ *   - a dense MFMA loop in the MLP's arithmetic types (the MLP of Eq. 13);
+ *   - scattered float atomics (the adjoint's gradient scatter, Sec. 5.2).
  * Both run on the caller's stream; time them with events around the call.
  */
 #ifndef METANERF_PROBE_H
@@ -30,6 +31,16 @@ extern "C" {
  * n_lanes * gathers_per_lane. */
 mnr_status mnr_probe_gather(const void* table, uint64_t table_bytes, int32_t row_bytes, uint32_t window_bytes,
                             int32_t gathers_per_lane, int32_t n_lanes, uint32_t seed, float* out, void* stream);
+
+/* Each of n_lanes lanes (a multiple of 256) adds 1.0f with
+ * atomics_per_lane device-scope float atomics (no return value) to words of
+ * the dev float buffer acc[n_words] chosen by a fixed hash of (seed, lane /
+ * run, k): `run` consecutive lanes (1..64) share each address, the pattern
+ * of consecutive samples of one ray in a coarse cell.  The adjoint's
+ * scatter is made of such atomics.  Atomics issued = n_lanes *
+ * atomics_per_lane; the buffer's sum grows by exactly that. */
+mnr_status mnr_probe_atomic(float* acc, uint32_t n_words, int32_t atomics_per_lane, int32_t n_lanes, int32_t run,
+                            uint32_t seed, void* stream);
 
 /* n_blocks blocks of 4 waves each run `iters` iterations of 4 independent
  * MFMA chains: F32 -> v_mfma_f32_16x16x4f32 (2048 FLOP each), BF16 ->

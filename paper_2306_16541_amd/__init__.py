@@ -110,12 +110,13 @@ _sig("mnr_motion_pack", C.c_int, [C.POINTER(Motion), C.c_void_p])
 _sig("mnr_probe_gather", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_uint32,
                                    C.c_void_p, C.c_void_p])
 _sig("mnr_probe_mfma", C.c_int, [C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p])
+_sig("mnr_probe_atomic", C.c_int, [C.c_void_p, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
-            "mnr_probe_gather", "mnr_probe_mfma"]
+            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -253,6 +254,12 @@ def probe_gather(table: torch.Tensor, row_bytes: int, window_bytes: int, gathers
     check(lib.mnr_probe_gather(_ptr(table), table.numel() * table.element_size(), row_bytes, window_bytes,
                                gathers_per_lane, n_lanes, seed, _ptr(out), _stream()), "probe_gather")
     return out
+
+
+def probe_atomic(acc: torch.Tensor, atomics_per_lane: int, n_lanes: int, run: int = 1, seed: int = 1) -> None:
+    """Scattered float-atomic ceiling probe (include/metanerf_probe.h)."""
+    check(lib.mnr_probe_atomic(_ptr(acc), acc.numel(), atomics_per_lane, n_lanes, run, seed, _stream()),
+          "probe_atomic")
 
 
 def probe_mfma(dtype: int, iters: int, n_blocks: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:

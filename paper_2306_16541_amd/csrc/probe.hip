@@ -1,5 +1,5 @@
-// Machine-ceiling probes: a random-gather kernel and a dense MFMA loop
-// (declared in metanerf_probe.h).  They share nothing with the renderer but
+// Machine-ceiling probes: a random-gather kernel, scattered float atomics
+// and a dense MFMA loop (declared in metanerf_probe.h).  They share nothing with the renderer but
 // the buffer-resource helper.
 #include <hip/hip_runtime.h>
 
@@ -57,6 +57,12 @@ __global__ void __launch_bounds__(256) probe_gather_kernel(const void* table, ui
   out[gid] = acc;
 }
 
+__global__ void __launch_bounds__(256) probe_atomic_kernel(float* __restrict__ acc, uint32_t n_words, int K, int run,
+                                                           uint32_t seed) {
+  const uint32_t gid = blockIdx.x * 256u + threadIdx.x, key = gid / (uint32_t)run;
+  for (int k = 0; k < K; ++k) unsafeAtomicAdd(acc + __umulhi(mix32(key, (uint32_t)k, seed), n_words), 1.0f);
+}
+
 template <bool BF16>
 __global__ void __launch_bounds__(256) probe_mfma_kernel(int iters, float* __restrict__ out) {
   const int lane = threadIdx.x & 63;
@@ -110,6 +116,18 @@ extern "C" mnr_status mnr_probe_gather(const void* table, uint64_t table_bytes, 
   else hipLaunchKernelGGL(probe_gather_kernel<16>, grid, block, 0, st, table, n_rows, win_rows, gathers_per_lane, seed, out);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_gather launch: %s", hipGetErrorString(e));
+}
+
+extern "C" mnr_status mnr_probe_atomic(float* acc, uint32_t n_words, int32_t atomics_per_lane, int32_t n_lanes,
+                                       int32_t run, uint32_t seed, void* stream) {
+  clear_error();
+  if (!acc) return fail(MNR_E_INVALID, "probe_atomic: null pointer");
+  if (n_words < 1 || atomics_per_lane < 1 || n_lanes < 256 || n_lanes % 256 || run < 1 || run > 64)
+    return fail(MNR_E_SHAPE, "probe_atomic: bad sizes");
+  hipLaunchKernelGGL(probe_atomic_kernel, dim3(n_lanes / 256), dim3(256), 0, (hipStream_t)stream, acc, n_words,
+                     atomics_per_lane, run, seed);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_atomic launch: %s", hipGetErrorString(e));
 }
 
 extern "C" mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_blocks, float* out, void* stream) {

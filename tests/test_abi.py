@@ -115,6 +115,8 @@ def test_invalid_calls_are_rejected_before_launch():
     assert m.lib.mnr_probe_gather(0x1000, 64, 4, 0, 12, 256, 1, 0x2000, None) == -2
     assert m.lib.mnr_probe_gather(0x1000, 64, 4, 128, 8, 256, 1, 0x2000, None) == -2   # window > table
     assert m.lib.mnr_probe_mfma(1, 10, 1, 0x2000, None) == -3               # F16: unsupported
+    assert m.lib.mnr_probe_atomic(None, 16, 1, 256, 1, 1, None) == -1
+    assert m.lib.mnr_probe_atomic(0x2000, 16, 1, 256, 65, 1, None) == -2      # run > 64
 
 
 def test_packed_motion_size():
