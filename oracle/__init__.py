@@ -6,3 +6,4 @@ import this package.  It shares no code with the GPU library.
 from .render import *  # noqa: F401,F403
 from .render import Field, render_image, render_rays, bone_transforms, camera_rays  # noqa: F401
 from .rng import splitmix64, stratified_xi  # noqa: F401
+from .residual import hann_window, posenc, residual_offset  # noqa: F401

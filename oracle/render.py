@@ -21,6 +21,8 @@ Steps and where they are defined:
   * likelihood augmentation of alpha ...... Sec. 4.4 (last paragraph)
   * squared-error loss .................... Sec. 2.1 and Sec. 5.2, Eq. 14
     (MSE term only)
+  * optional residual non-rigid motion .... Sec. 4.3, Eq. 11-12
+    (oracle/residual.py)
 
 Readings of ambiguous passages (each listed in the design doc):
   * Eq. 3: delta_i is the stratum width (t_f - t_n)/S for every sample, so
@@ -308,9 +310,12 @@ class Field:
 
 
 def render_rays(field: Field, G: torch.Tensor, o: torch.Tensor, d: torch.Tensor, S: int,
-                xi=None, bg=(0.0, 0.0, 0.0), chunk: int = 256, return_stats: bool = False):
+                xi=None, bg=(0.0, 0.0, 0.0), chunk: int = 256, return_stats: bool = False, residual=None):
     """Render rays (o, d [B,3]) with S samples each.  xi: None (midpoints) or
-    [B,S].  Missed rays give (bg, 0).  Returns RGBA [B,4]."""
+    [B,S].  Missed rays give (bg, 0).  Returns RGBA [B,4].  residual: None,
+    or a dict with the residual motion network (oracle/residual.py:
+    "weights", "w_omega", "omega", "alpha"); the field is then queried at
+    x_final = x_skel + x_res (Sec. 4.3, Eq. 12)."""
     G = as64(G)
     Wc = motion_weights(field.logits)
     B = d.shape[0]
@@ -330,6 +335,10 @@ def render_rays(field: Field, G: torch.Tensor, o: torch.Tensor, d: torch.Tensor,
             x = o[None, None, :] + t[:, :, None] * dd[:, None, :]
             nb = idx.shape[0]
             x_skel, L = inverse_lbs(x.reshape(-1, 3), G, Wc, field.box_min, field.box_max)
+            if residual is not None:
+                from .residual import residual_offset
+                x_skel = x_skel + residual_offset(x_skel, residual["omega"], residual["weights"],
+                                                  residual["w_omega"], residual["alpha"])
             feat = grid_encode(x_skel, field.table, field.level_res, field.box_min, field.box_max)
             rgb, sigma = mlp(feat, field.mlp)
             C, A, _ = composite(sigma.reshape(nb, S), rgb.reshape(nb, S, 3), L.reshape(nb, S), delta, bgt)
@@ -343,12 +352,17 @@ def render_rays(field: Field, G: torch.Tensor, o: torch.Tensor, d: torch.Tensor,
 
 
 def render_image(sc, field: Optional[Field] = None, pixel_ids=None, xi=None, bg=(0.0, 0.0, 0.0),
-                 axis_angle=None, cam=None, return_stats=False):
-    """Render a scene (all pixels, or the listed pixel ids) -> RGBA [B,4]."""
+                 axis_angle=None, cam=None, return_stats=False, residual=None):
+    """Render a scene (all pixels, or the listed pixel ids) -> RGBA [B,4].
+    residual: None, or {"weights", "w_omega", "alpha"} of the residual motion
+    network, conditioned on the rendered pose."""
     field = Field.from_scene(sc) if field is None else field
-    G = bone_transforms(sc.parents, sc.rest_joints, sc.axis_angle if axis_angle is None else axis_angle)
+    aa = sc.axis_angle if axis_angle is None else axis_angle
+    G = bone_transforms(sc.parents, sc.rest_joints, aa)
     o, d = camera_rays(sc.cam if cam is None else cam, sc.H, sc.W, pixel_ids)
-    return render_rays(field, G, o, d, sc.spp, xi=xi, bg=bg, return_stats=return_stats)
+    if residual is not None:
+        residual = dict(residual, omega=aa)
+    return render_rays(field, G, o, d, sc.spp, xi=xi, bg=bg, return_stats=return_stats, residual=residual)
 
 
 def mse_loss(rgba: torch.Tensor, target) -> torch.Tensor:

@@ -63,7 +63,7 @@ SEGMENT_RADIUS = (
 )
 
 # Tensor ids for per-tensor seed streams.
-_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR = range(1, 8)
+_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR, _TID_RES = range(1, 9)
 
 
 def rng(seed: int, tensor_id: int) -> np.random.Generator:
@@ -165,6 +165,22 @@ def mlp_weights(seed: int, widths) -> List[np.ndarray]:
         a = math.sqrt(6.0 / (fan_in + fan_out))
         out.append(g.uniform(-a, a, (fan_out, fan_in)).astype(np.float32))
     return out
+
+
+RES_SHAPES = ((64, 32), (64, 64), (64, 64), (64, 96), (3, 64))   # residual motion network W1..W5 [out, in]
+
+
+def residual_weights(seed: int, out_scale: float = 0.05, n_joints: int = N_JOINTS):
+    """Seeded weights of the residual motion network: W1..W5 in RES_SHAPES
+    and W_omega [64, 3 n_joints], Xavier-uniform; the output layer W5 is
+    scaled by out_scale so that offsets stay a few hundredths of the box."""
+    g = rng(seed, _TID_RES)
+    ws = []
+    for fan_out, fan_in in RES_SHAPES + ((64, 3 * n_joints),):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        ws.append(g.uniform(-a, a, (fan_out, fan_in)).astype(np.float32))
+    ws[4] *= np.float32(out_scale)
+    return ws[:5], ws[5]
 
 
 # ---------------------------------------------------------------------------

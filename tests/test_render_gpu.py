@@ -109,6 +109,23 @@ def test_full_size_body_frame_sampled():
     assert 0.27 <= (g[:, 3] > 0.5).mean() <= 0.33
 
 
+def test_mixed_1024_frame_sampled_psnr():
+    # The mixed-precision workload at its measured size (1024x1024, 192 spp):
+    # full frame on the GPU, the oracle on a band through the body plus a
+    # strided grid of pixels; PSNR over all sampled pixels and over those
+    # that hit the body.
+    sc = scenes.scene_body(H=1024, W=1024, spp=192)
+    g = gpu_render(sc, table_dtype=1, mlp_dtype=2)
+    pid = np.unique(np.concatenate([np.arange(500 * 1024 + 256, 500 * 1024 + 768),
+                                    np.array([v * 1024 + u for v in range(11, 1024, 61) for u in range(5, 1024, 53)])]))
+    o = oracle_render(sc, pixel_ids=pid)
+    _report("mixed 1024x1024x192 sampled", g[pid], o)
+    hit = o[:, 3] > 0
+    assert hit.sum() > 100
+    assert psnr(g[pid, :3], o[:, :3]) >= 45.0
+    assert psnr(g[pid][hit, :3], o[hit, :3]) >= 45.0
+
+
 def test_frame_and_ray_list_kernels_agree():
     # Full frames go through the 8x8 ray-packet kernel, explicit ray lists
     # through the per-ray chunk kernel; the two agree within the early
