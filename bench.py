@@ -95,8 +95,10 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
 
-def render_bench(sc, table_dt, mlp_dt, steps, warmup):
+def render_bench(sc, table_dt, mlp_dt, steps, warmup, residual=None):
     fld, _ = m.upload_scene(sc, "cuda", table_dt, mlp_dt)
+    if residual is not None:
+        fld.set_residual(*residual)
     pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
     cam = m.make_camera(sc.cam)
     opts = m.make_opts(ert_tau=1e-6)
@@ -392,6 +394,18 @@ def main():
             "speedup_vs_fp32": fp32["kernel_ms"] / mixed["kernel_ms"], "dtype": "fp16 table, bf16 MLP (fp32 acc)",
             "roofline": dict(roofline(mixed, sc, "f16", "bf16", widths)[0],
                              traffic=measured_traffic("render_fwd_mixed_512x512x128"))}
+        # Residual non-rigid motion network on (all four bands open).
+        rb = render_bench(sc, m.F16, m.BF16, args.steps, args.warmup, residual=(*scenes.residual_weights(21), 4.0))
+        res_flop = 2 * (64 * 32 + 2 * 64 * 64 + 64 * 96 + 3 * 64)
+        k_s = rb["kernel_ms"] * 1e-3
+        line["mixed_512_residual"] = {
+            "Msamples_per_s": nominal / k_s / 1e6, "frames_per_s": 1e3 / rb["kernel_ms"],
+            "cost_vs_mixed": rb["kernel_ms"] / mixed["kernel_ms"], "evaluated_samples": rb["n_eval"],
+            "roofline_mfma": {"bound": "mfma", "achieved": rb["n_eval"] * (mlp_flops(widths) + res_flop) / k_s / 1e12,
+                              "peak": MFMA_PEAK["bf16"], "unit": "TFLOP/s"}}
+        line["mixed_512_residual"]["roofline_mfma"]["frac"] = (line["mixed_512_residual"]["roofline_mfma"]["achieved"]
+                                                               / MFMA_PEAK["bf16"])
+        del rb
         sc3 = scenes.scene_body(H=1024, W=1024, spp=192)
         big = render_bench(sc3, m.F16, m.BF16, max(3, args.steps // 4), 1)
         line["mixed_1024_192spp"] = {

@@ -118,6 +118,22 @@ typedef struct {
   float box_min[3], box_max[3];
   const float* weights;
   const float* packed;
+  /* Residual non-rigid motion (Sec. 4.3, Eq. 11-12), optional: res_w[0] ==
+   * NULL turns it off.  Otherwise dev BF16 row-major weights
+   *   res_w[0] W1 [64][32], res_w[1] W2 [64][64], res_w[2] W3 [64][64],
+   *   res_w[3] W4 [64][96], res_w[4] W5 [3][64], res_w[5] W_omega [64][3 n_bones]
+   * of  h1 = ReLU(W1 g + W_omega Omega), h2 = ReLU(W2 h1), h3 = ReLU(W3 h2),
+   *     h4 = ReLU(W4 [h3; g]) (skip connection at the 4th layer), x_res = W5 h4,
+   * where Omega is the rendered pose's axis angles (joint-major) and
+   *   g = [x, for k = 0..3: w_k sin(2^k pi x_c), w_k cos(2^k pi x_c) (c = 0..2),
+   *        five zeros],  w_k = (1 - cos(pi clamp(res_alpha - k, 0, 1))) / 2
+   * (a truncated Hann window over the frequency bands; res_alpha = 4 opens
+   * all of them), x = x_skel.  The field is then queried at x_skel + x_res.
+   * Runs on BF16 MFMA with FP32 accumulation, so it needs mlp_dtype ==
+   * MNR_BF16; forward only: mnr_render_backward, mnr_train_step and the
+   * server return MNR_E_UNSUPPORTED when it is on. */
+  const void* res_w[6];
+  float res_alpha;
 } mnr_motion;
 
 /* Size in bytes of the packed copy: n_bones * res * (res+1)^2 * 16

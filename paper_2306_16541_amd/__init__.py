@@ -48,7 +48,8 @@ class Field(C.Structure):
 
 class Motion(C.Structure):
     _fields_ = [("n_bones", C.c_int32), ("res", C.c_int32), ("box_min", C.c_float * 3),
-                ("box_max", C.c_float * 3), ("weights", C.c_void_p), ("packed", C.c_void_p)]
+                ("box_max", C.c_float * 3), ("weights", C.c_void_p), ("packed", C.c_void_p),
+                ("res_w", C.c_void_p * 6), ("res_alpha", C.c_float)]
 
 
 class Pose(C.Structure):
@@ -227,6 +228,22 @@ class DeviceField:
             m.packed = self.packed.data_ptr()
         self.m = m
         self.repack()
+
+    def set_residual(self, weights: Sequence, w_omega, alpha: float = 4.0) -> None:
+        """Turn on the residual motion network (include/metanerf.h, mnr_motion):
+        FP32 W1..W5 and W_omega (arrays or tensors), stored as BF16 copies
+        made by the library's conversion kernel; alpha = Hann window position."""
+        dev = self.table.device
+        ws = [torch.as_tensor(np.asarray(w, dtype=np.float32), device=dev) for w in list(weights) + [w_omega]]
+        self.res_w = [convert(w.contiguous(), BF16) for w in ws]
+        for k, w in enumerate(self.res_w):
+            self.m.res_w[k] = w.data_ptr()
+        self.m.res_alpha = float(alpha)
+
+    def clear_residual(self) -> None:
+        for k in range(6):
+            self.m.res_w[k] = None
+        self.res_w = None
 
     def repack(self) -> None:
         if self.dense_packed is not None:

@@ -72,6 +72,13 @@ mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_po
   if (m->packed && m->res > MAX_PACKED_RES)
     return fail(MNR_E_SHAPE, "motion: packed copy needs res <= %d, got %d", MAX_PACKED_RES, m->res);
   if (m->packed && ((uintptr_t)m->packed & 15)) return fail(MNR_E_INVALID, "motion: packed copy not 16-byte aligned");
+  if (m->res_w[0]) {
+    for (int k = 1; k < 6; ++k)
+      if (!m->res_w[k]) return fail(MNR_E_INVALID, "motion: residual weight %d is null", k);
+    if (!std::isfinite(m->res_alpha)) return fail(MNR_E_INVALID, "motion: non-finite res_alpha");
+    if (f->mlp_dtype != MNR_BF16)
+      return fail(MNR_E_UNSUPPORTED, "motion: the residual motion network needs the BF16 MLP path");
+  }
   if (!c) return fail(MNR_E_INVALID, "camera: null pointer");
   if (!(c->fx > 0) || !(c->fy > 0) || !std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) ||
       !std::isfinite(c->cy))
@@ -139,6 +146,15 @@ void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr
   a.m.packed = (const f4*)m->packed;
   a.m.res = m->res;
   a.m.n_bones = m->n_bones;
+  if (m->res_w[0]) {
+    for (int k = 0; k < 6; ++k) a.res.w[k] = (const __bf16*)m->res_w[k];
+    for (int k = 0; k < 4; ++k) {  // truncated Hann window over the bands
+      const double t = std::fmin(std::fmax((double)m->res_alpha - k, 0.0), 1.0);
+      a.res.win[k] = (float)(0.5 * (1.0 - std::cos(M_PI * t)));
+    }
+    a.res.n_omega = 3 * p->n_joints;
+    for (int j = 0; j < 3 * p->n_joints; ++j) a.res.omega[j] = p->axis_angle[j];
+  }
   double G[MNR_MAX_BONES * 12];
   fk_bones_f64(p, G);
   for (int j = 0; j < p->n_joints; ++j)
@@ -221,6 +237,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                void* workspace, void* stream) {
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
+  if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the residual motion network");
   if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
   for (int k = 0; k < field->n_layers; ++k)
     if (!grad_w[k]) return fail(MNR_E_INVALID, "backward: null grad_w[%d]", k);
@@ -339,6 +356,7 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   clear_error();
   if (!st || !target) return fail(MNR_E_INVALID, "train_step: null state or target");
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, st->rgba)) return s;
+  if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the residual motion network");
   if (!st->table_master || !st->table_grad || !st->table_m || !st->table_v || !st->weights_grad || !st->grad_rgba ||
       !st->loss || !st->t_chunks)
     return fail(MNR_E_INVALID, "train_step: null state buffer");

@@ -69,9 +69,18 @@ struct RayArgs {
   uint64_t seed;
 };
 
+// Residual non-rigid motion network (BF16 weights; w[0] == NULL: off).
+struct ResArgs {
+  const __bf16* w[6];  // W1 [64][32], W2 [64][64], W3 [64][64], W4 [64][96], W5 [3][64], W_omega [64][n_omega]
+  float win[4];        // Hann window weight of each frequency band
+  float omega[MNR_MAX_BONES * 3];
+  int32_t n_omega;
+};
+
 struct RenderArgs {
   FieldArgs f;
   MotionArgs m;
+  ResArgs res;
   RayArgs r;
   float G[MNR_MAX_BONES][12];
   float* out;                        // [n_rays][4]

@@ -380,14 +380,21 @@ __device__ __forceinline__ bf16x8 pack_bf16(f4 lo, f4 hi) {
   return b;
 }
 
-// One dense layer: out[mt] = W x, K = 16 * (number of input tiles).
-template <int P, int MT, int KT>
-__device__ __forceinline__ void mma_layer(const char* wl, const f4 (&x)[4], f4 (&out)[4], int lane) {
+// One dense layer: out[mt] = W x (+ bias), K = 16 * KT input tiles.  The
+// optional bias (LDS floats, one per output row) initialises the
+// accumulators: lane j + 16g, element e of tile mt is row 16 mt + 4 g + e.
+template <int P, int MT, int KT, int NX>
+__device__ __forceinline__ void mma_layer(const char* wl, const f4 (&x)[NX], f4 (&out)[4], int lane,
+                                          const float* bias = nullptr) {
+  static_assert(KT <= NX, "input tiles");
+  auto acc0 = [&](int mt) {
+    return bias ? *(const f4*)(bias + 16 * mt + 4 * (lane >> 4)) : f4{0.f, 0.f, 0.f, 0.f};
+  };
   if constexpr (P == MNR_F32) {
     const f4* W = (const f4*)wl;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      f4 acc = acc0(mt);
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
         const f4 a = W[(mt * KT + t) * 64 + lane];
@@ -404,7 +411,7 @@ __device__ __forceinline__ void mma_layer(const char* wl, const f4 (&x)[4], f4 (
     for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      f4 acc = acc0(mt);
 #pragma unroll
       for (int s = 0; s < KS; ++s)
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
@@ -483,7 +490,95 @@ __device__ __forceinline__ float sample_jitter(const RayArgs& r, int ray_index, 
   return (float)(splitmix64(r.seed, (uint64_t)ray_index * r.spp + i) >> 40) * 0x1p-24f;
 }
 
-template <typename TableT, int P, int NHH>
+// ---------------------------------------------------------------------------
+// Residual non-rigid motion (Sec. 4.3, Eq. 11-12) on BF16 MFMA: the same
+// fragment layouts as the field's MLP.  LDS: W1 (64x32), W2, W3 (64x64),
+// W4 (64x96: the skip connection appends gamma's two input tiles to h3's
+// four), W5 (3 rows padded to 16), then the per-frame pose term W_omega
+// Omega as 64 floats (the first layer's bias).
+// ---------------------------------------------------------------------------
+
+struct ResShape {
+  static constexpr int FRAG = 64 * 16;
+  static constexpr int W1 = 4 * 1 * FRAG, W2 = 4 * 2 * FRAG, W3 = 4 * 2 * FRAG, W4 = 4 * 3 * FRAG, W5 = 2 * FRAG;
+  static constexpr int o2 = W1, o3 = o2 + W2, o4 = o3 + W3, o5 = o4 + W4, obias = o5 + W5;
+  static constexpr int bytes() { return obias + 64 * 4; }
+};
+
+__device__ void stage_residual(char* lds, const ResArgs& r) {
+  stage_layer<MNR_BF16>(lds, r.w[0], HIDDEN, 32, HIDDEN);
+  stage_layer<MNR_BF16>(lds + ResShape::o2, r.w[1], HIDDEN, HIDDEN, HIDDEN);
+  stage_layer<MNR_BF16>(lds + ResShape::o3, r.w[2], HIDDEN, HIDDEN, HIDDEN);
+  stage_layer<MNR_BF16>(lds + ResShape::o4, r.w[3], HIDDEN, HIDDEN + 32, HIDDEN);
+  stage_layer<MNR_BF16>(lds + ResShape::o5, r.w[4], 3, HIDDEN, 16);
+  float* bias = (float*)(lds + ResShape::obias);
+  for (int i = threadIdx.x; i < HIDDEN; i += blockDim.x) {
+    float b = 0.f;
+    for (int j = 0; j < r.n_omega; ++j) b = fmaf((float)r.w[5][i * r.n_omega + j], r.omega[j], b);
+    bias[i] = b;
+  }
+}
+
+// x_skel += x_res for the live lanes of the wave.  gamma goes through the
+// wave's feature buffer (layer-1 input layout, read again by the skip
+// layer); tile nt's outputs are carried back to their lanes through obuf.
+__device__ __forceinline__ void residual_step(const ResArgs& r, const char* rl, char* feat, f4* obuf, SampleState& st,
+                                              uint64_t live_mask, int lane) {
+  float g[32];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] = st.xs[c];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float sv, cv;
+      sincospif((float)(1 << k) * st.xs[c], &sv, &cv);  // sin, cos of 2^k pi x_c
+      g[3 + 6 * k + c] = r.win[k] * sv;
+      g[6 + 6 * k + c] = r.win[k] * cv;
+    }
+  }
+#pragma unroll
+  for (int i = 27; i < 32; ++i) g[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    store_feat2<MNR_BF16>(feat, lane, 2 * i, st.live ? f2{g[2 * i], g[2 * i + 1]} : f2{0.f, 0.f});
+  wave_sync_lds();
+  const float* bias = (const float*)(rl + ResShape::obias);
+#pragma unroll 1
+  for (int nt = 0; nt < 4; ++nt) {
+    f4 o = {0.f, 0.f, 0.f, 0.f};
+    if ((live_mask >> (16 * nt)) & 0xFFFFull) {
+      f4 x[4], h[4], h2[4];
+      load_input<MNR_BF16>(feat, nt, lane, x);
+      mma_layer<MNR_BF16, 4, 2>(rl, x, h, lane, bias);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(h[mt]);
+      mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o2, h, h2, lane);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+      mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o3, h2, h, lane);
+      const f4 cat[6] = {relu4(h[0]), relu4(h[1]), relu4(h[2]), relu4(h[3]), x[0], x[1]};
+      mma_layer<MNR_BF16, 4, 6>(rl + ResShape::o4, cat, h2, lane);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+      f4 oo[4];
+      mma_layer<MNR_BF16, 1, 4>(rl + ResShape::o5, h2, oo, lane);
+      o = oo[0];
+    }
+    wave_sync_lds();
+    if (lane < 16) obuf[nt * 16 + lane] = o;
+  }
+  wave_sync_lds();
+  const f4 d = obuf[lane];
+  wave_sync_lds();
+  if (st.live) {
+    st.xs[0] += d[0];
+    st.xs[1] += d[1];
+    st.xs[2] += d[2];
+  }
+}
+
+template <typename TableT, int P, int NHH, bool RES = false>
 __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, int lane, const char* wl, char* feat,
                                                f4* obuf, SampleState& st, f4& out) {
   st.L = 0.f;
@@ -492,6 +587,10 @@ __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, 
   st.live = valid && st.L > 0.f;
   const uint64_t live_mask = __ballot(st.live);
   if (live_mask == 0) return 0;
+  if constexpr (RES) {
+    static_assert(P == MNR_BF16, "the residual motion network runs on the BF16 path");
+    residual_step(a.res, wl + MlpShape<P>::bytes_total(NHH), feat, obuf, st, live_mask, lane);
+  }
 
   float u[3];
   unit_coords(a.f, st.xs, u);
@@ -513,7 +612,7 @@ __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, 
 }
 
 // One 64-sample chunk of a ray (lane i: sample 64 ch + i).
-template <typename TableT, int P, int NHH>
+template <typename TableT, int P, int NHH, bool RES = false>
 __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySetup& rs, int ray_index, int ch,
                                                int lane, const char* wl, char* feat, f4* obuf, SampleState& st,
                                                f4& out) {
@@ -523,7 +622,7 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
   st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
   st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
   st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
-  return field_eval<TableT, P, NHH>(a, valid, lane, wl, feat, obuf, st, out);
+  return field_eval<TableT, P, NHH, RES>(a, valid, lane, wl, feat, obuf, st, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -535,7 +634,7 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
 // and a ray stops once T < ert_tau.  Writes RGBA, optionally the adjoint's
 // saved state, and counts evaluated samples.
 // ---------------------------------------------------------------------------
-template <typename TableT, int P, int NHH>
+template <typename TableT, int P, int NHH, bool RES = false>
 __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile, int wave, int lane, const char* wl,
                                                    char* feat) {
   const int S_ = a.r.spp;
@@ -560,7 +659,7 @@ __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile
       st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
     }
     f4 out;
-    const uint64_t live_mask = field_eval<TableT, P, NHH>(a, act, lane, wl, feat, (f4*)feat, st, out);
+    const uint64_t live_mask = field_eval<TableT, P, NHH, RES>(a, act, lane, wl, feat, (f4*)feat, st, out);
     if (live_mask) {
       live_count += __popcll(live_mask);
       if (st.live) {

@@ -115,6 +115,22 @@ def test_invalid_calls_are_rejected_before_launch():
     assert m.lib.mnr_probe_gather(0x1000, 64, 4, 0, 12, 256, 1, 0x2000, None) == -2
     assert m.lib.mnr_probe_gather(0x1000, 64, 4, 128, 8, 256, 1, 0x2000, None) == -2   # window > table
     assert m.lib.mnr_probe_mfma(1, 10, 1, 0x2000, None) == -3               # F16: unsupported
+    mo.res_w[0], mo.res_alpha = 0x7000, 4.0                                # residual network, F32 MLP
+    for k in range(1, 6):
+        mo.res_w[k] = 0x7000 + 0x1000 * k
+    assert _render(m, f, mo, pose, cam) == -7                              # needs the BF16 path
+    assert "BF16" in m.lib.mnr_last_error().decode()
+    mo.res_w[3] = None
+    assert _render(m, f, mo, pose, cam) == -1                              # a null residual weight
+    mo.res_w[3] = 0xA000
+    f.mlp_dtype = 2
+    gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)
+    assert m.lib.mnr_render_backward(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), 8, 8, 8, None, None, 64,
+                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None) == -7
+    assert "adjoint" in m.lib.mnr_last_error().decode()
+    f.mlp_dtype = 0
+    for k in range(6):
+        mo.res_w[k] = None
     assert m.lib.mnr_probe_atomic(None, 16, 1, 256, 1, 1, None) == -1
     assert m.lib.mnr_probe_atomic(0x2000, 16, 1, 256, 65, 1, None) == -2      # run > 64
 
