@@ -7,3 +7,4 @@ from .render import *  # noqa: F401,F403
 from .render import Field, render_image, render_rays, bone_transforms, camera_rays  # noqa: F401
 from .rng import splitmix64, stratified_xi  # noqa: F401
 from .residual import hann_window, posenc, residual_offset  # noqa: F401
+from .pose import refine, refined_bone_transforms  # noqa: F401
