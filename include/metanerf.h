@@ -148,13 +148,18 @@ mnr_status mnr_motion_pack(const mnr_motion* motion, void* stream);
 
 /* Body pose (Sec. 4.1-4.2): host arrays.  parent[j] < j (root: -1), rest
  * joints [n][3] in the canonical (rest) pose, axis-angle [n][3] of the
- * observed pose theta^o.  Bone transforms G_j (Eq. 8) are computed from it
- * by forward kinematics in double precision on the host. */
+ * estimated pose.  delta (optional, NULL = none): the pose refiner's
+ * adjustments [n][3] (Sec. 4.1, Eq. 5-6); the observed pose theta^o then
+ * rotates joint j by R(delta_j) R(axis_angle_j).  Bone transforms G_j
+ * (Eq. 8) are computed from it by forward kinematics in double precision on
+ * the host.  (The residual motion network is conditioned on axis_angle and
+ * is rejected with MNR_E_UNSUPPORTED together with delta.) */
 typedef struct {
   int32_t n_joints;
   const int32_t* parent;
   const float* rest_joints;
   const float* axis_angle;
+  const float* delta;
 } mnr_pose;
 
 /* Pinhole camera, x_cam = R_wc * X + T (R_wc row-major); pixel (u, v) =
@@ -192,6 +197,31 @@ const char* mnr_version(void);
  * (the inverse of bone j's skinning transform). */
 mnr_status mnr_fk_bones(const mnr_pose* pose, float* G_out);
 
+/* Adjoint of mnr_fk_bones (host, double precision, exact derivatives by
+ * forward-mode dual numbers): given grad_G (host [n][3][4], dL/dG), writes
+ * dL/d(delta) to grad_delta and dL/d(axis_angle) to grad_axis_angle (host
+ * [n][3] each; either may be NULL).  mnr_render_backward's grad_bones is
+ * the device-side source of grad_G. */
+mnr_status mnr_fk_backward(const mnr_pose* pose, const float* grad_G, float* grad_delta, float* grad_axis_angle);
+
+/* Pose refiner MLP_theta (Sec. 4.1, Eq. 5): delta = W_L ReLU(... ReLU(W_1
+ * Omega)), Omega = the pose's axis angles flattened (3 n values), no
+ * biases.  Host weights w[k] row-major [width[k+1]][width[k]], width[0] =
+ * width[n_layers] = 3 n_joints, hidden widths <= 1024, 1 <= n_layers <= 4.
+ * Evaluated on the host in double precision: it runs once per frame. */
+typedef struct {
+  int32_t n_layers;
+  int32_t width[MNR_MAX_LAYERS + 1];
+  const float* w[MNR_MAX_LAYERS];
+} mnr_refiner;
+
+/* delta (host [n][3]) = MLP_theta(omega), omega host [n][3]. */
+mnr_status mnr_refiner_apply(const mnr_refiner* refiner, int32_t n_joints, const float* omega, float* delta);
+/* Accumulate dL/dw[k] into grad_w[k] (host, same shapes as w) given
+ * grad_delta = dL/d(delta) (host [n][3]). */
+mnr_status mnr_refiner_backward(const mnr_refiner* refiner, int32_t n_joints, const float* omega,
+                                const float* grad_delta, float* const* grad_w);
+
 /* Render rays (Sec. 4, Fig. 2; Eq. 3, 7-9, 13).  pixel_ids: dev int32
  * [n_rays] pixel indices of an H x W image, or NULL for the full frame in
  * row-major order (then n_rays must equal H*W).  Ids outside [0, H*W)
@@ -216,6 +246,10 @@ mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mn
  *   grad_table   dev float [n_levels][2^log2_T][n_feat]
  *   grad_w[k]    dev float [width[k+1]][width[k]]
  *   grad_weights dev float [n_bones + 1][res^3]   (dL/dW^c)
+ *   grad_bones   dev float [n_bones][3][4]         (dL/dG_j of Eq. 8; optional,
+ *                NULL skips it): through the warp's points G_j x and its
+ *                blend weights, per wave summed before one atomic per entry;
+ *                mnr_fk_backward carries it on to the pose.
  * Gradients are those of the forward actually computed (early termination
  * included).  Summation order of the atomics is not deterministic. */
 mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
@@ -223,7 +257,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
                                int32_t n_rays, const float* t_chunks, const float* grad_rgba,
                                float* grad_table, float* const* grad_w, float* grad_weights,
-                               void* workspace, void* stream);
+                               float* grad_bones, void* workspace, void* stream);
 
 /* Squared-error loss of Eq. 14's MSE term over RGB: loss = mean over rays
  * and channels of (rgb - target)^2.  target: dev [n_rays][3].  Writes

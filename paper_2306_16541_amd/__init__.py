@@ -54,7 +54,7 @@ class Motion(C.Structure):
 
 class Pose(C.Structure):
     _fields_ = [("n_joints", C.c_int32), ("parent", C.c_void_p), ("rest_joints", C.c_void_p),
-                ("axis_angle", C.c_void_p)]
+                ("axis_angle", C.c_void_p), ("delta", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -96,7 +96,8 @@ _RENDER_COMMON = [C.POINTER(Field), C.POINTER(Motion), C.POINTER(Pose), C.POINTE
                   C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_int32]
 _sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_render_backward", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
-                                                       C.c_void_p, C.c_void_p])
+                                                       C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_fk_backward", C.c_int, [C.POINTER(Pose), C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_mse_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_softmax_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
 _sig("mnr_softmax_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
@@ -117,7 +118,8 @@ _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainSta
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
-            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic"]
+            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_fk_backward", "mnr_refiner_apply",
+            "mnr_refiner_backward"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -156,13 +158,16 @@ def version() -> str:
 # ---------------------------------------------------------------------------
 
 class PoseHost:
-    """Keeps the host arrays of an mnr_pose alive."""
+    """Keeps the host arrays of an mnr_pose alive.  delta: optional pose
+    refiner adjustments [n, 3] (joint j rotates by R(delta_j) R(axis_angle_j))."""
 
-    def __init__(self, parents, rest_joints, axis_angle):
+    def __init__(self, parents, rest_joints, axis_angle, delta=None):
         self.parents = np.ascontiguousarray(parents, dtype=np.int32)
         self.rest = np.ascontiguousarray(rest_joints, dtype=np.float32)
         self.aa = np.ascontiguousarray(axis_angle, dtype=np.float32)
-        self.c = Pose(int(self.parents.shape[0]), self.parents.ctypes.data, self.rest.ctypes.data, self.aa.ctypes.data)
+        self.delta = None if delta is None else np.ascontiguousarray(delta, dtype=np.float32).reshape(-1, 3)
+        self.c = Pose(int(self.parents.shape[0]), self.parents.ctypes.data, self.rest.ctypes.data, self.aa.ctypes.data,
+                      None if self.delta is None else self.delta.ctypes.data)
 
 
 def make_camera(cam, box_min=(-0.5,) * 3, box_max=(0.5,) * 3) -> Camera:
@@ -338,14 +343,82 @@ def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp:
 
 def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts],
                     pixel_ids: Optional[torch.Tensor], t_chunks: torch.Tensor, grad_rgba: torch.Tensor,
-                    grad_table: torch.Tensor, grad_w: List[torch.Tensor], grad_weights: torch.Tensor) -> None:
+                    grad_table: torch.Tensor, grad_w: List[torch.Tensor], grad_weights: torch.Tensor,
+                    grad_bones: Optional[torch.Tensor] = None) -> None:
+    """Accumulates the adjoint into the gradient buffers; grad_bones
+    (optional, [n_bones, 3, 4]) receives dL/dG of the bone transforms."""
     n = H * W if pixel_ids is None else int(pixel_ids.numel())
     gw = (C.c_void_p * len(grad_w))(*[g.data_ptr() for g in grad_w])
     check(lib.mnr_render_backward(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                                   None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(t_chunks),
                                   _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights),
-                                  _ptr(_workspace(grad_table.device)), _stream()),
+                                  _ptr(grad_bones), _ptr(_workspace(grad_table.device)), _stream()),
           "render_backward")
+
+
+def fk_backward(pose: PoseHost, grad_G: np.ndarray):
+    """Host adjoint of the forward kinematics: (dL/d delta, dL/d axis_angle),
+    each [n, 3], from dL/dG [n, 3, 4]."""
+    n = pose.parents.shape[0]
+    g = np.ascontiguousarray(grad_G, dtype=np.float32)
+    gd = np.zeros((n, 3), np.float32)
+    ga = np.zeros((n, 3), np.float32)
+    check(lib.mnr_fk_backward(C.byref(pose.c), g.ctypes.data, gd.ctypes.data, ga.ctypes.data), "fk_backward")
+    return gd, ga
+
+
+class Refiner(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.c_int32 * (MAX_LAYERS + 1)), ("w", C.c_void_p * MAX_LAYERS)]
+
+
+_sig("mnr_refiner_apply", C.c_int, [C.POINTER(Refiner), C.c_int32, C.c_void_p, C.c_void_p])
+_sig("mnr_refiner_backward", C.c_int, [C.POINTER(Refiner), C.c_int32, C.c_void_p, C.c_void_p, _PL])
+
+
+class PoseRefiner:
+    """Host pose refiner MLP_theta (include/metanerf.h, mnr_refiner): FP32
+    weights [out, in] held in numpy arrays, evaluated and differentiated by
+    the library in double precision; Adam (beta 0.9/0.99) on the host."""
+
+    def __init__(self, weights: Sequence[np.ndarray], lr: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
+                 eps: float = 1e-8):
+        self.w = [np.ascontiguousarray(w, dtype=np.float32) for w in weights]
+        self.g = [np.zeros_like(w) for w in self.w]
+        self.m1 = [np.zeros_like(w) for w in self.w]
+        self.m2 = [np.zeros_like(w) for w in self.w]
+        self.lr, self.b1, self.b2, self.eps, self.t = lr, beta1, beta2, eps, 0
+        r = Refiner()
+        r.n_layers = len(self.w)
+        widths = [self.w[0].shape[1]] + [w.shape[0] for w in self.w]
+        r.width[: len(widths)] = widths
+        for k, w in enumerate(self.w):
+            r.w[k] = w.ctypes.data
+        self.c = r
+
+    def apply(self, axis_angle) -> np.ndarray:
+        om = np.ascontiguousarray(axis_angle, dtype=np.float32)
+        d = np.zeros_like(om)
+        check(lib.mnr_refiner_apply(C.byref(self.c), om.shape[0], om.ctypes.data, d.ctypes.data), "refiner_apply")
+        return d
+
+    def backward(self, axis_angle, grad_delta) -> None:
+        """Accumulate dL/dW into self.g."""
+        om = np.ascontiguousarray(axis_angle, dtype=np.float32)
+        gd = np.ascontiguousarray(grad_delta, dtype=np.float32)
+        ptrs = (C.c_void_p * len(self.g))(*[g.ctypes.data for g in self.g])
+        check(lib.mnr_refiner_backward(C.byref(self.c), om.shape[0], om.ctypes.data, gd.ctypes.data,
+                                       C.cast(ptrs, _PL)), "refiner_backward")
+
+    def step(self) -> None:
+        """Adam on the accumulated gradients, then clear them."""
+        self.t += 1
+        for w, g, m1, m2 in zip(self.w, self.g, self.m1, self.m2):
+            m1 *= self.b1; m1 += (1 - self.b1) * g
+            m2 *= self.b2; m2 += (1 - self.b2) * g * g
+            mh = m1 / (1 - self.b1 ** self.t)
+            vh = m2 / (1 - self.b2 ** self.t)
+            w -= (self.lr * mh / (np.sqrt(vh) + self.eps)).astype(np.float32)
+            g[:] = 0
 
 
 def mse_loss(rgba: torch.Tensor, target: torch.Tensor, grad_rgba: torch.Tensor,

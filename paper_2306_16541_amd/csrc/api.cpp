@@ -73,6 +73,7 @@ mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_po
     return fail(MNR_E_SHAPE, "motion: packed copy needs res <= %d, got %d", MAX_PACKED_RES, m->res);
   if (m->packed && ((uintptr_t)m->packed & 15)) return fail(MNR_E_INVALID, "motion: packed copy not 16-byte aligned");
   if (m->res_w[0]) {
+    if (p->delta) return fail(MNR_E_UNSUPPORTED, "motion: residual motion network together with a refined pose");
     for (int k = 1; k < 6; ++k)
       if (!m->res_w[k]) return fail(MNR_E_INVALID, "motion: residual weight %d is null", k);
     if (!std::isfinite(m->res_alpha)) return fail(MNR_E_INVALID, "motion: non-finite res_alpha");
@@ -234,7 +235,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
                                const int32_t* pixel_ids, int32_t n_rays, const float* t_chunks,
                                const float* grad_rgba, float* grad_table, float* const* grad_w, float* grad_weights,
-                               void* workspace, void* stream) {
+                               float* grad_bones, void* workspace, void* stream) {
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
   if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the residual motion network");
@@ -249,6 +250,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
   a.grad_table = grad_table;
   for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = grad_w[k];
   a.grad_weights = grad_weights;
+  a.grad_G = grad_bones;
   a.queues = (int32_t*)workspace;
   if (workspace) {
     if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, (hipStream_t)stream), "workspace")) return s;

@@ -92,6 +92,7 @@ struct RenderArgs {
   float* grad_table;
   float* grad_w[MNR_MAX_LAYERS];
   float* grad_weights;
+  float* grad_G;                     // optional [n_bones][12]
 };
 
 // Server tick work table (device memory, uploaded per tick).

@@ -18,7 +18,8 @@
 //      consecutive samples in the same cell are summed in the wave first;
 //   4. skinning adjoint (Eq. 7, 9): dx_skel/dw_i = (y_i - x_skel)/L and the
 //      likelihood term dalpha'/dL = alpha [L < 1], scattered through the
-//      trilinear weights into dL/dW^c.
+//      trilinear weights into dL/dW^c; optionally dL/dG_i through the
+//      points y_i = G_i x and the weights' spatial gradient.
 #include "field_device.h"
 #include "kernels.h"
 
@@ -435,6 +436,32 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         for (int k = 0; k < 8; ++k)
           v[k] = gw * ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
                  ((k & 4) ? t.f[2] : 1.f - t.f[2]);
+        if (a.grad_G) {  // uniform: dL/dG_b = dL/dy_b [x 1]^T, summed over the wave
+          // dL/dy_b = w_b / max(L, eps) dL/dx_skel + dL/dw_b grad_y w_b(y_b)
+          float c[8];
+          bone_corners(a.m, b, t, c);
+          const float w = trilerp(c, t.f);
+          const float fx = t.f[0], fy = t.f[1], fz = t.f[2];
+          const float x00 = c[0] + fx * (c[1] - c[0]), x10 = c[2] + fx * (c[3] - c[2]);
+          const float x01 = c[4] + fx * (c[5] - c[4]), x11 = c[6] + fx * (c[7] - c[6]);
+          const float y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
+          const float dqx = ((1.f - fy) * (1.f - fz)) * (c[1] - c[0]) + (fy * (1.f - fz)) * (c[3] - c[2]) +
+                            ((1.f - fy) * fz) * (c[5] - c[4]) + (fy * fz) * (c[7] - c[6]);
+          const float dqy = (1.f - fz) * (x10 - x00) + fz * (x11 - x01);
+          const float dqz = y1 - y0;
+          // (cells clamped to the volume's padding hold zeros: no weight, no gradient)
+          const float gy[3] = {w * invL * g_xs[0] + gw * dqx * a.m.mscale[0],
+                               w * invL * g_xs[1] + gw * dqy * a.m.mscale[1],
+                               w * invL * g_xs[2] + gw * dqz * a.m.mscale[2]};
+          const float xh[4] = {st.x[0], st.x[1], st.x[2], 1.f};
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const float s = wave_sum(live ? gy[r] * xh[k] : 0.f);
+              if (lane == 0) unsafeAtomicAdd(a.grad_G + b * 12 + r * 4 + k, s);
+            }
+        }
         const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
         run_sums<8>(cr, v);
         if (live && cr.head) {

@@ -126,7 +126,7 @@ def test_invalid_calls_are_rejected_before_launch():
     f.mlp_dtype = 2
     gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)
     assert m.lib.mnr_render_backward(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), 8, 8, 8, None, None, 64,
-                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None) == -7
+                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None, None) == -7
     assert "adjoint" in m.lib.mnr_last_error().decode()
     f.mlp_dtype = 0
     for k in range(6):
