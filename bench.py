@@ -246,6 +246,13 @@ def train_bench(steps, warmup):
     for t in [b["table_grad"], b["weights_grad"]] + b["w_grad"]:
         t.zero_()
     _, bwd_ms = timed_launches(bwd, steps, 1)
+    gG = torch.zeros(24, 3, 4, device=dev)
+
+    def bwd_pose():
+        m.render_backward(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, g_rgba, b["table_grad"],
+                          b["w_grad"], b["weights_grad"], grad_bones=gG)
+    _, bwd_pose_ms = timed_launches(bwd_pose, steps, 1)
+    res["adjoint_with_bone_grads_ms"] = bwd_pose_ms
     atomics = n_eval * (16 * 8 * 2 + 24 * 8)
     res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
     res["evaluated_samples"] = n_eval
