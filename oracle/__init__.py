@@ -8,3 +8,4 @@ from .render import Field, render_image, render_rays, bone_transforms, camera_ra
 from .rng import splitmix64, stratified_xi  # noqa: F401
 from .residual import hann_window, posenc, residual_offset  # noqa: F401
 from .pose import refine, refined_bone_transforms  # noqa: F401
+from .skel_cnn import skel_cnn_logits  # noqa: F401
