@@ -253,6 +253,12 @@ def train_bench(steps, warmup):
                           b["w_grad"], b["weights_grad"], grad_bones=gG)
     _, bwd_pose_ms = timed_launches(bwd_pose, steps, 1)
     res["adjoint_with_bone_grads_ms"] = bwd_pose_ms
+    # skeleton-motion CNN (32^3 x 25 logits from the 256-d latent): forward and adjoint per step
+    cnn = m.SkeletonCNN(*scenes.skel_cnn_weights(5))
+    glog = torch.ones(25, 32, 32, 32, device=dev)
+    _, cnn_f = timed_launches(lambda: cnn.forward(), steps, 1)
+    _, cnn_b = timed_launches(lambda: cnn.backward(glog), steps, 1)
+    res["skel_cnn_ms"] = {"forward": cnn_f, "adjoint": cnn_b}
     atomics = n_eval * (16 * 8 * 2 + 24 * 8)
     res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
     res["evaluated_samples"] = n_eval

@@ -283,6 +283,36 @@ mnr_status mnr_adam_step(float* param, const float* grad, float* m, float* v, in
                          float lr, float beta1, float beta2, float eps, int32_t step,
                          void* lowp, mnr_dtype lowp_dtype, void* stream);
 
+/* Skeleton-motion CNN (Sec. 4.2, Eq. 10, Fig. 7): the source of the
+ * canonical blend-weight logits, from a constant latent z:
+ *   a0 = LeakyReLU(w_fc z)                       (c0 channels at one voxel)
+ *   a_k = LeakyReLU(TConv_k(a_{k-1})), k = 1..4, logits = TConv_5(a_4),
+ * TConv = 3-D transposed convolution, kernel 4, stride 2, padding 1 (the
+ * grid doubles 1 -> 32), LeakyReLU slope 0.2, no biases.  logits: dev
+ * [c5][32^3], x fastest; c5 = n_bones + 1 feeds mnr_softmax_fwd for a
+ * motion volume of res 32.  Dev FP32 weights: w_fc [c0][latent],
+ * w[k] [c_k][c_{k+1}][4][4][4] (input channel, output channel, kz, ky,
+ * kx).  1 <= latent <= 4096, 1 <= c_k <= 1024. */
+typedef struct {
+  int32_t latent;
+  int32_t channels[6];
+  const float* z;
+  const float* w_fc;
+  const float* w[5];
+} mnr_skel_cnn;
+
+/* Floats of the activations a0..a4 the forward saves for the adjoint, and
+ * of the adjoint's scratch; 0 for an invalid network. */
+uint64_t mnr_skel_cnn_act_floats(const mnr_skel_cnn* cnn);
+uint64_t mnr_skel_cnn_scratch_floats(const mnr_skel_cnn* cnn);
+/* act: dev [mnr_skel_cnn_act_floats]; logits: dev [c5][32^3]. */
+mnr_status mnr_skel_cnn_forward(const mnr_skel_cnn* cnn, float* act, float* logits, void* stream);
+/* ACCUMULATES dL/dw_fc and dL/dw[k] (dev, same shapes) from grad_logits
+ * (dev [c5][32^3]) and the forward's act; scratch: dev
+ * [mnr_skel_cnn_scratch_floats]. */
+mnr_status mnr_skel_cnn_backward(const mnr_skel_cnn* cnn, const float* act, const float* grad_logits,
+                                 float* grad_w_fc, float* const* grad_w, float* scratch, void* stream);
+
 /* dst = round-to-nearest-even(src) in dtype (F16 or BF16); n elements. */
 mnr_status mnr_convert(const float* src, void* dst, mnr_dtype dtype, int64_t n, void* stream);
 /* Zero n_bytes of dev memory with a kernel (safe inside captured graphs). */
@@ -306,7 +336,8 @@ typedef struct {
   void* workspace;                                           /* MNR_WORKSPACE_BYTES, or NULL */
   float lr_field, lr_motion, beta1, beta2, eps;
   int32_t step;                                                           /* 1-based */
-  int32_t train_motion;                                                   /* 0 = logits frozen */
+  int32_t train_motion;  /* 0 = logits frozen; 1 = Adam on the logits; 2 = only dL/dlogits into logits_grad
+                            (their source, e.g. the skeleton-motion CNN, is the caller's to update) */
 } mnr_train_state;
 
 mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,

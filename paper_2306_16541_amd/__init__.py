@@ -119,7 +119,8 @@ EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
             "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_fk_backward", "mnr_refiner_apply",
-            "mnr_refiner_backward"]
+            "mnr_refiner_backward", "mnr_skel_cnn_act_floats", "mnr_skel_cnn_scratch_floats", "mnr_skel_cnn_forward",
+            "mnr_skel_cnn_backward"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -367,6 +368,64 @@ def fk_backward(pose: PoseHost, grad_G: np.ndarray):
     return gd, ga
 
 
+class SkelCnn(C.Structure):
+    _fields_ = [("latent", C.c_int32), ("channels", C.c_int32 * 6), ("z", C.c_void_p), ("w_fc", C.c_void_p),
+                ("w", C.c_void_p * 5)]
+
+
+_sig("mnr_skel_cnn_act_floats", C.c_uint64, [C.POINTER(SkelCnn)])
+_sig("mnr_skel_cnn_scratch_floats", C.c_uint64, [C.POINTER(SkelCnn)])
+_sig("mnr_skel_cnn_forward", C.c_int, [C.POINTER(SkelCnn), C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_skel_cnn_backward", C.c_int, [C.POINTER(SkelCnn), C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
+                                        C.c_void_p])
+
+
+class SkeletonCNN:
+    """Skeleton-motion CNN (include/metanerf.h, mnr_skel_cnn) with its
+    device buffers: latent z, weights, saved activations, gradient and Adam
+    state; the blend-weight logits come out of forward()."""
+
+    def __init__(self, z, w_fc, ws, device="cuda"):
+        t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float32), device=device).contiguous()
+        self.z, self.w_fc, self.ws = t(z), t(w_fc), [t(w) for w in ws]
+        c = SkelCnn()
+        c.latent = int(self.z.numel())
+        c.channels[:] = [int(self.w_fc.shape[0])] + [int(w.shape[1]) for w in self.ws]
+        c.z, c.w_fc = self.z.data_ptr(), self.w_fc.data_ptr()
+        for k, w in enumerate(self.ws):
+            c.w[k] = w.data_ptr()
+        self.c = c
+        na, ns = int(lib.mnr_skel_cnn_act_floats(C.byref(c))), int(lib.mnr_skel_cnn_scratch_floats(C.byref(c)))
+        if na == 0:
+            raise MnrError("skel_cnn: " + lib.mnr_last_error().decode())
+        self.act = torch.zeros(na, device=device)
+        self.scratch = torch.zeros(ns, device=device)
+        self.params = [self.w_fc] + self.ws
+        self.grads = [torch.zeros_like(p) for p in self.params]
+        self.m1 = [torch.zeros_like(p) for p in self.params]
+        self.m2 = [torch.zeros_like(p) for p in self.params]
+        self.t = 0
+
+    def forward(self, logits: Optional[torch.Tensor] = None) -> torch.Tensor:
+        c5 = self.c.channels[5]
+        logits = torch.empty(c5, 32, 32, 32, device=self.z.device) if logits is None else logits
+        check(lib.mnr_skel_cnn_forward(C.byref(self.c), _ptr(self.act), _ptr(logits), _stream()), "skel_cnn_forward")
+        return logits
+
+    def backward(self, grad_logits: torch.Tensor) -> None:
+        """Accumulate dL/dweights into self.grads."""
+        gw = (C.c_void_p * 5)(*[g.data_ptr() for g in self.grads[1:]])
+        check(lib.mnr_skel_cnn_backward(C.byref(self.c), _ptr(self.act), _ptr(grad_logits), _ptr(self.grads[0]),
+                                        C.cast(gw, _PL), _ptr(self.scratch), _stream()), "skel_cnn_backward")
+
+    def step(self, lr: float, beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8) -> None:
+        """Adam (the library's kernel) on every weight, then clear the gradients."""
+        self.t += 1
+        for p, g, m1, m2 in zip(self.params, self.grads, self.m1, self.m2):
+            adam_step(p, g, m1, m2, lr, self.t, beta1, beta2, eps)
+            zero_(g)
+
+
 class Refiner(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("width", C.c_int32 * (MAX_LAYERS + 1)), ("w", C.c_void_p * MAX_LAYERS)]
 
@@ -472,11 +531,16 @@ class Trainer:
     def __init__(self, table32: torch.Tensor, mlp32: Sequence[torch.Tensor], logits32: torch.Tensor, level_res,
                  table_dtype: int = F32, mlp_dtype: int = F32, max_rays: int = 8192, spp: int = 128,
                  lr_field: float = 5e-4, lr_motion: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
-                 eps: float = 1e-8, train_motion: bool = True, box_min=(-0.5,) * 3, box_max=(0.5,) * 3):
+                 eps: float = 1e-8, train_motion: bool = True, box_min=(-0.5,) * 3, box_max=(0.5,) * 3,
+                 skel_cnn: Optional["SkeletonCNN"] = None):
+        """skel_cnn: generate the blend-weight logits with the skeleton-motion
+        CNN (logits32 is then ignored) and train its weights instead of free
+        logits (lr_motion applies to them)."""
         dev = table32.device
         self.table32 = table32.contiguous().clone()
         self.mlp32 = [w.contiguous().clone() for w in mlp32]
-        self.logits = logits32.contiguous().clone()
+        self.cnn = skel_cnn
+        self.logits = logits32.contiguous().clone() if skel_cnn is None else skel_cnn.forward()
         self.weights = softmax_fwd(self.logits)
         self.table = self.table32 if table_dtype == F32 else convert(self.table32, table_dtype)
         self.mlp = self.mlp32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in self.mlp32]
@@ -505,7 +569,7 @@ class Trainer:
         s.t_chunks, s.loss = b["t_chunks"].data_ptr(), b["loss"].data_ptr()
         s.workspace = b["workspace"].data_ptr()
         s.lr_field, s.lr_motion, s.beta1, s.beta2, s.eps = lr_field, lr_motion, beta1, beta2, eps
-        s.step, s.train_motion = 0, int(bool(train_motion))
+        s.step, s.train_motion = 0, (2 if skel_cnn is not None else 1) if train_motion else 0
         self.state = s
 
     def step(self, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, pixel_ids: torch.Tensor,
@@ -518,6 +582,14 @@ class Trainer:
         check(lib.mnr_train_step(C.byref(self.field.c), C.byref(self.field.m), C.byref(pose.c), C.byref(cam), H, W,
                                  spp, C.byref(opts), _ptr(pixel_ids), n, _ptr(target), C.byref(self.state), _stream()),
               "train_step")
+        if self.cnn is not None and self.state.train_motion == 2:
+            # dL/dlogits -> the CNN's weights; regenerate logits, W^c and its packed copy
+            self.cnn.backward(self.buf["logits_grad"])
+            self.cnn.step(self.state.lr_motion, self.state.beta1, self.state.beta2, self.state.eps)
+            self.cnn.forward(self.logits)
+            softmax_fwd(self.logits, out=self.weights)
+            if self.field.packed is not None:
+                check(lib.mnr_motion_pack(C.byref(self.field.m), _stream()), "motion_pack")
 
     def loss(self) -> float:
         return float(self.buf["loss"].item())

@@ -365,7 +365,9 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   for (int k = 0; k < field->n_layers; ++k)
     if (!st->w_master[k] || !st->w_grad[k] || !st->w_m[k] || !st->w_v[k])
       return fail(MNR_E_INVALID, "train_step: null state buffer for layer %d", k);
-  if (st->train_motion && (!st->logits || !st->logits_grad || !st->logits_m || !st->logits_v))
+  if (st->train_motion < 0 || st->train_motion > 2) return fail(MNR_E_INVALID, "train_step: train_motion must be 0, 1 or 2");
+  if (st->train_motion == 2 && !st->logits_grad) return fail(MNR_E_INVALID, "train_step: null logits_grad");
+  if (st->train_motion == 1 && (!st->logits || !st->logits_grad || !st->logits_m || !st->logits_v))
     return fail(MNR_E_INVALID, "train_step: null logits state");
   if (field->table_dtype == MNR_F32 && field->table != st->table_master)
     return fail(MNR_E_INVALID, "train_step: an F32 table must be the master copy itself");
@@ -411,6 +413,8 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   if (st->train_motion) {
     ok(launch_zero(st->logits_grad, n_wc * 4, s));
     ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));
+  }
+  if (st->train_motion == 1) {
     ok(launch_adam(st->logits, st->logits_grad, st->logits_m, st->logits_v, n_wc, st->lr_motion, st->beta1,
                    st->beta2, st->eps, st->step, nullptr, MNR_F32, s));
     ok(launch_softmax_fwd(st->logits, (float*)motion->weights, motion->n_bones + 1, n_vox, s));

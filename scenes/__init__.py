@@ -63,7 +63,7 @@ SEGMENT_RADIUS = (
 )
 
 # Tensor ids for per-tensor seed streams.
-_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR, _TID_RES = range(1, 9)
+_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR, _TID_RES, _TID_CNN = range(1, 10)
 
 
 def rng(seed: int, tensor_id: int) -> np.random.Generator:
@@ -181,6 +181,24 @@ def residual_weights(seed: int, out_scale: float = 0.05, n_joints: int = N_JOINT
         ws.append(g.uniform(-a, a, (fan_out, fan_in)).astype(np.float32))
     ws[4] *= np.float32(out_scale)
     return ws[:5], ws[5]
+
+
+SKEL_CNN_CHANNELS = (256, 128, 64, 32, 32, 25)
+
+
+def skel_cnn_weights(seed: int, channels=SKEL_CNN_CHANNELS, latent: int = 256):
+    """Seeded latent z ~ N(0, 1) and weights of the skeleton-motion CNN:
+    w_fc [c0, latent] and w[k] [c_k, c_{k+1}, 4, 4, 4], uniform with bound
+    sqrt(6 / fan_in) (a transposed-convolution output sums 8 taps per input
+    channel)."""
+    g = rng(seed, _TID_CNN)
+    z = g.standard_normal(latent).astype(np.float32)
+    w_fc = g.uniform(-1, 1, (channels[0], latent)).astype(np.float32) * np.float32(math.sqrt(6.0 / latent))
+    ws = []
+    for k in range(5):
+        a = math.sqrt(6.0 / (8 * channels[k]))
+        ws.append(g.uniform(-a, a, (channels[k], channels[k + 1], 4, 4, 4)).astype(np.float32))
+    return z, w_fc, ws
 
 
 # ---------------------------------------------------------------------------
