@@ -9,3 +9,4 @@ from .rng import splitmix64, stratified_xi  # noqa: F401
 from .residual import hann_window, posenc, residual_offset  # noqa: F401
 from .pose import refine, refined_bone_transforms  # noqa: F401
 from .skel_cnn import skel_cnn_logits  # noqa: F401
+from .freq_field import freq_field, posenc10  # noqa: F401

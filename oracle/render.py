@@ -23,6 +23,8 @@ Steps and where they are defined:
     (MSE term only)
   * optional residual non-rigid motion .... Sec. 4.3, Eq. 11-12
     (oracle/residual.py)
+  * optional frequency-encoded field ...... Sec. 4.4, Eq. 13, Fig. 9 (a Field
+    with encoding = "freq"; oracle/freq_field.py)
 
 Readings of ambiguous passages (each listed in the design doc):
   * Eq. 3: delta_i is the stratum width (t_f - t_n)/S for every sample, so
@@ -339,8 +341,12 @@ def render_rays(field: Field, G: torch.Tensor, o: torch.Tensor, d: torch.Tensor,
                 from .residual import residual_offset
                 x_skel = x_skel + residual_offset(x_skel, residual["omega"], residual["weights"],
                                                   residual["w_omega"], residual["alpha"])
-            feat = grid_encode(x_skel, field.table, field.level_res, field.box_min, field.box_max)
-            rgb, sigma = mlp(feat, field.mlp)
+            if getattr(field, "encoding", "grid") == "freq":
+                from .freq_field import freq_field
+                rgb, sigma = freq_field(x_skel, field.mlp)
+            else:
+                feat = grid_encode(x_skel, field.table, field.level_res, field.box_min, field.box_max)
+                rgb, sigma = mlp(feat, field.mlp)
             C, A, _ = composite(sigma.reshape(nb, S), rgb.reshape(nb, S, 3), L.reshape(nb, S), delta, bgt)
             rgba = rgba.index_put((idx,), torch.cat([C, A[:, None]], 1))
             n_eval += nb * S
