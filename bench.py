@@ -419,6 +419,26 @@ def main():
         line["mixed_512_residual"]["roofline_mfma"]["frac"] = (line["mixed_512_residual"]["roofline_mfma"]["achieved"]
                                                                / MFMA_PEAK["bf16"])
         del rb
+        # The paper's own field: 10-band positional encoding and the skip MLP (BF16), no grid.
+        lg = torch.as_tensor(sc.logits, device="cuda")
+        ffield = m.DeviceField.frequency([m.convert(torch.as_tensor(w, device="cuda"), m.BF16)
+                                          for w in scenes.freq_field_weights(31)], m.softmax_fwd(lg))
+        fpose, fcam = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle), m.make_camera(sc.cam)
+        fout = torch.empty(sc.H * sc.W, 4, device="cuda")
+        fcnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        m.render(ffield, fpose, fcam, sc.H, sc.W, sc.spp, m.make_opts(), out=fout, counter=fcnt)
+        torch.cuda.synchronize()
+        f_eval = int(fcnt.item())
+        _, f_ms = timed_launches(lambda: m.render(ffield, fpose, fcam, sc.H, sc.W, sc.spp, m.make_opts(), out=fout),
+                                 args.steps, args.warmup)
+        f_flop = 2 * (64 * 64 * 3 + 64 * 128 + 4 * 64)
+        line["freq_field_512"] = {
+            "Msamples_per_s": nominal / (f_ms * 1e-3) / 1e6, "frames_per_s": 1e3 / f_ms, "evaluated_samples": f_eval,
+            "roofline_mfma": {"bound": "mfma", "achieved": f_eval * f_flop / (f_ms * 1e-3) / 1e12,
+                              "peak": MFMA_PEAK["bf16"], "unit": "TFLOP/s"}}
+        line["freq_field_512"]["roofline_mfma"]["frac"] = line["freq_field_512"]["roofline_mfma"]["achieved"] / \
+            MFMA_PEAK["bf16"]
+        del ffield
         sc3 = scenes.scene_body(H=1024, W=1024, spp=192)
         big = render_bench(sc3, m.F16, m.BF16, max(3, args.steps // 4), 1)
         line["mixed_1024_192spp"] = {

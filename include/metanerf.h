@@ -38,7 +38,7 @@ extern "C" {
 
 #define MNR_MAX_BONES 32
 #define MNR_MAX_LEVELS 16
-#define MNR_MAX_LAYERS 4
+#define MNR_MAX_LAYERS 5
 #define MNR_MAX_SPP 1024
 /* Bytes of the optional device workspace of the render entry points: eight
  * per-XCD work-queue counters (zeroed by the library on the call's stream
@@ -59,6 +59,7 @@ typedef enum {
 } mnr_status;
 
 typedef enum { MNR_F32 = 0, MNR_F16 = 1, MNR_BF16 = 2 } mnr_dtype;
+typedef enum { MNR_ENC_GRID = 0, MNR_ENC_FREQ = 1 } mnr_encoding;
 
 /* Canonical radiance field (Sec. 4.4, Eq. 13): a multiresolution grid
  * encoding (Mueller et al. 2022, cited in Sec. 2.3) followed by a bias-free
@@ -79,7 +80,20 @@ typedef enum { MNR_F32 = 0, MNR_F16 = 1, MNR_BF16 = 2 } mnr_dtype;
  *     identical results); re-pack after changing `table` (mnr_train_step
  *     does so itself).
  * Supported: n_feat = 2, n_levels * n_feat = width[0] = 32, hidden widths
- * 64, width[n_layers] = 4, 2 <= n_layers <= 4, log2_T <= 24. */
+ * 64, width[n_layers] = 4, 2 <= n_layers <= 4, log2_T <= 24.
+ *
+ * encoding = MNR_ENC_FREQ selects the paper's own field instead (Sec. 4.4,
+ * Eq. 13, Fig. 9): c, sigma = MLP_nerf(gamma(x)) with the positional
+ * encoding gamma(x) = [x, sin(2^k pi x_c), cos(2^k pi x_c) for k = 0..9,
+ * c = 0..2, one zero] (64 values: x, then per band the three sines and the
+ * three cosines) and a skip of gamma into the fourth layer:
+ *   h1 = ReLU(W1 gamma), h2 = ReLU(W2 h1), h3 = ReLU(W3 h2),
+ *   h4 = ReLU(W4 [h3; gamma]), o = W5 h4  (c = sigmoid(o[0:3]), sigma = ReLU(o[3])).
+ * Then n_layers = 5, width = {64, 64, 64, 64, 64, 4} (w[3] is [64][128]:
+ * h3 and gamma), mlp_dtype = MNR_BF16 (BF16 MFMA, FP32 accumulation); the
+ * grid fields (n_levels .. table, dense_packed) are ignored.  Forward only:
+ * mnr_render_backward, mnr_train_step and the server return
+ * MNR_E_UNSUPPORTED for it. */
 typedef struct {
   int32_t n_levels, n_feat, log2_T;
   int32_t level_res[MNR_MAX_LEVELS];
@@ -91,6 +105,7 @@ typedef struct {
   mnr_dtype mlp_dtype;
   const void* w[MNR_MAX_LAYERS];
   const void* dense_packed;
+  int32_t encoding;
 } mnr_field;
 
 /* Size in bytes of the packed copy of the dense levels: for every dense

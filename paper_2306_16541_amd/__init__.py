@@ -19,7 +19,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmetanerf.so")
 
-MAX_BONES, MAX_LEVELS, MAX_LAYERS = 32, 16, 4
+MAX_BONES, MAX_LEVELS, MAX_LAYERS = 32, 16, 5
 F32, F16, BF16 = 0, 1, 2
 _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 
@@ -43,7 +43,7 @@ class Field(C.Structure):
                 ("level_res", C.c_int32 * MAX_LEVELS), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
                 ("table_dtype", C.c_int), ("table", C.c_void_p), ("n_layers", C.c_int32),
                 ("width", C.c_int32 * (MAX_LAYERS + 1)), ("mlp_dtype", C.c_int), ("w", C.c_void_p * MAX_LAYERS),
-                ("dense_packed", C.c_void_p)]
+                ("dense_packed", C.c_void_p), ("encoding", C.c_int32)]
 
 
 class Motion(C.Structure):
@@ -235,11 +235,39 @@ class DeviceField:
         self.m = m
         self.repack()
 
+    @classmethod
+    def frequency(cls, mlp: Sequence[torch.Tensor], weights: torch.Tensor, box_min=(-0.5,) * 3, box_max=(0.5,) * 3,
+                  packed: bool = True) -> "DeviceField":
+        """The paper's own field (include/metanerf.h, MNR_ENC_FREQ): BF16
+        W1..W5 of the 10-band positional encoding's skip MLP, no grid."""
+        self = cls.__new__(cls)
+        self.table, self.mlp, self.weights = None, list(mlp), weights
+        f = Field()
+        f.box_min[:], f.box_max[:] = list(box_min), list(box_max)
+        f.encoding, f.mlp_dtype, f.n_layers = 1, BF16, 5
+        f.width[:6] = [64, 64, 64, 64, 64, 4]
+        for k, w in enumerate(self.mlp):
+            f.w[k] = w.data_ptr()
+        self.c = f
+        self.dense_packed = None
+        m = Motion()
+        m.n_bones, m.res = int(weights.shape[0]) - 1, int(weights.shape[-1])
+        m.box_min[:], m.box_max[:] = list(box_min), list(box_max)
+        m.weights = weights.data_ptr()
+        self.packed = None
+        if packed:
+            nb = int(lib.mnr_motion_packed_bytes(m.res, m.n_bones))
+            self.packed = torch.empty(nb // 4, dtype=torch.float32, device=weights.device)
+            m.packed = self.packed.data_ptr()
+        self.m = m
+        self.repack()
+        return self
+
     def set_residual(self, weights: Sequence, w_omega, alpha: float = 4.0) -> None:
         """Turn on the residual motion network (include/metanerf.h, mnr_motion):
         FP32 W1..W5 and W_omega (arrays or tensors), stored as BF16 copies
         made by the library's conversion kernel; alpha = Hann window position."""
-        dev = self.table.device
+        dev = self.weights.device
         ws = [torch.as_tensor(np.asarray(w, dtype=np.float32), device=dev) for w in list(weights) + [w_omega]]
         self.res_w = [convert(w.contiguous(), BF16) for w in ws]
         for k, w in enumerate(self.res_w):
@@ -335,7 +363,7 @@ def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp:
     pass a work-queue workspace (dynamic load balancing) or not (static split)."""
     n = H * W if pixel_ids is None else int(pixel_ids.numel())
     if out is None:
-        out = torch.empty((n, 4), dtype=torch.float32, device=field.table.device)
+        out = torch.empty((n, 4), dtype=torch.float32, device=field.weights.device)
     check(lib.mnr_render(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                          None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(out), _ptr(t_chunks),
                          _ptr(counter), _ptr(_workspace(out.device)) if dynamic else None, _stream()), "render")

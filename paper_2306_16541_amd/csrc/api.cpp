@@ -36,8 +36,23 @@ static mnr_status check_box(const float* lo, const float* hi, const char* who) {
   return MNR_OK;
 }
 
+static mnr_status validate_freq_field(const mnr_field* f) {
+  if (f->mlp_dtype != MNR_BF16)
+    return fail(MNR_E_UNSUPPORTED, "field: the frequency-encoded field needs the BF16 MLP path");
+  if (f->n_layers != 5) return fail(MNR_E_SHAPE, "field: the frequency-encoded field has 5 layers, got %d", f->n_layers);
+  const int want[6] = {64, 64, 64, 64, 64, 4};
+  for (int k = 0; k < 6; ++k)
+    if (f->width[k] != want[k]) return fail(MNR_E_SHAPE, "field: frequency-field widths must be 64,64,64,64,64,4");
+  for (int k = 0; k < 5; ++k)
+    if (!f->w[k]) return fail(MNR_E_INVALID, "field: null weight pointer for layer %d", k);
+  return check_box(f->box_min, f->box_max, "field");
+}
+
 mnr_status validate_field(const mnr_field* f) {
-  if (!f || !f->table) return fail(MNR_E_INVALID, "field: null pointer");
+  if (!f) return fail(MNR_E_INVALID, "field: null pointer");
+  if (f->encoding == MNR_ENC_FREQ) return validate_freq_field(f);
+  if (f->encoding != MNR_ENC_GRID) return fail(MNR_E_INVALID, "field: unknown encoding %d", f->encoding);
+  if (!f->table) return fail(MNR_E_INVALID, "field: null pointer");
   if (f->n_feat != 2) return fail(MNR_E_SHAPE, "field: n_feat must be 2, got %d", f->n_feat);
   if (f->n_levels < 1 || f->n_levels > MNR_MAX_LEVELS || f->n_levels * f->n_feat != 32)
     return fail(MNR_E_SHAPE, "field: n_levels * n_feat must be 32 (n_levels %d)", f->n_levels);
@@ -47,8 +62,7 @@ mnr_status validate_field(const mnr_field* f) {
       return fail(MNR_E_SHAPE, "field: level_res[%d] = %d out of [1, 65535]", l, f->level_res[l]);
   if (f->table_dtype != MNR_F32 && f->table_dtype != MNR_F16) return fail(MNR_E_DTYPE, "field: table dtype must be F32 or F16");
   if (f->mlp_dtype != MNR_F32 && f->mlp_dtype != MNR_BF16) return fail(MNR_E_DTYPE, "field: MLP dtype must be F32 or BF16");
-  if (f->n_layers < 2 || f->n_layers > MNR_MAX_LAYERS)
-    return fail(MNR_E_SHAPE, "field: n_layers must be in [2, %d], got %d", MNR_MAX_LAYERS, f->n_layers);
+  if (f->n_layers < 2 || f->n_layers > 4) return fail(MNR_E_SHAPE, "field: n_layers must be in [2, 4], got %d", f->n_layers);
   if (f->width[0] != 32 || f->width[f->n_layers] != 4)
     return fail(MNR_E_SHAPE, "field: widths must run 32 -> ... -> 4");
   for (int k = 1; k < f->n_layers; ++k)
@@ -110,8 +124,17 @@ static bool level_is_dense(const mnr_field* f, int l) {
 
 void field_args(FieldArgs& F, const mnr_field* f) {
   std::memset(&F, 0, sizeof(F));
-  F.table = f->table;
   for (int k = 0; k < f->n_layers; ++k) F.w[k] = f->w[k];
+  F.n_layers = f->n_layers;
+  for (int i = 0; i < 3; ++i) {
+    F.gmin[i] = f->box_min[i];
+    F.gscale[i] = (float)(1.0 / ((double)f->box_max[i] - f->box_min[i]));
+  }
+  if (f->encoding == MNR_ENC_FREQ) {  // no grid: levels, table and packed copy unused
+    F.freq = 1;
+    return;
+  }
+  F.table = f->table;
   F.dpk = (const char*)f->dense_packed;
   uint64_t off = 0;
   bool prefix = true;
@@ -128,11 +151,6 @@ void field_args(FieldArgs& F, const mnr_field* f) {
   }
   F.n_levels = f->n_levels;
   F.log2_T = f->log2_T;
-  F.n_layers = f->n_layers;
-  for (int i = 0; i < 3; ++i) {
-    F.gmin[i] = f->box_min[i];
-    F.gscale[i] = (float)(1.0 / ((double)f->box_max[i] - f->box_min[i]));
-  }
 }
 
 void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr_pose* p, const mnr_camera* c,
@@ -239,6 +257,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
   if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the residual motion network");
+  if (field->encoding == MNR_ENC_FREQ) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the frequency-encoded field");
   if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
   for (int k = 0; k < field->n_layers; ++k)
     if (!grad_w[k]) return fail(MNR_E_INVALID, "backward: null grad_w[%d]", k);
@@ -279,7 +298,7 @@ mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channe
 
 uint64_t mnr_field_packed_bytes(const mnr_field* f) {
   clear_error();
-  if (validate_field(f) != MNR_OK) return 0;
+  if (validate_field(f) != MNR_OK || f->encoding == MNR_ENC_FREQ) return 0;
   uint64_t b = 0;
   for (int l = 0; l < f->n_levels; ++l)
     if (level_is_dense(f, l)) b += dense_level_bytes(f->level_res[l], f->table_dtype);
@@ -289,6 +308,7 @@ uint64_t mnr_field_packed_bytes(const mnr_field* f) {
 mnr_status mnr_field_pack(const mnr_field* f, void* stream) {
   clear_error();
   if (mnr_status s = validate_field(f)) return s;
+  if (f->encoding == MNR_ENC_FREQ) return MNR_OK;  // no grid levels to pack
   if (!f->dense_packed) return fail(MNR_E_INVALID, "field_pack: null dense_packed");
   FieldArgs F;
   field_args(F, f);
@@ -359,6 +379,8 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   if (!st || !target) return fail(MNR_E_INVALID, "train_step: null state or target");
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, st->rgba)) return s;
   if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the residual motion network");
+  if (field->encoding == MNR_ENC_FREQ)
+    return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the frequency-encoded field");
   if (!st->table_master || !st->table_grad || !st->table_m || !st->table_v || !st->weights_grad || !st->grad_rgba ||
       !st->loss || !st->t_chunks)
     return fail(MNR_E_INVALID, "train_step: null state buffer");

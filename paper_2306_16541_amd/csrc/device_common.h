@@ -42,6 +42,7 @@ struct FieldArgs {
   const char* dpk;           // optional packed copy of the dense levels (NULL: gather from table)
   uint64_t dpk_off[MNR_MAX_LEVELS];  // byte offset of each dense level in dpk
   int32_t n_packed;          // leading dense levels read from dpk (0 without it)
+  int32_t freq;              // 1: frequency-encoded field with the skip MLP (no grid)
 };
 
 // Largest volume resolution with a packed copy: one bone's packed plane

@@ -578,7 +578,75 @@ __device__ __forceinline__ void residual_step(const ResArgs& r, const char* rl, 
   }
 }
 
-template <typename TableT, int P, int NHH, bool RES = false>
+// ---------------------------------------------------------------------------
+// The paper's own field (Sec. 4.4, Eq. 13, Fig. 9): 10-band positional
+// encoding (64 values) and a 64-wide skip MLP on BF16 MFMA.  LDS: W1
+// (64x64), W2, W3 (64x64), W4 (64x128: h3's four input tiles, then
+// gamma's four), W5 (4 rows padded to 16).  gamma lives in the wave's
+// feature buffer as two 32-feature halves in the layer-1 input layout.
+// ---------------------------------------------------------------------------
+
+struct FreqShape {
+  static constexpr int FRAG = 64 * 16;
+  static constexpr int W1 = 4 * 2 * FRAG, W2 = 4 * 2 * FRAG, W3 = 4 * 2 * FRAG, W4 = 4 * 4 * FRAG, W5 = 2 * FRAG;
+  static constexpr int o2 = W1, o3 = o2 + W2, o4 = o3 + W3, o5 = o4 + W4;
+  static constexpr int bytes() { return o5 + W5; }
+  static constexpr int feat_bytes_per_wave() { return 64 * 64 * 2; }
+};
+
+__device__ void stage_freq(char* lds, const FieldArgs& f) {
+  stage_layer<MNR_BF16>(lds, (const __bf16*)f.w[0], HIDDEN, 64, HIDDEN);
+  stage_layer<MNR_BF16>(lds + FreqShape::o2, (const __bf16*)f.w[1], HIDDEN, HIDDEN, HIDDEN);
+  stage_layer<MNR_BF16>(lds + FreqShape::o3, (const __bf16*)f.w[2], HIDDEN, HIDDEN, HIDDEN);
+  stage_layer<MNR_BF16>(lds + FreqShape::o4, (const __bf16*)f.w[3], HIDDEN, 2 * HIDDEN, HIDDEN);
+  stage_layer<MNR_BF16>(lds + FreqShape::o5, (const __bf16*)f.w[4], 4, HIDDEN, 16);
+}
+
+// gamma(x) of the lane's sample into the feature buffer (zeros for lanes
+// that are not live); value k goes to half k / 32, feature k % 32.
+__device__ __forceinline__ void store_posenc10(char* feat, int lane, const float x[3], bool live) {
+  float prev = 0.f;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    float v;
+    if (k < 3) {
+      v = x[k];
+    } else if (k < 63) {
+      const int band = (k - 3) / 6, r = (k - 3) % 6, c = r % 3;
+      float sv, cv;
+      sincospif((float)(1 << band) * x[c], &sv, &cv);
+      v = r < 3 ? sv : cv;
+    } else {
+      v = 0.f;
+    }
+    if (k & 1) store_feat2<MNR_BF16>(feat + (k >> 5) * 4096, lane, (k - 1) & 31, live ? f2{prev, v} : f2{0.f, 0.f});
+    prev = v;
+  }
+}
+
+// Raw outputs (o0..o3) of the 16 samples of tile nt, lanes 0..15.
+__device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt, int lane) {
+  f4 xa[4], xb[4], h[4], h2[4];
+  load_input<MNR_BF16>(feat, nt, lane, xa);
+  load_input<MNR_BF16>(feat + 4096, nt, lane, xb);
+  const f4 g[4] = {xa[0], xa[1], xb[0], xb[1]};
+  mma_layer<MNR_BF16, 4, 4>(wl, g, h, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(h[mt]);
+  mma_layer<MNR_BF16, 4, 4>(wl + FreqShape::o2, h, h2, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+  mma_layer<MNR_BF16, 4, 4>(wl + FreqShape::o3, h2, h, lane);
+  const f4 cat[8] = {relu4(h[0]), relu4(h[1]), relu4(h[2]), relu4(h[3]), g[0], g[1], g[2], g[3]};
+  mma_layer<MNR_BF16, 4, 8>(wl + FreqShape::o4, cat, h2, lane);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+  f4 o[4];
+  mma_layer<MNR_BF16, 1, 4>(wl + FreqShape::o5, h2, o, lane);
+  return o[0];
+}
+
+template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
 __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, int lane, const char* wl, char* feat,
                                                f4* obuf, SampleState& st, f4& out) {
   st.L = 0.f;
@@ -589,19 +657,28 @@ __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, 
   if (live_mask == 0) return 0;
   if constexpr (RES) {
     static_assert(P == MNR_BF16, "the residual motion network runs on the BF16 path");
-    residual_step(a.res, wl + MlpShape<P>::bytes_total(NHH), feat, obuf, st, live_mask, lane);
+    residual_step(a.res, wl + (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)), feat, obuf, st, live_mask,
+                  lane);
   }
 
-  float u[3];
-  unit_coords(a.f, st.xs, u);
-  encode_all<TableT>(a.f, u, st.live, [&](int l, f2 v) { store_feat2<P>(feat, lane, 2 * l, v); });
+  if constexpr (FREQ) {
+    static_assert(P == MNR_BF16, "the frequency-encoded field runs on the BF16 path");
+    store_posenc10(feat, lane, st.xs, st.live);
+  } else {
+    float u[3];
+    unit_coords(a.f, st.xs, u);
+    encode_all<TableT>(a.f, u, st.live, [&](int l, f2 v) { store_feat2<P>(feat, lane, 2 * l, v); });
+  }
   wave_sync_lds();
   // Tile nt's outputs go to obuf[16 nt ..]; when obuf aliases the feature
   // buffer those bytes belong to tile 0, whose features are already consumed.
 #pragma unroll 1
   for (int nt = 0; nt < 4; ++nt) {
     f4 o = {0.f, 0.f, 0.f, 0.f};
-    if ((live_mask >> (16 * nt)) & 0xFFFFull) o = mlp_tile<P, NHH>(wl, feat, nt, lane);
+    if ((live_mask >> (16 * nt)) & 0xFFFFull) {
+      if constexpr (FREQ) o = freq_tile(wl, feat, nt, lane);
+      else o = mlp_tile<P, NHH>(wl, feat, nt, lane);
+    }
     wave_sync_lds();
     if (lane < 16) obuf[nt * 16 + lane] = o;
   }
@@ -612,7 +689,7 @@ __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, 
 }
 
 // One 64-sample chunk of a ray (lane i: sample 64 ch + i).
-template <typename TableT, int P, int NHH, bool RES = false>
+template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
 __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySetup& rs, int ray_index, int ch,
                                                int lane, const char* wl, char* feat, f4* obuf, SampleState& st,
                                                f4& out) {
@@ -622,7 +699,7 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
   st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
   st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
   st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
-  return field_eval<TableT, P, NHH, RES>(a, valid, lane, wl, feat, obuf, st, out);
+  return field_eval<TableT, P, NHH, RES, FREQ>(a, valid, lane, wl, feat, obuf, st, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,7 +711,7 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
 // and a ray stops once T < ert_tau.  Writes RGBA, optionally the adjoint's
 // saved state, and counts evaluated samples.
 // ---------------------------------------------------------------------------
-template <typename TableT, int P, int NHH, bool RES = false>
+template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
 __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile, int wave, int lane, const char* wl,
                                                    char* feat) {
   const int S_ = a.r.spp;
@@ -659,7 +736,7 @@ __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile
       st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
     }
     f4 out;
-    const uint64_t live_mask = field_eval<TableT, P, NHH, RES>(a, act, lane, wl, feat, (f4*)feat, st, out);
+    const uint64_t live_mask = field_eval<TableT, P, NHH, RES, FREQ>(a, act, lane, wl, feat, (f4*)feat, st, out);
     if (live_mask) {
       live_count += __popcll(live_mask);
       if (st.live) {

@@ -52,24 +52,31 @@ __device__ __forceinline__ int n_iters(int nblk, int n_slots) {
 
 // LDS bytes in front of the per-wave feature buffers: the field's MLP
 // weights, then (RES) the residual motion network's.
-template <int P, int NHH, bool RES>
-constexpr int weight_lds_bytes() { return MlpShape<P>::bytes_total(NHH) + (RES ? ResShape::bytes() : 0); }
-
-template <int P, int NHH, bool RES>
-__device__ __forceinline__ void stage_all(char* wl, const RenderArgs& a) {
-  stage_weights<P, NHH>(wl, a.f);
-  if constexpr (RES) stage_residual(wl + MlpShape<P>::bytes_total(NHH), a.res);
+template <int P, int NHH, bool RES, bool FREQ = false>
+constexpr int weight_lds_bytes() {
+  return (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)) + (RES ? ResShape::bytes() : 0);
 }
 
-template <typename TableT, int P, int NHH, int NW, bool RES>
+// Per-wave feature buffer: the grid's 32 features, or gamma's 64 (FREQ).
+template <int P, bool FREQ>
+constexpr int feat_bytes() { return FREQ ? FreqShape::feat_bytes_per_wave() : MlpShape<P>::feat_bytes_per_wave(); }
+
+template <int P, int NHH, bool RES, bool FREQ = false>
+__device__ __forceinline__ void stage_all(char* wl, const RenderArgs& a) {
+  if constexpr (FREQ) stage_freq(wl, a.f);
+  else stage_weights<P, NHH>(wl, a.f);
+  if constexpr (RES) stage_residual(wl + (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)), a.res);
+}
+
+template <typename TableT, int P, int NHH, int NW, bool RES, bool FREQ = false>
 __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a, int n_slots) {
   using S = MlpShape<P>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* wl = lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  char* feat = lds + weight_lds_bytes<P, NHH, RES>() + wave * S::feat_bytes_per_wave();
+  char* feat = lds + weight_lds_bytes<P, NHH, RES, FREQ>() + wave * feat_bytes<P, FREQ>();
 
-  stage_all<P, NHH, RES>(wl, a);
+  stage_all<P, NHH, RES, FREQ>(wl, a);
   __syncthreads();
 
   const int S_ = a.r.spp;
@@ -102,7 +109,7 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
         SampleState st;
         f4 out;
         const uint64_t live_mask =
-            chunk_eval<TableT, P, NHH, RES>(a, rs, orow, ch, lane, wl, feat, (f4*)feat, st, out);
+            chunk_eval<TableT, P, NHH, RES, FREQ>(a, rs, orow, ch, lane, wl, feat, (f4*)feat, st, out);
         if (live_mask == 0) continue;  // nothing visible in this chunk (alpha' = 0)
         live_count += __popcll(live_mask);
         const bool live = st.live;
@@ -141,23 +148,23 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
 
 // NW / 4 consecutive 16x16 tiles per block iteration (four 8x8 packets
 // each); without a workspace, tile groups are dealt round-robin to the XCDs.
-template <typename TableT, int P, int NHH, int NW, bool RES>
+template <typename TableT, int P, int NHH, int NW, bool RES, bool FREQ = false>
 __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs a, int n_tiles) {
   using S = MlpShape<P>;
   constexpr int TPB = NW / 4;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* wl = lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  char* feat = lds + weight_lds_bytes<P, NHH, RES>() + wave * S::feat_bytes_per_wave();
+  char* feat = lds + weight_lds_bytes<P, NHH, RES, FREQ>() + wave * feat_bytes<P, FREQ>();
 
-  stage_all<P, NHH, RES>(wl, a);
+  stage_all<P, NHH, RES, FREQ>(wl, a);
   __syncthreads();
   if (a.queues) {  // dynamic: each wave pulls 8x8 packets (4 per tile) from per-XCD queues
     int q = blockIdx.x & 7, tried = 0;
     for (;;) {
       const int unit = pull_unit(a.queues, n_tiles * 4, q, tried);
       if (unit < 0) break;
-      render_tile_packet<TableT, P, NHH, RES>(a, unit >> 2, unit & 3, lane, wl, feat);
+      render_tile_packet<TableT, P, NHH, RES, FREQ>(a, unit >> 2, unit & 3, lane, wl, feat);
     }
     return;
   }
@@ -168,7 +175,7 @@ __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs
     const int group = k * 8 + xcd;
     if (group >= n_groups) break;
     const int tile = group * TPB + (wave >> 2);
-    if (tile < n_tiles) render_tile_packet<TableT, P, NHH, RES>(a, tile, wave & 3, lane, wl, feat);
+    if (tile < n_tiles) render_tile_packet<TableT, P, NHH, RES, FREQ>(a, tile, wave & 3, lane, wl, feat);
   }
 }
 
@@ -185,13 +192,12 @@ static int persistent_blocks(KernelT kern, int threads, int lds, int* cache) {
   return *cache;
 }
 
-template <typename TableT, int P, int NHH, bool RES>
+template <typename TableT, int P, int NHH, bool RES, bool FREQ = false>
 static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
-  using S = MlpShape<P>;
   constexpr int NW = block_waves<P>();
-  const int lds = weight_lds_bytes<P, NHH, RES>() + NW * S::feat_bytes_per_wave();
+  const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>();
   if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, NW/4 16x16 tiles per block
-    auto kern = render_packet_kernel<TableT, P, NHH, NW, RES>;
+    auto kern = render_packet_kernel<TableT, P, NHH, NW, RES, FREQ>;
     static int max_blocks = 0;
     const int n_tiles = n_slots / 256;
     const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
@@ -200,7 +206,7 @@ static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
     hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
     return hipGetLastError();
   }
-  auto kern = render_fwd_kernel<TableT, P, NHH, NW, RES>;
+  auto kern = render_fwd_kernel<TableT, P, NHH, NW, RES, FREQ>;
   static int max_blocks = 0;
   const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
   const int need = (n_slots + NW - 1) / NW;
@@ -229,6 +235,9 @@ static hipError_t launch_fwd_bf16(const RenderArgs& a, int n_slots, mnr_dtype ta
 // only; the host rejects it for F32 MLPs before launching.
 hipError_t launch_render_fwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt,
                              int nhh, hipStream_t st) {
+  if (a.f.freq)  // the frequency-encoded field: BF16 only, no grid table
+    return a.res.w[0] ? launch_fwd_t<float, MNR_BF16, 0, true, true>(a, n_slots, st)
+                      : launch_fwd_t<float, MNR_BF16, 0, false, true>(a, n_slots, st);
   if (mlp_dt == MNR_BF16)
     return a.res.w[0] ? launch_fwd_bf16<true>(a, n_slots, table_dt, nhh, st)
                       : launch_fwd_bf16<false>(a, n_slots, table_dt, nhh, st);

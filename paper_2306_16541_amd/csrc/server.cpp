@@ -278,6 +278,7 @@ mnr_status mnr_server_add_user(mnr_server* s, int32_t user, const mnr_field* fie
   clear_error();
   if (!s || !field || !motion || !motion->weights) return fail(MNR_E_INVALID, "server: null argument");
   if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "server: users with a residual motion network");
+  if (field->encoding != MNR_ENC_GRID) return fail(MNR_E_UNSUPPORTED, "server: users with a frequency-encoded field");
   if (user < 0 || user > 1023) return fail(MNR_E_INVALID, "server: user id out of range");
   if (mnr_status st = validate_field(field)) return st;
   const uint64_t bytes = field_bytes(*field, *motion);

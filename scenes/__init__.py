@@ -63,7 +63,8 @@ SEGMENT_RADIUS = (
 )
 
 # Tensor ids for per-tensor seed streams.
-_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR, _TID_RES, _TID_CNN = range(1, 10)
+_TID_POSE, _TID_LOGITS, _TID_TABLE, _TID_MLP, _TID_RAYS, _TID_TARGET, _TID_COLOR, _TID_RES, _TID_CNN, _TID_FREQ = \
+    range(1, 11)
 
 
 def rng(seed: int, tensor_id: int) -> np.random.Generator:
@@ -181,6 +182,22 @@ def residual_weights(seed: int, out_scale: float = 0.05, n_joints: int = N_JOINT
         ws.append(g.uniform(-a, a, (fan_out, fan_in)).astype(np.float32))
     ws[4] *= np.float32(out_scale)
     return ws[:5], ws[5]
+
+
+FREQ_SHAPES = ((64, 64), (64, 64), (64, 64), (64, 128), (4, 64))   # the frequency-encoded field's W1..W5
+
+
+def freq_field_weights(seed: int, sigma_gain: float = 30.0):
+    """Seeded Xavier-uniform weights of the frequency-encoded field's skip
+    MLP; the density row of W5 is scaled by sigma_gain so that the random
+    field is a fog of moderate opacity (sigma up to a few tens)."""
+    g = rng(seed, _TID_FREQ)
+    ws = []
+    for fan_out, fan_in in FREQ_SHAPES:
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        ws.append(g.uniform(-a, a, (fan_out, fan_in)).astype(np.float32))
+    ws[4][3] *= np.float32(sigma_gain)
+    return ws
 
 
 SKEL_CNN_CHANNELS = (256, 128, 64, 32, 32, 25)

@@ -131,6 +131,20 @@ def test_invalid_calls_are_rejected_before_launch():
     f.mlp_dtype = 0
     for k in range(6):
         mo.res_w[k] = None
+    f.encoding = 7                                                         # unknown encoding
+    assert _render(m, f, mo, pose, cam) == -1
+    f.encoding = 1                                                         # frequency field, F32 MLP
+    f.n_layers, f.w[4] = 5, 0x2400
+    f.width[:6] = [64, 64, 64, 64, 64, 4]
+    assert _render(m, f, mo, pose, cam) == -7
+    f.mlp_dtype = 2
+    f.width[3] = 32
+    assert _render(m, f, mo, pose, cam) == -2                              # widths are fixed
+    f.width[3] = 64
+    assert m.lib.mnr_field_packed_bytes(C.byref(f)) == 0                   # no grid, nothing to pack
+    f.encoding, f.mlp_dtype, f.n_layers = 0, 0, len(sc.mlp)
+    widths = [32] + [w.shape[0] for w in sc.mlp]
+    f.width[: len(widths)] = widths
     assert m.lib.mnr_probe_atomic(None, 16, 1, 256, 1, 1, None) == -1
     assert m.lib.mnr_probe_atomic(0x2000, 16, 1, 256, 65, 1, None) == -2      # run > 64
 
