@@ -274,6 +274,14 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                float* grad_table, float* const* grad_w, float* grad_weights,
                                float* grad_bones, void* workspace, void* stream);
 
+/* Patch ray batch for training (Sec. 5.2: n_patches patches of size x size
+ * pixels per image, so that patch losses can be taken): patch k's top-left
+ * corner is drawn uniformly from the positions where the patch fits, from
+ * SplitMix64 outputs (seed, 2k) and (seed, 2k + 1); out_ids (host int32
+ * [n_patches * size * size]) lists each patch's pixels row by row, patches
+ * in order.  MNR_E_SHAPE when a patch does not fit the image. */
+mnr_status mnr_patch_rays(int32_t H, int32_t W, int32_t n_patches, int32_t size, uint64_t seed, int32_t* out_ids);
+
 /* Squared-error loss of Eq. 14's MSE term over RGB: loss = mean over rays
  * and channels of (rgb - target)^2.  target: dev [n_rays][3].  Writes
  * grad_rgba dev [n_rays][4] (alpha gradient 0) and, if loss_out != NULL,

@@ -120,7 +120,7 @@ EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
             "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_fk_backward", "mnr_refiner_apply",
             "mnr_refiner_backward", "mnr_skel_cnn_act_floats", "mnr_skel_cnn_scratch_floats", "mnr_skel_cnn_forward",
-            "mnr_skel_cnn_backward"]
+            "mnr_skel_cnn_backward", "mnr_patch_rays"]
 
 
 def check(status: int, what: str = "") -> None:
@@ -394,6 +394,16 @@ def fk_backward(pose: PoseHost, grad_G: np.ndarray):
     ga = np.zeros((n, 3), np.float32)
     check(lib.mnr_fk_backward(C.byref(pose.c), g.ctypes.data, gd.ctypes.data, ga.ctypes.data), "fk_backward")
     return gd, ga
+
+
+_sig("mnr_patch_rays", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p])
+
+
+def patch_rays(H: int, W: int, n_patches: int = 6, size: int = 20, seed: int = 0) -> np.ndarray:
+    """Pixel ids of a patch ray batch (include/metanerf.h, mnr_patch_rays)."""
+    out = np.zeros(n_patches * size * size, dtype=np.int32)
+    check(lib.mnr_patch_rays(H, W, n_patches, size, seed, out.ctypes.data), "patch_rays")
+    return out
 
 
 class SkelCnn(C.Structure):

@@ -296,6 +296,29 @@ mnr_status mnr_softmax_fwd(const float* logits, float* weights, int32_t n_channe
   return hip_status(launch_softmax_fwd(logits, weights, n_channels, n_voxels, (hipStream_t)stream), "softmax launch");
 }
 
+static uint64_t splitmix64_host(uint64_t seed, uint64_t n) {  // n-th output of SplitMix64 (Steele et al. 2014)
+  uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+mnr_status mnr_patch_rays(int32_t H, int32_t W, int32_t n_patches, int32_t size, uint64_t seed, int32_t* out_ids) {
+  clear_error();
+  if (!out_ids) return fail(MNR_E_INVALID, "patch_rays: null output");
+  if (H < 1 || W < 1 || n_patches < 1 || size < 1 || size > H || size > W)
+    return fail(MNR_E_SHAPE, "patch_rays: %d patches of %d^2 do not fit a %dx%d image", n_patches, size, H, W);
+  int32_t* o = out_ids;
+  for (int k = 0; k < n_patches; ++k) {
+    const uint64_t ny = (uint64_t)(H - size + 1), nx = (uint64_t)(W - size + 1);
+    const int y0 = (int)(((splitmix64_host(seed, 2 * (uint64_t)k) >> 11) * ny) >> 53);
+    const int x0 = (int)(((splitmix64_host(seed, 2 * (uint64_t)k + 1) >> 11) * nx) >> 53);
+    for (int y = 0; y < size; ++y)
+      for (int x = 0; x < size; ++x) *o++ = (y0 + y) * W + x0 + x;
+  }
+  return MNR_OK;
+}
+
 uint64_t mnr_field_packed_bytes(const mnr_field* f) {
   clear_error();
   if (validate_field(f) != MNR_OK || f->encoding == MNR_ENC_FREQ) return 0;
