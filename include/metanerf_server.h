@@ -16,7 +16,8 @@
  *   - one persistent kernel per tick pulls tiles from a device-side table;
  *     the per-tick work (table upload + kernel) is replayed from captured
  *     hipGraphs (two, double-buffered, so the host prepares tick k+1 while
- *     tick k runs);
+ *     tick k runs), each on its own stream so that tick k+1 starts on the
+ *     compute units that tick k's last blocks leave idle;
  *   - per-request timestamps (arrival, admission, first tick, completion)
  *     give p50/p99 latency.
  * A request's pixels are computed with a fixed ray-to-lane mapping and no
@@ -27,7 +28,7 @@
  * All calls are thread-safe.  Device memory: the server allocates its
  * request slots and tile tables; users' fields and request outputs are
  * caller-owned and must stay valid while in use.  The server works on its
- * own stream, unordered with the caller's streams: a field or output
+ * own streams, unordered with the caller's streams: a field or output
  * buffer must have no pending work on other streams when it is registered
  * or submitted, and must not be reused until the request has completed.
  */
@@ -52,7 +53,7 @@ typedef struct {
 
 /* mem_budget: bytes for resident users plus admitted outputs.  max_slots:
  * admitted requests at once (1..256).  tiles_per_tick: tile budget of one
- * GPU tick (16..16384; 0 = 1024).  Creates the server's stream and
+ * GPU tick (16..16384; 0 = 1024).  Creates the server's streams and
  * scheduler thread on the current device. */
 mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t tiles_per_tick, mnr_server** out);
 

@@ -4,12 +4,15 @@
 // One scheduler thread owns the GPU side: it retires finished ticks,
 // admits queued requests (free slot + memory budget), and launches the next
 // tick whenever fewer than two are in flight.  A tick renders up to
-// tiles_per_tick 16x16 tiles taken from admitted requests oldest first; a
-// request completes with the tick that renders its last tile (tick
-// composition: see launch_locked).  Ticks are
-// replayed from two captured hipGraphs (tile-table upload + tick kernel),
-// alternating between two tile tables so the host can fill one while the
-// GPU reads the other.
+// tiles_per_tick 16x16 tiles taken from admitted requests; a request
+// completes with the tick that renders its last tile (tick composition: see
+// launch_locked).  Ticks are replayed from two captured hipGraphs (tile-table
+// upload + tick kernel), alternating between two tile tables so the host can
+// fill one while the GPU reads the other.  Each table has its own stream, so
+// the next tick's blocks take over compute units as the previous tick's
+// last blocks drain instead of waiting for the whole grid; ticks still
+// retire in launch order.  Per-request arguments go up on a third stream
+// that every tick waits on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,7 +93,10 @@ struct mnr_server {
   uint64_t next_ticket = 1;
   mnr_server_stats st{};
   // device side
-  hipStream_t stream = nullptr;
+  hipStream_t stream[2] = {nullptr, nullptr};  // one per tick buffer
+  hipStream_t copy_stream = nullptr;            // request arguments
+  hipEvent_t copy_ev = nullptr;                 // after the latest argument upload
+  bool copy_wait[2] = {false, false};           // tick stream must wait on copy_ev
   RenderArgs* d_slots = nullptr;
   RenderArgs* h_slots = nullptr;  // pinned staging, one per slot
   WorkTable* d_wt[2] = {nullptr, nullptr};
@@ -145,11 +151,16 @@ bool mnr_server::admit_locked() {
     r.t[1] = now_ns();
     h_slots[r.slot] = r.args;
     const hipError_t e = hipMemcpyAsync(d_slots + r.slot, h_slots + r.slot, sizeof(RenderArgs),
-                                        hipMemcpyHostToDevice, stream);
+                                        hipMemcpyHostToDevice, copy_stream);
     if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
     active.push_back(r.ticket);
     queue.pop_front();
     any = true;
+  }
+  if (any) {  // a slot is rewritten only after every tick that read it retired
+    const hipError_t e = hipEventRecord(copy_ev, copy_stream);
+    if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
+    copy_wait[0] = copy_wait[1] = true;
   }
   return any;
 }
@@ -192,13 +203,14 @@ bool mnr_server::launch_locked() {
   if (n == 0) return false;
   w->counter = 0;
   w->n_items = n;
+  hipStream_t sb = stream[buf];
   if (!graph[buf]) {  // capture this buffer's tick once: table upload + tick kernel
     hipGraph_t g = nullptr;
-    hipError_t e = launch_serve(nullptr, nullptr, table_dt, mlp_dt, nhh, stream);  // kernel set-up, no launch
-    if (e == hipSuccess) e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_wt[buf], h_wt[buf], wt_bytes, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_serve(d_slots, d_wt[buf], table_dt, mlp_dt, nhh, stream);
-    const hipError_t e2 = hipStreamEndCapture(stream, &g);
+    hipError_t e = launch_serve(nullptr, nullptr, table_dt, mlp_dt, nhh, sb);  // kernel set-up, no launch
+    if (e == hipSuccess) e = hipStreamBeginCapture(sb, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_wt[buf], h_wt[buf], wt_bytes, hipMemcpyHostToDevice, sb);
+    if (e == hipSuccess) e = launch_serve(d_slots, d_wt[buf], table_dt, mlp_dt, nhh, sb);
+    const hipError_t e2 = hipStreamEndCapture(sb, &g);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&graph[buf], g, nullptr, nullptr, 0);
     if (g) hipGraphDestroy(g);
@@ -207,8 +219,13 @@ bool mnr_server::launch_locked() {
       return false;
     }
   }
-  hipError_t e = hipGraphLaunch(graph[buf], stream);
-  if (e == hipSuccess) e = hipEventRecord(t.ev, stream);
+  hipError_t e = hipSuccess;
+  if (copy_wait[buf]) {
+    e = hipStreamWaitEvent(sb, copy_ev, 0);
+    copy_wait[buf] = false;
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(graph[buf], sb);
+  if (e == hipSuccess) e = hipEventRecord(t.ev, sb);
   if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
   t.inflight = true;
   next_buf ^= 1;
@@ -257,7 +274,9 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
   for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
   s->wt_bytes = sizeof(WorkTable) + sizeof(WorkItem) * (size_t)tiles_per_tick;
   hipError_t e = hipGetDevice(&s->device);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipStreamCreateWithFlags(&s->stream[b], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&s->d_slots, sizeof(RenderArgs) * max_slots);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_slots, sizeof(RenderArgs) * max_slots, hipHostMallocDefault);
   for (int b = 0; b < 2 && e == hipSuccess; ++b) {
@@ -389,7 +408,9 @@ mnr_status mnr_server_destroy(mnr_server* s) {
     s->cv_work.notify_all();
     s->th.join();
   }
-  if (s->stream) hipStreamSynchronize(s->stream);
+  for (int b = 0; b < 2; ++b)
+    if (s->stream[b]) hipStreamSynchronize(s->stream[b]);
+  if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
   for (int b = 0; b < 2; ++b) {
     if (s->graph[b]) hipGraphExecDestroy(s->graph[b]);
     if (s->ticks[b].ev) hipEventDestroy(s->ticks[b].ev);
@@ -398,7 +419,10 @@ mnr_status mnr_server_destroy(mnr_server* s) {
   }
   if (s->d_slots) hipFree(s->d_slots);
   if (s->h_slots) hipHostFree(s->h_slots);
-  if (s->stream) hipStreamDestroy(s->stream);
+  if (s->copy_ev) hipEventDestroy(s->copy_ev);
+  for (int b = 0; b < 2; ++b)
+    if (s->stream[b]) hipStreamDestroy(s->stream[b]);
+  if (s->copy_stream) hipStreamDestroy(s->copy_stream);
   delete s;
   return MNR_OK;
 }
