@@ -91,8 +91,9 @@ struct BwdShape {
   static constexpr int dw_floats(int nhh) { return HIDDEN * IN_FEAT + nhh * HIDDEN * HIDDEN + 4 * HIDDEN; }
   static constexpr int tbuf_bytes() { return 2 * 64 * 16 * (int)sizeof(TB); }
   static constexpr int wave_bytes() { return S::feat_bytes_per_wave() + 64 * IN_FEAT * 4 + tbuf_bytes(); }
+  static constexpr int dg_floats() { return MNR_MAX_BONES * 12; }  // block sums of dL/dG
   static constexpr int lds_bytes(int nhh, int nw) {
-    return S::bytes_total(nhh) + bytes_t(nhh) + dw_floats(nhh) * 4 + nw * wave_bytes();
+    return S::bytes_total(nhh) + bytes_t(nhh) + (dw_floats(nhh) + dg_floats()) * 4 + nw * wave_bytes();
   }
 };
 
@@ -241,15 +242,16 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   char* wl = lds;
   char* wt = wl + S::bytes_total(NHH);
   float* dw = (float*)(wt + B::bytes_t(NHH));
+  float* dg = dw + B::dw_floats(NHH);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  char* wbase = (char*)(dw + B::dw_floats(NHH)) + wave * B::wave_bytes();
+  char* wbase = (char*)(dg + B::dg_floats()) + wave * B::wave_bytes();
   char* feat = wbase;
   float* dfeat = (float*)(wbase + S::feat_bytes_per_wave());
   TB* tb = (TB*)(wbase + S::feat_bytes_per_wave() + 64 * IN_FEAT * 4);
 
   stage_weights<P, NHH>(wl, a.f);
   stage_weights_t<P, NHH>(wt, a.f);
-  for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) dw[i] = 0.f;
+  for (int i = threadIdx.x; i < B::dw_floats(NHH) + B::dg_floats(); i += blockDim.x) dw[i] = 0.f;
   __syncthreads();
 
   const size_t T = (size_t)1 << a.f.log2_T;
@@ -436,7 +438,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         for (int k = 0; k < 8; ++k)
           v[k] = gw * ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
                  ((k & 4) ? t.f[2] : 1.f - t.f[2]);
-        if (a.grad_G) {  // uniform: dL/dG_b = dL/dy_b [x 1]^T, summed over the wave
+        if (a.grad_G) {  // uniform: dL/dG_b = dL/dy_b [x 1]^T, summed over the wave, then the block
           // dL/dy_b = w_b / max(L, eps) dL/dx_skel + dL/dw_b grad_y w_b(y_b)
           float c[8];
           bone_corners(a.m, b, t, c);
@@ -459,7 +461,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
               const float s = wave_sum(live ? gy[r] * xh[k] : 0.f);
-              if (lane == 0) unsafeAtomicAdd(a.grad_G + b * 12 + r * 4 + k, s);
+              if (lane == 0) atomicAdd(dg + b * 12 + r * 4 + k, s);
             }
         }
         const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
@@ -478,6 +480,11 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
     }
   }
   __syncthreads();
+  // flush the block's bone-transform gradients: every wave of every block
+  // adds into the same few cache lines, so the sums stay in LDS until here
+  if (a.grad_G)
+    for (int i = threadIdx.x; i < a.m.n_bones * 12; i += blockDim.x)
+      if (dg[i] != 0.f) unsafeAtomicAdd(a.grad_G + i, dg[i]);
   // flush the block's MLP weight gradients
   const int n_first = HIDDEN * IN_FEAT, n_hid = HIDDEN * HIDDEN;
   for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) {
