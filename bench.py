@@ -207,6 +207,31 @@ def ceilings(reps=5):
     return out
 
 
+def mlp_unfused_bench(sc, n, fused_ms, reps=10):
+    """The field MLP alone (mnr_probe_mlp: the renderer's MLP device code)
+    over n stored feature rows, n = the frame's evaluated samples, against
+    the MFMA peak of its type; `share` = its time / the fused frame kernel's."""
+    out = {}
+    widths = [32] + [w.shape[0] for w in sc.mlp]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(16541)
+    for dt, key, tname, row in ((m.F32, "f32", "fp32", 128), (m.BF16, "bf16", "mixed", 64)):
+        fld, _ = m.upload_scene(sc, "cuda", m.F32, dt)
+        feat = torch.rand(n, 32, generator=g, device="cuda").mul_(2.0).sub_(1.0)
+        if dt == m.BF16:
+            feat = feat.to(torch.bfloat16)
+        o = torch.empty(n, 4, device="cuda")
+        timed_launches(lambda: m.probe_mlp(fld, feat, out=o), reps, 2)
+        ms = timed_launches.last_median
+        tf = n * mlp_flops(widths) / (ms * 1e-3) / 1e12
+        out[key] = {"samples": n, "kernel_ms_median": ms, "Gsamples_per_s": n / (ms * 1e-3) / 1e9,
+                    "TFLOP_per_s": tf, "frac_of_mfma_peak": tf / MFMA_PEAK[key],
+                    "GB_per_s": n * (row + 16) / (ms * 1e-3) / 1e9,
+                    "share_of_fused_frame": ms / fused_ms[tname] if fused_ms.get(tname) else None}
+        del feat, o, fld
+    return out
+
+
 def train_bench(steps, warmup):
     sc = scenes.scene_body()
     dev = "cuda"
@@ -439,13 +464,18 @@ def main():
         line["freq_field_512"]["roofline_mfma"]["frac"] = line["freq_field_512"]["roofline_mfma"]["achieved"] / \
             MFMA_PEAK["bf16"]
         del ffield
+        line["mlp_unfused"] = mlp_unfused_bench(sc, fp32["n_eval"],
+                                                {"fp32": fp32["kernel_ms_median"], "mixed": mixed["kernel_ms_median"]})
         sc3 = scenes.scene_body(H=1024, W=1024, spp=192)
         big = render_bench(sc3, m.F16, m.BF16, max(3, args.steps // 4), 1)
-        line["mixed_1024_192spp"] = {
-            "Msamples_per_s": 1024 * 1024 * 192 / (big["kernel_ms"] * 1e-3) / 1e6,
-            "frames_per_s": 1e3 / big["kernel_ms"],
-            "evaluated_Msamples_per_s": big["n_eval"] / (big["kernel_ms"] * 1e-3) / 1e6}
-        del big
+        big32 = render_bench(sc3, m.F32, m.F32, max(3, args.steps // 4), 1)
+        for key, r in (("mixed_1024_192spp", big), ("fp32_1024_192spp", big32)):
+            line[key] = {
+                "Msamples_per_s": 1024 * 1024 * 192 / (r["kernel_ms"] * 1e-3) / 1e6,
+                "frames_per_s": 1e3 / r["kernel_ms"],
+                "evaluated_Msamples_per_s": r["n_eval"] / (r["kernel_ms"] * 1e-3) / 1e6}
+        line["mixed_1024_192spp"]["speedup_vs_fp32"] = big32["kernel_ms"] / big["kernel_ms"]
+        del big, big32
         line["train_step_8192x128"] = train_bench(max(3, args.steps // 2), 2)
         line["ceilings"] = ceilings()
         if not args.no_serve:

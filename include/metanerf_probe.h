@@ -8,8 +8,9 @@
  *   - small random gathers from a table of the grid encoding's size
  *     (the warp and encoding steps, Sec. 4.2 Eq. 9 and Sec. 4.4 Eq. 13);
  *   - a dense MFMA loop in the MLP's arithmetic types (the MLP of Eq. 13);
- *   - scattered float atomics (the adjoint's gradient scatter, Sec. 5.2).
- * Both run on the caller's stream; time them with events around the call.
+ *   - scattered float atomics (the adjoint's gradient scatter, Sec. 5.2);
+ *   - the renderer's MLP run unfused, over features read from memory.
+ * All run on the caller's stream; time them with events around the call.
  */
 #ifndef METANERF_PROBE_H
 #define METANERF_PROBE_H
@@ -47,6 +48,21 @@ mnr_status mnr_probe_atomic(float* acc, uint32_t n_words, int32_t atomics_per_la
  * v_mfma_f32_16x16x32_bf16 (16384 FLOP each).  FLOP issued = n_blocks * 4
  * waves * iters * 4 * (FLOP per MFMA).  out: dev float [n_blocks * 256]. */
 mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_blocks, float* out, void* stream);
+
+/* The field MLP of Sec. 4.4 Eq. 13 (the grid-encoded field's: 32 -> 64 ...
+ * -> 4, bias-free, ReLU hidden layers) on its own, with the renderer's
+ * device code: the weights field->w[] (field->mlp_dtype, F32 or BF16;
+ * field->n_layers 2..4; other field members are not read) are staged into
+ * LDS once per block, and each wave pushes 64-sample chunks through the
+ * MFMA layer chain.  feat: dev [n][32] features in the MLP's type (F32:
+ * float, BF16: bfloat16), 16-byte aligned.  out: dev float [n][4], 16-byte
+ * aligned, receives (sigmoid(o0), sigmoid(o1), sigmoid(o2), ReLU(o3)), the
+ * colour and density heads of Sec. 4.4.  n = 0 launches nothing.  Reads
+ * 128 (F32) or 64 (BF16) bytes and writes 16 bytes per sample; MLP work
+ * 2 * (32*64 + (n_layers-2)*64*64 + 64*4) FLOP per sample.  Errors: null
+ * pointers, misalignment, widths other than 32/64/4, a frequency-encoded
+ * field (MNR_E_UNSUPPORTED). */
+mnr_status mnr_probe_mlp(const mnr_field* field, const void* feat, int64_t n, float* out, void* stream);
 
 #ifdef __cplusplus
 }

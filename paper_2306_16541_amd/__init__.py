@@ -113,12 +113,13 @@ _sig("mnr_probe_gather", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32
                                    C.c_void_p, C.c_void_p])
 _sig("mnr_probe_mfma", C.c_int, [C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p])
 _sig("mnr_probe_atomic", C.c_int, [C.c_void_p, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_void_p])
+_sig("mnr_probe_mlp", C.c_int, [C.POINTER(Field), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
-            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_fk_backward", "mnr_refiner_apply",
+            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_probe_mlp", "mnr_fk_backward", "mnr_refiner_apply",
             "mnr_refiner_backward", "mnr_skel_cnn_act_floats", "mnr_skel_cnn_scratch_floats", "mnr_skel_cnn_forward",
             "mnr_skel_cnn_backward", "mnr_patch_rays"]
 
@@ -317,6 +318,15 @@ def probe_mfma(dtype: int, iters: int, n_blocks: int, out: Optional[torch.Tensor
     """Dense MFMA-loop ceiling probe (include/metanerf_probe.h)."""
     out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda") if out is None else out
     check(lib.mnr_probe_mfma(dtype, iters, n_blocks, _ptr(out), _stream()), "probe_mfma")
+    return out
+
+
+def probe_mlp(field, feat: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The field's MLP run unfused over feat [n, 32] (the MLP's dtype) into
+    out [n, 4] = (rgb, sigma) (include/metanerf_probe.h)."""
+    n = feat.shape[0]
+    out = torch.empty(n, 4, dtype=torch.float32, device=feat.device) if out is None else out
+    check(lib.mnr_probe_mlp(C.byref(field.c), _ptr(feat), n, _ptr(out), _stream()), "probe_mlp")
     return out
 
 

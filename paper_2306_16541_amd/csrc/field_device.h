@@ -369,15 +369,38 @@ __device__ __forceinline__ void store_feat2(char* feat, int s, int k, f2 v) {
   }
 }
 
-__device__ __forceinline__ f4 relu4(f4 v) {
-  return f4{fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f)};
+// ReLU as a signed-integer max on the bit pattern: one instruction (fmaxf
+// costs two on MFMA results, a canonicalisation and the max).  Equal to
+// max(x, 0) for every non-NaN x, with -0 mapped to +0.
+__device__ __forceinline__ float relu1(float x) {
+  const int i = __builtin_bit_cast(int, x);
+  return __builtin_bit_cast(float, i > 0 ? i : 0);
 }
+
+__device__ __forceinline__ f4 relu4(f4 v) { return f4{relu1(v[0]), relu1(v[1]), relu1(v[2]), relu1(v[3])}; }
 
 __device__ __forceinline__ bf16x8 pack_bf16(f4 lo, f4 hi) {
   bf16x8 b;
   b[0] = (__bf16)lo[0]; b[1] = (__bf16)lo[1]; b[2] = (__bf16)lo[2]; b[3] = (__bf16)lo[3];
   b[4] = (__bf16)hi[0]; b[5] = (__bf16)hi[1]; b[6] = (__bf16)hi[2]; b[7] = (__bf16)hi[3];
   return b;
+}
+
+// BF16 layer on operands already packed: b[s] holds input rows 32 s ..
+// 32 s + 31 of the lane's sample column (the layout of pack_bf16 over two
+// F32 input tiles).
+template <int MT, int KS>
+__device__ __forceinline__ void mma_layer_bf16(const char* wl, const bf16x8 (&b)[KS], f4 (&out)[4], int lane,
+                                               const float* bias = nullptr) {
+  const bf16x8* W = (const bf16x8*)wl;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    f4 acc = bias ? *(const f4*)(bias + 16 * mt + 4 * (lane >> 4)) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+    out[mt] = acc;
+  }
 }
 
 // One dense layer: out[mt] = W x (+ bias), K = 16 * KT input tiles.  The
@@ -404,19 +427,11 @@ __device__ __forceinline__ void mma_layer(const char* wl, const f4 (&x)[NX], f4 
       out[mt] = acc;
     }
   } else {
-    const bf16x8* W = (const bf16x8*)wl;
     constexpr int KS = KT / 2;
     bf16x8 b[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      f4 acc = acc0(mt);
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
-      out[mt] = acc;
-    }
+    mma_layer_bf16<MT, KS>(wl, b, out, lane, bias);
   }
 }
 
@@ -443,9 +458,15 @@ template <int P, int NHH>
 __device__ __forceinline__ f4 mlp_tile(const char* wl, const char* feat, int nt, int lane,
                                        f4 (*hidden)[4] = nullptr) {
   using S = MlpShape<P>;
-  f4 x[4], h[4];
-  load_input<P>(feat, nt, lane, x);
-  mma_layer<P, 4, 2>(wl, x, h, lane);
+  f4 h[4];
+  if constexpr (P == MNR_BF16) {  // the stored features are already the packed B operand
+    const bf16x8 b[1] = {((const bf16x8*)feat)[nt * 64 + lane]};
+    mma_layer_bf16<4, 1>(wl, b, h, lane);
+  } else {
+    f4 x[4];
+    load_input<P>(feat, nt, lane, x);
+    mma_layer<P, 4, 2>(wl, x, h, lane);
+  }
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(h[mt]);
   if (hidden) {

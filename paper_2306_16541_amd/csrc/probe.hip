@@ -1,7 +1,11 @@
 // Machine-ceiling probes: a random-gather kernel, scattered float atomics
-// and a dense MFMA loop (declared in metanerf_probe.h).  They share nothing with the renderer but
-// the buffer-resource helper.
+// and a dense MFMA loop (declared in metanerf_probe.h), which share nothing
+// with the renderer but the buffer-resource helper; and the renderer's own
+// MLP code run unfused, over features read from memory.
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
 
 #include "../../include/metanerf_probe.h"
 #include "field_device.h"  // make_rsrc
@@ -92,6 +96,82 @@ __global__ void __launch_bounds__(256) probe_mfma_kernel(int iters, float* __res
   out[blockIdx.x * 256u + threadIdx.x] = (c0[0] + c1[1]) + (c2[2] + c3[3]);
 }
 
+// The renderer's MLP (weights staged once per block in LDS in MFMA
+// fragment order, the layer chain of mlp_tile) over features read from
+// memory, one 64-sample chunk per wave at a time; the heads are the
+// renderer's: rgb = sigmoid(o0..2), sigma = ReLU(o3).
+template <int P, int NHH>
+__global__ void __launch_bounds__(256) probe_mlp_kernel(const FieldArgs f, const void* __restrict__ feat_in, int64_t n,
+                                                        float* __restrict__ out) {
+  using S = MlpShape<P>;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* feat = lds + S::bytes_total(NHH) + wave * S::feat_bytes_per_wave();
+  stage_weights<P, NHH>(lds, f);
+  __syncthreads();
+  const int64_t nchunks = (n + 63) >> 6;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wave; c < nchunks; c += (int64_t)gridDim.x * 4) {
+    const int64_t s = c * 64 + lane;
+    if constexpr (P == MNR_F32) {
+      float v[IN_FEAT];
+#pragma unroll
+      for (int k = 0; k < IN_FEAT; ++k) v[k] = 0.f;
+      if (s < n) {
+        const f4* src = (const f4*)((const float*)feat_in + s * IN_FEAT);
+#pragma unroll
+        for (int q = 0; q < IN_FEAT / 4; ++q) {
+          const f4 t = src[q];
+          v[4 * q] = t[0]; v[4 * q + 1] = t[1]; v[4 * q + 2] = t[2]; v[4 * q + 3] = t[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < IN_FEAT / 2; ++k) store_feat2<P>(feat, lane, 2 * k, f2{v[2 * k], v[2 * k + 1]});
+    } else {  // BF16 features go to their LDS slots as they are (store_feat2's layout, no conversion)
+      const bf16x8* src = (const bf16x8*)((const __bf16*)feat_in + s * IN_FEAT);
+#pragma unroll
+      for (int q = 0; q < IN_FEAT / 8; ++q) {
+        bf16x8 t = {};
+        if (s < n) t = src[q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // features 8q + 2j, 8q + 2j + 1
+          const int k = 8 * q + 2 * j, nt = lane >> 4, ln = (lane & 15) + 16 * ((k & 15) >> 2);
+          *(bf16x2*)(feat + ((nt * 64 + ln) * 8 + (k >> 4) * 4 + (k & 3)) * 2) = bf16x2{t[2 * j], t[2 * j + 1]};
+        }
+      }
+    }
+    wave_sync_lds();
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+      const f4 o = mlp_tile<P, NHH>(lds, feat, nt, lane);
+      const int64_t r = c * 64 + nt * 16 + lane;
+      if (lane < 16 && r < n)
+        *(f4*)(out + r * 4) = f4{1.f / (1.f + expf(-o[0])), 1.f / (1.f + expf(-o[1])), 1.f / (1.f + expf(-o[2])),
+                                 fmaxf(o[3], 0.f)};
+    }
+    wave_sync_lds();  // the next chunk rewrites the feature buffer
+  }
+}
+
+template <int P, int NHH>
+static hipError_t launch_probe_mlp(const FieldArgs& F, const void* feat, int64_t n, float* out, hipStream_t st) {
+  using S = MlpShape<P>;
+  const int lds = S::bytes_total(NHH) + 4 * S::feat_bytes_per_wave();
+  auto kern = probe_mlp_kernel<P, NHH>;
+  static int max_blocks = 0;
+  if (max_blocks == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 256, lds);
+    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  const int64_t need = ((n + 63) / 64 + 3) / 4;
+  const int grid = need < max_blocks ? (int)need : max_blocks;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, F, feat, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace mnr
 
 using namespace mnr;
@@ -140,4 +220,38 @@ extern "C" mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_b
   else hipLaunchKernelGGL(probe_mfma_kernel<false>, dim3(n_blocks), dim3(256), 0, st, iters, out);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_mfma launch: %s", hipGetErrorString(e));
+}
+
+extern "C" mnr_status mnr_probe_mlp(const mnr_field* field, const void* feat, int64_t n, float* out, void* stream) {
+  clear_error();
+  if (!field) return fail(MNR_E_INVALID, "probe_mlp: null field");
+  if (n < 0 || n > ((int64_t)1 << 40)) return fail(MNR_E_SHAPE, "probe_mlp: n out of range");
+  if (n > 0 && (!feat || !out)) return fail(MNR_E_INVALID, "probe_mlp: null pointer");
+  if (((uintptr_t)feat | (uintptr_t)out) & 15) return fail(MNR_E_INVALID, "probe_mlp: feat and out must be 16-byte aligned");
+  if (field->encoding != MNR_ENC_GRID) return fail(MNR_E_UNSUPPORTED, "probe_mlp: the grid-encoded field's MLP only");
+  if (field->mlp_dtype != MNR_F32 && field->mlp_dtype != MNR_BF16) return fail(MNR_E_DTYPE, "probe_mlp: F32 or BF16 MLP");
+  const int nl = field->n_layers;
+  if (nl < 2 || nl > 4) return fail(MNR_E_SHAPE, "probe_mlp: 2..4 layers");
+  if (field->width[0] != IN_FEAT || field->width[nl] != 4) return fail(MNR_E_SHAPE, "probe_mlp: widths 32 -> ... -> 4");
+  for (int k = 1; k < nl; ++k)
+    if (field->width[k] != HIDDEN) return fail(MNR_E_SHAPE, "probe_mlp: hidden width must be 64");
+  for (int k = 0; k < nl; ++k)
+    if (!field->w[k]) return fail(MNR_E_INVALID, "probe_mlp: null weight %d", k);
+  if (n == 0) return MNR_OK;
+  FieldArgs F;
+  std::memset(&F, 0, sizeof(F));  // only the weights are read
+  for (int k = 0; k < nl; ++k) F.w[k] = field->w[k];
+  F.n_layers = nl;
+  hipStream_t st = (hipStream_t)stream;
+  const int nhh = nl - 2;
+  hipError_t e;
+  if (field->mlp_dtype == MNR_BF16)
+    e = nhh == 0 ? launch_probe_mlp<MNR_BF16, 0>(F, feat, n, out, st)
+      : nhh == 1 ? launch_probe_mlp<MNR_BF16, 1>(F, feat, n, out, st)
+                 : launch_probe_mlp<MNR_BF16, 2>(F, feat, n, out, st);
+  else
+    e = nhh == 0 ? launch_probe_mlp<MNR_F32, 0>(F, feat, n, out, st)
+      : nhh == 1 ? launch_probe_mlp<MNR_F32, 1>(F, feat, n, out, st)
+                 : launch_probe_mlp<MNR_F32, 2>(F, feat, n, out, st);
+  return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_mlp launch: %s", hipGetErrorString(e));
 }

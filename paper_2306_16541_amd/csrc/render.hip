@@ -26,10 +26,14 @@ namespace mnr {
 
 // Waves per block of the frame and ray-list kernels: the MLP weights in LDS
 // are shared by the block, so bigger blocks leave more LDS per CU for the
-// per-wave feature buffers (FP32: 44 KiB + 12 x 8 KiB fits one block, three
-// waves per SIMD).
-template <int P>
-constexpr int block_waves() { return P == MNR_F32 ? 12 : 8; }
+// per-wave feature buffers.  Twelve waves (three per SIMD, what the kernels'
+// registers allow) fit one block in the 160 KiB of LDS: FP32 44 + 12 x 8
+// KiB, BF16 22 + 12 x 4 KiB (+ 34 KiB with the residual network), the
+// frequency field 42 + 12 x 8 KiB.  The frequency field with the residual
+// network needs 34 KiB more and takes eight.  The BF16 ray-list kernel
+// (training batches of a few thousand rays) measured faster with eight.
+template <int P, bool RES, bool FREQ, bool RAY_LIST>
+constexpr int block_waves() { return ((RES && FREQ) || (RAY_LIST && P != MNR_F32)) ? 8 : 12; }
 
 // Ray slot handled by iteration `it` of wave `w` of block `blk`.
 template <int NW>
@@ -194,9 +198,10 @@ static int persistent_blocks(KernelT kern, int threads, int lds, int* cache) {
 
 template <typename TableT, int P, int NHH, bool RES, bool FREQ = false>
 static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
-  constexpr int NW = block_waves<P>();
-  const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>();
+  constexpr int NW = block_waves<P, RES, FREQ, false>();
+  static_assert(weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>() <= 160 * 1024, "LDS per block");
   if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, NW/4 16x16 tiles per block
+    const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>();
     auto kern = render_packet_kernel<TableT, P, NHH, NW, RES, FREQ>;
     static int max_blocks = 0;
     const int n_tiles = n_slots / 256;
@@ -206,13 +211,15 @@ static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
     hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
     return hipGetLastError();
   }
-  auto kern = render_fwd_kernel<TableT, P, NHH, NW, RES, FREQ>;
+  constexpr int NWR = block_waves<P, RES, FREQ, true>();
+  const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NWR * feat_bytes<P, FREQ>();
+  auto kern = render_fwd_kernel<TableT, P, NHH, NWR, RES, FREQ>;
   static int max_blocks = 0;
-  const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
-  const int need = (n_slots + NW - 1) / NW;
+  const int mb = persistent_blocks(kern, 64 * NWR, lds, &max_blocks);
+  const int need = (n_slots + NWR - 1) / NWR;
   int grid = need < mb ? need : mb;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, st, a, n_slots);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NWR), lds, st, a, n_slots);
   return hipGetLastError();
 }
 

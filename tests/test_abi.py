@@ -147,6 +147,20 @@ def test_invalid_calls_are_rejected_before_launch():
     f.width[: len(widths)] = widths
     assert m.lib.mnr_probe_atomic(None, 16, 1, 256, 1, 1, None) == -1
     assert m.lib.mnr_probe_atomic(0x2000, 16, 1, 256, 65, 1, None) == -2      # run > 64
+    assert m.lib.mnr_probe_mlp(None, 0x1000, 64, 0x2000, None) == -1
+    assert m.lib.mnr_probe_mlp(C.byref(f), None, 64, 0x2000, None) == -1
+    assert m.lib.mnr_probe_mlp(C.byref(f), 0x1008, 64, 0x2000, None) == -1   # not 16-byte aligned
+    assert m.lib.mnr_probe_mlp(C.byref(f), 0x1000, -1, 0x2000, None) == -2
+    assert m.lib.mnr_probe_mlp(C.byref(f), None, 0, None, None) == 0         # nothing to do, no launch
+    f.mlp_dtype = 1
+    assert m.lib.mnr_probe_mlp(C.byref(f), 0x1000, 64, 0x2000, None) == -3   # F16 MLP
+    f.mlp_dtype = 0
+    f.width[1] = 48
+    assert m.lib.mnr_probe_mlp(C.byref(f), 0x1000, 64, 0x2000, None) == -2
+    f.width[1] = 64
+    f.encoding = 1
+    assert m.lib.mnr_probe_mlp(C.byref(f), 0x1000, 64, 0x2000, None) == -7   # frequency field
+    f.encoding = 0
 
 
 def test_packed_motion_size():
