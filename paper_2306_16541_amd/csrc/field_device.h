@@ -724,31 +724,76 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
 }
 
 // ---------------------------------------------------------------------------
-// One 8x8 ray packet (packet `wave` of 16x16 tile `tile` of the frame): each
-// lane owns one pixel's ray and the 64 rays march in lockstep, one sample
-// per iteration.  Compositing is the per-lane recurrence
+// Full-frame ray blocks.  Compositing is the per-ray recurrence
 //   alpha = 1 - exp(-sigma delta), alpha' = alpha min(L, 1),
 //   C += T alpha' c, T *= 1 - alpha'
-// and a ray stops once T < ert_tau.  Writes RGBA, optionally the adjoint's
-// saved state, and counts evaluated samples.
+// sample after sample, and a ray stops once T < ert_tau.  A block writes
+// RGBA, optionally the adjoint's saved state, and counts evaluated samples.
 // ---------------------------------------------------------------------------
+// Value held by lane Q of the caller's group of four lanes (DPP quad
+// permutation; every lane of the wave must be active).
+template <int Q>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), Q * 0x55, 0xF, 0xF, false));
+}
+
+// Compositing (Sec. 2.1 Eq. 3 with the Sec. 4.4 likelihood factor) of
+// sample j + Q of the ray held by this group of four lanes, whose
+// opacity and colour lane Q computed.  Every lane of the group applies the
+// same update, so the ray's state stays replicated; the order and the
+// expressions are those of one sample per step, and so is early
+// termination (after the sample that takes T below ert_tau).  The
+// broadcast values reach the update as plain operands, so the compiler
+// cannot fuse 1 - alpha' with the product that formed alpha'.
+template <int Q>
+__device__ __forceinline__ void composite_q(const RenderArgs& a, int j, int pix, int nchunks, int k, float ap, float c0,
+                                            float c1, float c2, float lv, bool& ray_act, float& Tr, float& C0,
+                                            float& C1, float& C2, int& n_done, unsigned& cnt) {
+  const float apq = quad_bcast<Q>(ap), c0q = quad_bcast<Q>(c0), c1q = quad_bcast<Q>(c1), c2q = quad_bcast<Q>(c2);
+  const float lq = quad_bcast<Q>(lv);
+  const int i = j + Q;
+  if (ray_act && i < a.r.spp) {
+    if (a.t_chunks && (i & 63) == 0 && k == 0) a.t_chunks[(size_t)pix * (nchunks + 1) + (i >> 6)] = Tr;
+    if (lq != 0.f) {
+      const float w = Tr * apq;
+      C0 = fmaf(w, c0q, C0);
+      C1 = fmaf(w, c1q, C1);
+      C2 = fmaf(w, c2q, C2);
+      Tr *= 1.f - apq;
+      ++cnt;
+    }
+    n_done = i + 1;
+    if (Tr < a.r.ert_tau || i + 1 >= a.r.spp) ray_act = false;
+  }
+}
+
+// One 4x4 block of rays (sub = 0..15, raster order inside the 16x16 tile),
+// marched four samples per step: lane 4 r + k evaluates sample j + k of ray
+// r.  A block of 16 rays is a quarter of the serial work of a wave holding
+// 64 rays, so a frame splits into four times as many units and the last
+// units to finish are short.  A ray's recurrence, its order and its
+// stopping rule are those of marching it one sample per step; samples that
+// follow the terminating one inside its group of four are evaluated and
+// discarded (at most three per ray), and are not counted in n_eval.
 template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
-__device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile, int wave, int lane, const char* wl,
-                                                   char* feat) {
+__device__ __forceinline__ void render_tile_rays4(const RenderArgs& a, int tile, int sub, int lane, const char* wl,
+                                                  char* feat) {
   const int S_ = a.r.spp;
   const int nchunks = (S_ + 63) >> 6;
-  const int u = (tile % a.r.tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
-  const int v = (tile / a.r.tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+  const int r = lane >> 2, k = lane & 3;
+  const int u = (tile % a.r.tiles_x) * 16 + (sub & 3) * 4 + (r & 3);
+  const int v = (tile / a.r.tiles_x) * 16 + (sub >> 2) * 4 + (r >> 2);
   const bool in_image = u < a.r.W && v < a.r.H;
   const int pix = in_image ? v * a.r.W + u : 0;
   RaySetup rs;
-  bool act = in_image && setup_ray(a.r, pix, rs);
+  bool ray_act = in_image && setup_ray(a.r, pix, rs);
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;
   int n_done = 0;
-  unsigned live_count = 0;
-  for (int i = 0;; ++i) {
-    if (__ballot(act) == 0) break;
-    if (a.t_chunks && act && (i & 63) == 0) a.t_chunks[(size_t)pix * (nchunks + 1) + (i >> 6)] = Tr;
+  unsigned cnt = 0;
+  for (int j = 0;; j += 4) {
+    if (__ballot(ray_act) == 0) break;
+    const int i = j + k;
+    const bool act = ray_act && i < S_;
     SampleState st;
     if (act) {
       const float s = ((float)i + sample_jitter(a.r, pix, i)) * rs.delta;
@@ -758,24 +803,21 @@ __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile
     }
     f4 out;
     const uint64_t live_mask = field_eval<TableT, P, NHH, RES, FREQ>(a, act, lane, wl, feat, (f4*)feat, st, out);
-    if (live_mask) {
-      live_count += __popcll(live_mask);
-      if (st.live) {
-        const float sigma = fmaxf(out[3], 0.f);
-        const float ap = -expm1f(-sigma * rs.delta) * fminf(st.L, 1.f);
-        const float w = Tr * ap;
-        C0 = fmaf(w, 1.f / (1.f + expf(-out[0])), C0);
-        C1 = fmaf(w, 1.f / (1.f + expf(-out[1])), C1);
-        C2 = fmaf(w, 1.f / (1.f + expf(-out[2])), C2);
-        Tr *= 1.f - ap;
-      }
+    float ap = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, lv = 0.f;
+    if (live_mask && st.live) {
+      const float sigma = fmaxf(out[3], 0.f);
+      ap = -expm1f(-sigma * rs.delta) * fminf(st.L, 1.f);
+      c0 = 1.f / (1.f + expf(-out[0]));
+      c1 = 1.f / (1.f + expf(-out[1]));
+      c2 = 1.f / (1.f + expf(-out[2]));
+      lv = 1.f;
     }
-    if (act) {
-      n_done = i + 1;
-      if (Tr < a.r.ert_tau || i + 1 >= S_) act = false;
-    }
+    composite_q<0>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
+    composite_q<1>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
+    composite_q<2>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
+    composite_q<3>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
   }
-  if (in_image) {
+  if (in_image && k == 0) {
     *(f4*)(a.out + (size_t)pix * 4) = f4{C0 + Tr * a.r.bg[0], C1 + Tr * a.r.bg[1], C2 + Tr * a.r.bg[2], 1.f - Tr};
     if (a.t_chunks) {
       float* tc = a.t_chunks + (size_t)pix * (nchunks + 1);
@@ -783,7 +825,21 @@ __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile
       tc[nchunks] = (float)n_done;
     }
   }
-  if (a.n_eval && lane == 0 && live_count) atomicAdd(a.n_eval, (unsigned long long)live_count);
+  if (a.n_eval) {
+    const float tot = wave_sum(k == 0 ? (float)cnt : 0.f);  // exact: at most 16 x 1024
+    if (lane == 0 && tot > 0.f) atomicAdd(a.n_eval, (unsigned long long)tot);
+  }
+}
+
+// Quadrant `quad` (0..3) of a 16x16 tile: its four 4x4 ray blocks in turn.
+template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
+__device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile, int quad, int lane, const char* wl,
+                                                   char* feat) {
+#pragma unroll 1
+  for (int s = 0; s < 4; ++s) {
+    const int sx = (quad & 1) * 2 + (s & 1), sy = (quad >> 1) * 2 + (s >> 1);
+    render_tile_rays4<TableT, P, NHH, RES, FREQ>(a, tile, sy * 4 + sx, lane, wl, feat);
+  }
 }
 
 }  // namespace mnr

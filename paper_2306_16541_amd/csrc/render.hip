@@ -7,13 +7,14 @@
 //   with the likelihood augmentation (Eq. 3, Sec. 4.4) as a wave
 //   prefix-product; transmittance is carried across chunks and the ray stops
 //   after the chunk where it falls below ert_tau.
-// render_packet_kernel (full frames): one wavefront owns an 8x8 block of
-// neighbouring pixels, one ray per lane, and marches the 64 rays in
-// lockstep, one sample per iteration.  The 64 samples of an iteration lie
-// within a few voxels of each other, so the skinning-volume and grid
-// gathers of a wave share cache lines; compositing is a per-lane
-// recurrence and each ray stops as soon as its transmittance is below
-// ert_tau.  A block's four waves cover one 16x16 tile.
+// render_packet_kernel (full frames): one wavefront owns a 4x4 block of
+// neighbouring pixels and marches the 16 rays in lockstep, four
+// consecutive samples of each ray per iteration (lane 4 r + k: sample
+// 4 j + k of ray r).  The 64 samples of an iteration lie within a few
+// voxels of each other, so the skinning-volume and grid gathers of a wave
+// share cache lines; the four lanes of a ray composite its four samples in
+// order (a per-ray recurrence) and each ray stops as soon as its
+// transmittance is below ert_tau.  A 16x16 tile is 16 such blocks.
 // Both use a persistent grid: blocks stage the MLP weights into LDS once
 // and loop over work.  With a workspace, waves pull work from per-XCD
 // queues over contiguous bands of the frame (block b runs on XCD b % 8),
@@ -150,8 +151,10 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
 }
 
 
-// NW / 4 consecutive 16x16 tiles per block iteration (four 8x8 packets
-// each); without a workspace, tile groups are dealt round-robin to the XCDs.
+// With a workspace, waves pull 4x4 ray blocks (16 per tile) from per-XCD
+// queues; without one, NW / 4 consecutive 16x16 tiles per block iteration
+// (each wave a quadrant: four 4x4 blocks in turn), tile groups dealt
+// round-robin to the XCDs.
 template <typename TableT, int P, int NHH, int NW, bool RES, bool FREQ = false>
 __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs a, int n_tiles) {
   using S = MlpShape<P>;
@@ -163,12 +166,12 @@ __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs
 
   stage_all<P, NHH, RES, FREQ>(wl, a);
   __syncthreads();
-  if (a.queues) {  // dynamic: each wave pulls 8x8 packets (4 per tile) from per-XCD queues
+  if (a.queues) {  // dynamic: each wave pulls 4x4 ray blocks (16 per tile) from per-XCD queues
     int q = blockIdx.x & 7, tried = 0;
     for (;;) {
-      const int unit = pull_unit(a.queues, n_tiles * 4, q, tried);
+      const int unit = pull_unit(a.queues, n_tiles * 16, q, tried);
       if (unit < 0) break;
-      render_tile_packet<TableT, P, NHH, RES, FREQ>(a, unit >> 2, unit & 3, lane, wl, feat);
+      render_tile_rays4<TableT, P, NHH, RES, FREQ>(a, unit >> 4, unit & 15, lane, wl, feat);
     }
     return;
   }
@@ -200,13 +203,13 @@ template <typename TableT, int P, int NHH, bool RES, bool FREQ = false>
 static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
   constexpr int NW = block_waves<P, RES, FREQ, false>();
   static_assert(weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>() <= 160 * 1024, "LDS per block");
-  if (!a.r.pixel_ids) {  // full frame: 8x8 ray packets, NW/4 16x16 tiles per block
+  if (!a.r.pixel_ids) {  // full frame: 4x4 ray blocks
     const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>();
     auto kern = render_packet_kernel<TableT, P, NHH, NW, RES, FREQ>;
     static int max_blocks = 0;
     const int n_tiles = n_slots / 256;
     const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
-    const int groups = a.queues ? (n_tiles * 4 + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
+    const int groups = a.queues ? (n_tiles * 16 + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
     const int grid = groups < mb ? groups : mb;
     hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
     return hipGetLastError();
