@@ -5,6 +5,7 @@
 //                 field's input (Sec. 4.4, Eq. 13)
 //   stage_weights / mlp_tile  the bias-free MLP of Eq. 13 on MFMA
 #pragma once
+#include <utility>
 #include "device_common.h"
 
 namespace mnr {
@@ -730,27 +731,31 @@ __device__ __forceinline__ uint64_t chunk_eval(const RenderArgs& a, const RaySet
 // sample after sample, and a ray stops once T < ert_tau.  A block writes
 // RGBA, optionally the adjoint's saved state, and counts evaluated samples.
 // ---------------------------------------------------------------------------
-// Value held by lane Q of the caller's group of four lanes (DPP quad
-// permutation; every lane of the wave must be active).
-template <int Q>
-__device__ __forceinline__ float quad_bcast(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), Q * 0x55, 0xF, 0xF, false));
+// Value held by lane Q of the caller's group of G lanes (G = 4: DPP quad
+// permutation; G = 8 or 16: swizzle inside each 32-lane half, lane
+// (l & (32 - G)) | Q).  Every lane of the wave must be active.
+template <int G, int Q>
+__device__ __forceinline__ float group_bcast(float v) {
+  static_assert(G == 4 || G == 8 || G == 16, "groups of 4, 8 or 16 lanes");
+  const int b = __builtin_bit_cast(int, v);
+  if constexpr (G == 4) return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(b, Q * 0x55, 0xF, 0xF, false));
+  else return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(b, (Q << 5) | (32 - G)));
 }
 
 // Compositing (Sec. 2.1 Eq. 3 with the Sec. 4.4 likelihood factor) of
-// sample j + Q of the ray held by this group of four lanes, whose
-// opacity and colour lane Q computed.  Every lane of the group applies the
-// same update, so the ray's state stays replicated; the order and the
-// expressions are those of one sample per step, and so is early
-// termination (after the sample that takes T below ert_tau).  The
-// broadcast values reach the update as plain operands, so the compiler
-// cannot fuse 1 - alpha' with the product that formed alpha'.
-template <int Q>
+// sample j + Q of the ray held by this group of G lanes, whose opacity and
+// colour lane Q computed.  Every lane of the group applies the same update,
+// so the ray's state stays replicated; the order and the expressions are
+// those of one sample per step, and so is early termination (after the
+// sample that takes T below ert_tau).  The broadcast values reach the
+// update as plain operands, so the compiler cannot fuse 1 - alpha' with the
+// product that formed alpha'.
+template <int G, int Q>
 __device__ __forceinline__ void composite_q(const RenderArgs& a, int j, int pix, int nchunks, int k, float ap, float c0,
                                             float c1, float c2, float lv, bool& ray_act, float& Tr, float& C0,
                                             float& C1, float& C2, int& n_done, unsigned& cnt) {
-  const float apq = quad_bcast<Q>(ap), c0q = quad_bcast<Q>(c0), c1q = quad_bcast<Q>(c1), c2q = quad_bcast<Q>(c2);
-  const float lq = quad_bcast<Q>(lv);
+  const float apq = group_bcast<G, Q>(ap), c0q = group_bcast<G, Q>(c0), c1q = group_bcast<G, Q>(c1);
+  const float c2q = group_bcast<G, Q>(c2), lq = group_bcast<G, Q>(lv);
   const int i = j + Q;
   if (ray_act && i < a.r.spp) {
     if (a.t_chunks && (i & 63) == 0 && k == 0) a.t_chunks[(size_t)pix * (nchunks + 1) + (i >> 6)] = Tr;
@@ -767,22 +772,32 @@ __device__ __forceinline__ void composite_q(const RenderArgs& a, int j, int pix,
   }
 }
 
-// One 4x4 block of rays (sub = 0..15, raster order inside the 16x16 tile),
-// marched four samples per step: lane 4 r + k evaluates sample j + k of ray
-// r.  A block of 16 rays is a quarter of the serial work of a wave holding
-// 64 rays, so a frame splits into four times as many units and the last
-// units to finish are short.  A ray's recurrence, its order and its
-// stopping rule are those of marching it one sample per step; samples that
-// follow the terminating one inside its group of four are evaluated and
-// discarded (at most three per ray), and are not counted in n_eval.
-template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
-__device__ __forceinline__ void render_tile_rays4(const RenderArgs& a, int tile, int sub, int lane, const char* wl,
-                                                  char* feat) {
+template <int G, int... Q>
+__device__ __forceinline__ void composite_group(std::integer_sequence<int, Q...>, const RenderArgs& a, int j, int pix,
+                                                int nchunks, int k, float ap, float c0, float c1, float c2, float lv,
+                                                bool& ray_act, float& Tr, float& C0, float& C1, float& C2, int& n_done,
+                                                unsigned& cnt) {
+  (composite_q<G, Q>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt), ...);
+}
+
+// One block of 64 / G rays, 4 wide and 16 / G tall (sub = 0 .. 4G - 1, raster
+// order inside the 16x16 tile), marched G samples per step: lane G r + k
+// evaluates sample j + k of ray r.  A block of 64 / G rays is 1 / G of the
+// serial work of a wave holding 64 rays, so a frame splits into G times as
+// many units and the last units to finish are short.  A ray's recurrence,
+// its order and its stopping rule are those of marching it one sample per
+// step; samples that follow the terminating one inside its group of G are
+// evaluated and discarded (at most G - 1 per ray), and are not counted in
+// n_eval.
+template <typename TableT, int P, int NHH, bool RES, bool FREQ, int G>
+__device__ __forceinline__ void render_tile_rays(const RenderArgs& a, int tile, int sub, int lane, const char* wl,
+                                                 char* feat) {
+  constexpr int RH = 16 / G;  // rows of the block
   const int S_ = a.r.spp;
   const int nchunks = (S_ + 63) >> 6;
-  const int r = lane >> 2, k = lane & 3;
+  const int r = lane / G, k = lane % G;
   const int u = (tile % a.r.tiles_x) * 16 + (sub & 3) * 4 + (r & 3);
-  const int v = (tile / a.r.tiles_x) * 16 + (sub >> 2) * 4 + (r >> 2);
+  const int v = (tile / a.r.tiles_x) * 16 + (sub >> 2) * RH + (r >> 2);
   const bool in_image = u < a.r.W && v < a.r.H;
   const int pix = in_image ? v * a.r.W + u : 0;
   RaySetup rs;
@@ -790,7 +805,7 @@ __device__ __forceinline__ void render_tile_rays4(const RenderArgs& a, int tile,
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;
   int n_done = 0;
   unsigned cnt = 0;
-  for (int j = 0;; j += 4) {
+  for (int j = 0;; j += G) {
     if (__ballot(ray_act) == 0) break;
     const int i = j + k;
     const bool act = ray_act && i < S_;
@@ -812,10 +827,8 @@ __device__ __forceinline__ void render_tile_rays4(const RenderArgs& a, int tile,
       c2 = 1.f / (1.f + expf(-out[2]));
       lv = 1.f;
     }
-    composite_q<0>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
-    composite_q<1>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
-    composite_q<2>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
-    composite_q<3>(a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr, C0, C1, C2, n_done, cnt);
+    composite_group<G>(std::make_integer_sequence<int, G>{}, a, j, pix, nchunks, k, ap, c0, c1, c2, lv, ray_act, Tr,
+                       C0, C1, C2, n_done, cnt);
   }
   if (in_image && k == 0) {
     *(f4*)(a.out + (size_t)pix * 4) = f4{C0 + Tr * a.r.bg[0], C1 + Tr * a.r.bg[1], C2 + Tr * a.r.bg[2], 1.f - Tr};
@@ -838,7 +851,7 @@ __device__ __forceinline__ void render_tile_packet(const RenderArgs& a, int tile
 #pragma unroll 1
   for (int s = 0; s < 4; ++s) {
     const int sx = (quad & 1) * 2 + (s & 1), sy = (quad >> 1) * 2 + (s >> 1);
-    render_tile_rays4<TableT, P, NHH, RES, FREQ>(a, tile, sy * 4 + sx, lane, wl, feat);
+    render_tile_rays<TableT, P, NHH, RES, FREQ, 4>(a, tile, sy * 4 + sx, lane, wl, feat);
   }
 }
 

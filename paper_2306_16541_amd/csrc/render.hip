@@ -7,14 +7,15 @@
 //   with the likelihood augmentation (Eq. 3, Sec. 4.4) as a wave
 //   prefix-product; transmittance is carried across chunks and the ray stops
 //   after the chunk where it falls below ert_tau.
-// render_packet_kernel (full frames): one wavefront owns a 4x4 block of
-// neighbouring pixels and marches the 16 rays in lockstep, four
-// consecutive samples of each ray per iteration (lane 4 r + k: sample
-// 4 j + k of ray r).  The 64 samples of an iteration lie within a few
-// voxels of each other, so the skinning-volume and grid gathers of a wave
-// share cache lines; the four lanes of a ray composite its four samples in
+// render_packet_kernel (full frames): one wavefront owns a small block of
+// neighbouring pixels and marches its rays in lockstep, G consecutive
+// samples of each ray per iteration (lane G r + k: sample j + k of ray r):
+// 8 rays x 8 samples when pulling work from the queues, 16 rays x 4
+// samples on the static path.  The 64 samples of an iteration lie within a
+// few voxels of each other, so the skinning-volume and grid gathers of a
+// wave share cache lines; the G lanes of a ray composite its G samples in
 // order (a per-ray recurrence) and each ray stops as soon as its
-// transmittance is below ert_tau.  A 16x16 tile is 16 such blocks.
+// transmittance is below ert_tau.
 // Both use a persistent grid: blocks stage the MLP weights into LDS once
 // and loop over work.  With a workspace, waves pull work from per-XCD
 // queues over contiguous bands of the frame (block b runs on XCD b % 8),
@@ -33,6 +34,12 @@ namespace mnr {
 // frequency field 42 + 12 x 8 KiB.  The frequency field with the residual
 // network needs 34 KiB more and takes eight.  The BF16 ray-list kernel
 // (training batches of a few thousand rays) measured faster with eight.
+// Samples per ray per step of the full-frame kernel's dynamic path: its
+// ray blocks hold 64 / FRAME_G = 8 rays (4 x 2 pixels), 32 per 16x16 tile.
+// Measured at 512x512x128 (FP32 / mixed): 5.63 / 3.40 ms with 4, 5.24 /
+// 3.27 with 8, 5.29 / 3.71 with 16 samples per step.
+constexpr int FRAME_G = 8;
+
 template <int P, bool RES, bool FREQ, bool RAY_LIST>
 constexpr int block_waves() { return ((RES && FREQ) || (RAY_LIST && P != MNR_F32)) ? 8 : 12; }
 
@@ -166,12 +173,13 @@ __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs
 
   stage_all<P, NHH, RES, FREQ>(wl, a);
   __syncthreads();
-  if (a.queues) {  // dynamic: each wave pulls 4x4 ray blocks (16 per tile) from per-XCD queues
+  if (a.queues) {  // dynamic: each wave pulls ray blocks (4 G per tile) from per-XCD queues
     int q = blockIdx.x & 7, tried = 0;
     for (;;) {
-      const int unit = pull_unit(a.queues, n_tiles * 16, q, tried);
+      const int unit = pull_unit(a.queues, n_tiles * 4 * FRAME_G, q, tried);
       if (unit < 0) break;
-      render_tile_rays4<TableT, P, NHH, RES, FREQ>(a, unit >> 4, unit & 15, lane, wl, feat);
+      render_tile_rays<TableT, P, NHH, RES, FREQ, FRAME_G>(a, unit / (4 * FRAME_G), unit % (4 * FRAME_G), lane, wl,
+                                                           feat);
     }
     return;
   }
@@ -209,7 +217,7 @@ static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
     static int max_blocks = 0;
     const int n_tiles = n_slots / 256;
     const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
-    const int groups = a.queues ? (n_tiles * 16 + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
+    const int groups = a.queues ? (n_tiles * 4 * FRAME_G + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
     const int grid = groups < mb ? groups : mb;
     hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
     return hipGetLastError();
