@@ -1,6 +1,9 @@
 // Server tick kernel: persistent blocks pull (request slot, tile) items
-// from a device-side table and render each 16x16 tile with the same packet
-// code as a full-frame mnr_render.  MLP weights are restaged into LDS only
+// from a device-side table and render each 16x16 tile with the same
+// ray-block code as a full-frame mnr_render (each wave a quadrant: four
+// blocks of 16 rays x 4 samples; splitting the tile's 32 blocks of 8 x 8
+// between the waves through an LDS counter measured no better, since
+// consecutive ticks already overlap).  MLP weights are restaged into LDS only
 // when consecutive tiles of a block belong to different users.
 #include "field_device.h"
 #include "kernels.h"

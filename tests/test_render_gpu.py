@@ -127,7 +127,7 @@ def test_mixed_1024_frame_sampled_psnr():
 
 
 def test_frame_and_ray_list_kernels_agree():
-    # Full frames go through the 8x8 ray-packet kernel, explicit ray lists
+    # Full frames go through the ray-block kernel, explicit ray lists
     # through the per-ray chunk kernel; the two agree within the early
     # termination bound (they stop at different granularity).
     sc = scenes.scene_body(H=40, W=56, spp=128)
