@@ -158,3 +158,38 @@ def test_adjoint_after_full_frame_forward():
         r = _rel(a.cpu().numpy(), b.numpy())
         print(f"  full-frame {name:7s} rel-L2 {r:.3e}", flush=True)
         assert r <= 2e-3, name
+
+
+def test_render_fn_autograd_matches_oracle_gradient():
+    # The adjoint behind torch.autograd: the loss is built and differentiated
+    # by torch on the GPU, while the render and its backward are RenderFn
+    # (the library's kernels).  dL/dW^c goes to the logits through the
+    # library's softmax adjoint; tolerances as for the FP32 path above.
+    import paper_2306_16541_amd as m
+    sc = _scene()
+    pid, tgt = _rays(sc)
+    fld, _ = m.upload_scene(sc, "cuda", m.F32, m.F32)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    opts = m.make_opts(ert_tau=1e-6, stratified=True, seed=SEED)
+    pid_t = torch.as_tensor(pid, device="cuda")
+    tgt_t = torch.as_tensor(tgt, device="cuda")
+    table = fld.table.requires_grad_(True)
+    weights = fld.weights.requires_grad_(True)
+    mlp = [w.requires_grad_(True) for w in fld.mlp]
+    rgba = m.RenderFn.apply(table, weights, *mlp, (fld, pose, cam, sc.H, sc.W, sc.spp, opts, pid_t))
+    loss = ((rgba[:, :3] - tgt_t) ** 2).mean()
+    loss.backward()
+    g_logits = torch.zeros_like(weights)
+    m.softmax_bwd(weights.detach(), weights.grad, g_logits)
+    torch.cuda.synchronize()
+    lo, to, wo, logo, _ = oracle_grads(sc, pid, tgt)
+    assert abs(float(loss.detach()) - lo) <= 1e-5 * abs(lo)
+    groups = [("table", table.grad, to), ("logits", g_logits, logo)] + \
+        [(f"w{k}", w.grad, b) for k, (w, b) in enumerate(zip(mlp, wo))]
+    for name, a, b in groups:
+        a = a.detach().cpu().numpy()
+        r = _rel(a, b)
+        print(f"  autograd {name:7s} rel-L2 {r:.3e}", flush=True)
+        assert np.linalg.norm(b) > 0, name
+        assert r <= 2e-3, name
