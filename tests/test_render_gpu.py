@@ -39,7 +39,7 @@ def test_body_scene_fp32_reduced_frame():
     assert _report("body fp32 64x64", g, o) <= FP32_TOL
 
 
-@pytest.mark.parametrize("spp", [1, 2, 63, 64, 65, 100, 192])
+@pytest.mark.parametrize("spp", [1, 2, 63, 64, 65, 100, 192, 1023, 1024])
 def test_ragged_samples_per_ray(spp):
     # With one or two samples per ray the stratum is most of the chord, so a
     # float32 rounding of the sample position moves alpha by delta * dsigma/dx;
