@@ -443,6 +443,10 @@ def main():
                               "peak": MFMA_PEAK["bf16"], "unit": "TFLOP/s"}}
         line["mixed_512_residual"]["roofline_mfma"]["frac"] = (line["mixed_512_residual"]["roofline_mfma"]["achieved"]
                                                                / MFMA_PEAK["bf16"])
+        # the same gathers as the mixed frame (warp + FP16 grid): its binding bound
+        rb_gbs = rb["n_eval"] * (BYTES_WARP + BYTES_ENC["f16"]) / k_s / 1e9
+        line["mixed_512_residual"]["roofline"] = {"bound": "hbm", "achieved": rb_gbs, "peak": HBM_PEAK_GBS,
+                                                  "unit": "GB/s", "frac": rb_gbs / HBM_PEAK_GBS, "traffic": None}
         del rb
         # The paper's own field: 10-band positional encoding and the skip MLP (BF16), no grid.
         lg = torch.as_tensor(sc.logits, device="cuda")
@@ -463,6 +467,10 @@ def main():
                               "peak": MFMA_PEAK["bf16"], "unit": "TFLOP/s"}}
         line["freq_field_512"]["roofline_mfma"]["frac"] = line["freq_field_512"]["roofline_mfma"]["achieved"] / \
             MFMA_PEAK["bf16"]
+        # no grid: the warp's gathers are the only table traffic, and they bind
+        f_gbs = f_eval * BYTES_WARP / (f_ms * 1e-3) / 1e9
+        line["freq_field_512"]["roofline"] = {"bound": "hbm", "achieved": f_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                              "frac": f_gbs / HBM_PEAK_GBS, "traffic": None}
         del ffield
         line["mlp_unfused"] = mlp_unfused_bench(sc, fp32["n_eval"],
                                                 {"fp32": fp32["kernel_ms_median"], "mixed": mixed["kernel_ms_median"]})
