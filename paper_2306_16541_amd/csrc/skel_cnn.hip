@@ -1,9 +1,14 @@
 // Skeleton-motion CNN (Sec. 4.2, Eq. 10, Fig. 7): fully connected layer,
 // then five 3-D transposed convolutions (kernel 4, stride 2, padding 1)
 // from one voxel to the 32^3 logit volume of the blend weights, and its
-// adjoint.  It runs once per training step (about 1 GFLOP), so the kernels
-// are direct: one thread per output element, weights and activations read
-// through the caches.
+// adjoint.  It runs once per training step (about 1.5 GFLOP with the
+// adjoint).  The kernels are direct, weights and activations read through
+// the caches; each output element belongs to a group of R lanes that split
+// its reduction and meet by xor shuffles.  R is chosen per layer so that
+// every launch has about 512 K lanes (the chip's wave slots): the coarse
+// layers have few outputs and
+// long reductions (2,048 terms per output in the first layer, 8,192 in its
+// adjoint), the fine ones many outputs and short reductions.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -15,14 +20,27 @@ constexpr float SLOPE = 0.2f;  // LeakyReLU
 
 __device__ __forceinline__ float lrelu(float x) { return x > 0.f ? x : SLOPE * x; }
 
+// Sum over the R lanes of the caller's group (R divides 64; a group is
+// either fully active or fully idle).
+template <int R>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int m = R / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, WAVE);
+  return v;
+}
+
 // out[o][X] = sum_i sum_taps w[i][o][k] in[i][v], X = 2 v - 1 + k per axis.
 // For each output coordinate two input positions contribute:
-// v = (X + 1) / 2 - t, k = X + 1 - 2 v, t = 0, 1.
+// v = (X + 1) / 2 - t, k = X + 1 - 2 v, t = 0, 1.  Lane r of a group takes
+// the input channels i = r, r + R, ...
+template <int R>
 __global__ void tconv_fwd_kernel(const float* __restrict__ in, const float* __restrict__ w, float* __restrict__ out,
                                  int ci, int co, int D, int act) {
   const int D2 = 2 * D;
   const int64_t n = (int64_t)co * D2 * D2 * D2;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+  const int r = threadIdx.x % R;
+  const int64_t groups = (int64_t)gridDim.x * blockDim.x / R;
+  for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / R; e < n; e += groups) {
     const int X = (int)(e % D2), Y = (int)((e / D2) % D2), Z = (int)((e / D2 / D2) % D2);
     const int o = (int)(e / ((int64_t)D2 * D2 * D2));
     float acc = 0.f;
@@ -36,21 +54,26 @@ __global__ void tconv_fwd_kernel(const float* __restrict__ in, const float* __re
           const int vx = (X + 1) / 2 - tx, kx = X + 1 - 2 * vx;
           if (vx < 0 || vx >= D || kx > 3) continue;
           const int64_t vi = ((int64_t)vz * D + vy) * D + vx, ki = (kz * 4 + ky) * 4 + kx;
-          for (int i = 0; i < ci; ++i)
+          for (int i = r; i < ci; i += R)
             acc = fmaf(w[((int64_t)i * co + o) * 64 + ki], in[(int64_t)i * D * D * D + vi], acc);
         }
       }
     }
-    out[e] = act ? lrelu(acc) : acc;
+    acc = group_sum<R>(acc);
+    if (r == 0) out[e] = act ? lrelu(acc) : acc;
   }
 }
 
-// gin[i][v] = lrelu'(a_in[i][v]) sum_o sum_k w[i][o][k] gout[o][2 v - 1 + k].
+// gin[i][v] = lrelu'(a_in[i][v]) sum_o sum_k w[i][o][k] gout[o][2 v - 1 + k];
+// lane r of a group takes the output channels o = r, r + R, ...
+template <int R>
 __global__ void tconv_dgrad_kernel(const float* __restrict__ gout, const float* __restrict__ w,
                                    const float* __restrict__ a_in, float* __restrict__ gin, int ci, int co, int D) {
   const int D2 = 2 * D;
   const int64_t n = (int64_t)ci * D * D * D;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+  const int r = threadIdx.x % R;
+  const int64_t groups = (int64_t)gridDim.x * blockDim.x / R;
+  for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / R; e < n; e += groups) {
     const int vx = (int)(e % D), vy = (int)((e / D) % D), vz = (int)((e / D / D) % D);
     const int i = (int)(e / ((int64_t)D * D * D));
     float acc = 0.f;
@@ -65,40 +88,39 @@ __global__ void tconv_dgrad_kernel(const float* __restrict__ gout, const float* 
           if (X < 0 || X >= D2) continue;
           const int64_t oi = ((int64_t)Z * D2 + Y) * D2 + X;
           const int ki = (kz * 4 + ky) * 4 + kx;
-          for (int o = 0; o < co; ++o)
+          for (int o = r; o < co; o += R)
             acc = fmaf(w[((int64_t)i * co + o) * 64 + ki], gout[(int64_t)o * D2 * D2 * D2 + oi], acc);
         }
       }
     }
-    gin[e] = a_in[e] > 0.f ? acc : SLOPE * acc;
+    acc = group_sum<R>(acc);
+    if (r == 0) gin[e] = a_in[e] > 0.f ? acc : SLOPE * acc;
   }
 }
 
-// gw[i][o][k] += sum_v in[i][v] gout[o][2 v - 1 + k].
+// gw[i][o][k] += sum_v in[i][v] gout[o][2 v - 1 + k]; lane r of a group
+// takes the input positions v = r, r + R, ... (flattened).
+template <int R>
 __global__ void tconv_wgrad_kernel(const float* __restrict__ in, const float* __restrict__ gout,
                                    float* __restrict__ gw, int ci, int co, int D) {
-  const int D2 = 2 * D;
+  const int D2 = 2 * D, DDD = D * D * D;
   const int64_t n = (int64_t)ci * co * 64;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+  const int r = threadIdx.x % R;
+  const int64_t groups = (int64_t)gridDim.x * blockDim.x / R;
+  for (int64_t e = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / R; e < n; e += groups) {
     const int ki = (int)(e % 64), kx = ki & 3, ky = (ki >> 2) & 3, kz = ki >> 4;
     const int o = (int)((e / 64) % co), i = (int)(e / 64 / co);
-    const float* src = in + (int64_t)i * D * D * D;
+    const float* src = in + (int64_t)i * DDD;
     const float* g = gout + (int64_t)o * D2 * D2 * D2;
     float acc = 0.f;
-    for (int vz = 0; vz < D; ++vz) {
-      const int Z = 2 * vz - 1 + kz;
-      if (Z < 0 || Z >= D2) continue;
-      for (int vy = 0; vy < D; ++vy) {
-        const int Y = 2 * vy - 1 + ky;
-        if (Y < 0 || Y >= D2) continue;
-        for (int vx = 0; vx < D; ++vx) {
-          const int X = 2 * vx - 1 + kx;
-          if (X < 0 || X >= D2) continue;
-          acc = fmaf(src[((int64_t)vz * D + vy) * D + vx], g[((int64_t)Z * D2 + Y) * D2 + X], acc);
-        }
-      }
+    for (int v = r; v < DDD; v += R) {
+      const int vx = v % D, vy = (v / D) % D, vz = v / (D * D);
+      const int Z = 2 * vz - 1 + kz, Y = 2 * vy - 1 + ky, X = 2 * vx - 1 + kx;
+      if (Z < 0 || Z >= D2 || Y < 0 || Y >= D2 || X < 0 || X >= D2) continue;
+      acc = fmaf(src[v], g[((int64_t)Z * D2 + Y) * D2 + X], acc);
     }
-    gw[e] += acc;
+    acc = group_sum<R>(acc);
+    if (r == 0) gw[e] += acc;
   }
 }
 
@@ -123,6 +145,34 @@ static int grid_of(int64_t n) {
   const int64_t g = (n + 255) / 256;
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
+
+// Lanes per output element: about 512 K lanes in all, at most `terms`
+// (the reduction length) and at most a wave.
+static int lanes_per_output(int64_t n, int64_t terms) {
+  int R = 1;
+  while (R < 64 && n * R * 2 <= (int64_t)1 << 19 && R * 2 <= terms) R *= 2;
+  return R;
+}
+
+// Launches kernel template K<R> for the R that lanes_per_output picks.
+template <template <int> class K, typename... Args>
+static void launch_grouped(int64_t n, int64_t terms, hipStream_t st, Args... args) {
+  const int R = lanes_per_output(n, terms);
+  const dim3 grid(grid_of(n * R)), block(256);
+  switch (R) {
+    case 1: hipLaunchKernelGGL(K<1>::fn, grid, block, 0, st, args...); break;
+    case 2: hipLaunchKernelGGL(K<2>::fn, grid, block, 0, st, args...); break;
+    case 4: hipLaunchKernelGGL(K<4>::fn, grid, block, 0, st, args...); break;
+    case 8: hipLaunchKernelGGL(K<8>::fn, grid, block, 0, st, args...); break;
+    case 16: hipLaunchKernelGGL(K<16>::fn, grid, block, 0, st, args...); break;
+    case 32: hipLaunchKernelGGL(K<32>::fn, grid, block, 0, st, args...); break;
+    default: hipLaunchKernelGGL(K<64>::fn, grid, block, 0, st, args...); break;
+  }
+}
+
+template <int R> struct TconvFwd { static constexpr auto fn = tconv_fwd_kernel<R>; };
+template <int R> struct TconvDgrad { static constexpr auto fn = tconv_dgrad_kernel<R>; };
+template <int R> struct TconvWgrad { static constexpr auto fn = tconv_wgrad_kernel<R>; };
 
 // Activation k (k = 0..4) has channels[k] channels on a (2^k)^3 grid.
 static int64_t act_size(const mnr_skel_cnn* c, int k) { return (int64_t)c->channels[k] << (3 * k); }
@@ -171,8 +221,8 @@ extern "C" mnr_status mnr_skel_cnn_forward(const mnr_skel_cnn* c, float* act, fl
     const float* in = act + act_offset(c, k - 1);
     float* out = k < 5 ? act + act_offset(c, k) : logits;
     const int64_t n = (int64_t)c->channels[k] << (3 * k);
-    hipLaunchKernelGGL(tconv_fwd_kernel, dim3(grid_of(n)), dim3(256), 0, st, in, c->w[k - 1], out, c->channels[k - 1],
-                       c->channels[k], 1 << (k - 1), k < 5 ? 1 : 0);
+    launch_grouped<TconvFwd>(n, c->channels[k - 1], st, in, (const float*)c->w[k - 1], out, c->channels[k - 1],
+                             c->channels[k], 1 << (k - 1), k < 5 ? 1 : 0);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "skel_cnn forward: %s", hipGetErrorString(e));
@@ -193,11 +243,9 @@ extern "C" mnr_status mnr_skel_cnn_backward(const mnr_skel_cnn* c, const float* 
   for (int k = 5; k >= 1; --k) {
     const float* in = act + act_offset(c, k - 1);
     const int D = 1 << (k - 1), ci = c->channels[k - 1], co = c->channels[k];
-    hipLaunchKernelGGL(tconv_wgrad_kernel, dim3(grid_of((int64_t)ci * co * 64)), dim3(256), 0, st, in, g,
-                       grad_w[k - 1], ci, co, D);
+    launch_grouped<TconvWgrad>((int64_t)ci * co * 64, (int64_t)D * D * D, st, in, g, grad_w[k - 1], ci, co, D);
     float* gin = buf[k & 1];
-    hipLaunchKernelGGL(tconv_dgrad_kernel, dim3(grid_of((int64_t)ci * D * D * D)), dim3(256), 0, st, g, c->w[k - 1],
-                       in, gin, ci, co, D);
+    launch_grouped<TconvDgrad>((int64_t)ci * D * D * D, co, st, g, (const float*)c->w[k - 1], in, gin, ci, co, D);
     g = gin;
   }
   hipLaunchKernelGGL(fc_wgrad_kernel, dim3(grid_of((int64_t)c->channels[0] * c->latent)), dim3(256), 0, st, g, c->z,
