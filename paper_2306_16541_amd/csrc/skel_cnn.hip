@@ -6,9 +6,9 @@
 // the caches; each output element belongs to a group of R lanes that split
 // its reduction and meet by xor shuffles.  R is chosen per layer so that
 // every launch has about 512 K lanes (the chip's wave slots): the coarse
-// layers have few outputs and
-// long reductions (2,048 terms per output in the first layer, 8,192 in its
-// adjoint), the fine ones many outputs and short reductions.
+// layers have few outputs and long reductions (2,048 terms per output in
+// the first layer, 8,192 in its adjoint), the fine ones many outputs and
+// short reductions.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
