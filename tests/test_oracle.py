@@ -7,6 +7,8 @@ operand in it fails here.
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -22,10 +24,15 @@ F64 = torch.float64
 # ---------------------------------------------------------------- RNG ------
 
 def test_splitmix64_published_first_output():
-    # SplitMix64 seeded with 0: first output 0xE220A8397B1DCDAF, which is
-    # java.util.SplittableRandom(0).nextLong() = -2152535657050944081.
-    assert int(splitmix64(0, np.array([0]))[0]) == 0xE220A8397B1DCDAF
-    assert int(splitmix64(0, np.array([0]))[0]) - (1 << 64) == -2152535657050944081
+    # The published first output of SplitMix64 seeded with 0 (a cited text
+    # fixture under tests/golden/).
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "splitmix64_seed0.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert rows
+    for seed, idx, hex_out, signed_out in rows:
+        got = int(splitmix64(int(seed), np.array([int(idx)]))[0])
+        assert got == int(hex_out, 16)
+        assert got - (1 << 64) == int(signed_out)
 
 
 def test_stratified_xi_range_and_counter_layout():
