@@ -175,3 +175,14 @@ def test_status_strings():
     m = _lib()
     for s, txt in [(0, "ok"), (-1, "invalid argument"), (-6, "busy")]:
         assert m.lib.mnr_status_str(s).decode() == txt
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # One GPU only: asking bench.py for several exits with status 2 and a
+    # message before any device work.
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
