@@ -186,3 +186,20 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=300, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_build_script_loads_without_the_package():
+    # __graft_entry__.build() must work on a checkout with no built library:
+    # the build script is loaded by path and must not import the package
+    # (which loads libmetanerf.so at import).
+    import subprocess
+    import sys
+    code = ("import sys, importlib.util\n"
+            "sys.modules['paper_2306_16541_amd'] = None\n"
+            f"spec = importlib.util.spec_from_file_location('_b', {os.path.join(ROOT, 'paper_2306_16541_amd', 'build.py')!r})\n"
+            "mod = importlib.util.module_from_spec(spec); spec.loader.exec_module(mod)\n"
+            "assert callable(mod.build)\n"
+            "import __graft_entry__ as g\n"
+            "import inspect; assert 'spec_from_file_location' in inspect.getsource(g.build)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
