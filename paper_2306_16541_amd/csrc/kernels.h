@@ -2,9 +2,36 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_common.h"
 
 namespace mnr {
+
+// Persistent grid size of one kernel instantiation: compute units times the
+// blocks per CU that its LDS and registers allow.  The first launch on any
+// thread raises the kernel's dynamic-LDS limit and queries the occupancy
+// under std::call_once; concurrent launchers (the server's scheduler thread
+// and callers on other streams) wait for it and then only read the result.
+// One process drives one GPU model, so the value is kept per instantiation,
+// not per device.
+struct PersistentGrid {
+  std::once_flag once;
+  int blocks = 1;
+};
+
+template <typename KernelT>
+inline int persistent_blocks(KernelT kern, int threads, int lds, PersistentGrid& g) {
+  std::call_once(g.once, [&] {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, threads, lds);
+    g.blocks = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  });
+  return g.blocks;
+}
 
 // Fused forward renderer.  n_slots: number of ray slots (n_rays, or the
 // 16x16-tiled full frame).  nhh: number of 64->64 hidden layers.

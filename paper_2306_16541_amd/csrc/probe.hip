@@ -10,6 +10,7 @@
 #include "../../include/metanerf_probe.h"
 #include "field_device.h"  // make_rsrc
 #include "host_common.h"
+#include "kernels.h"  // persistent_blocks
 
 namespace mnr {
 
@@ -157,15 +158,8 @@ static hipError_t launch_probe_mlp(const FieldArgs& F, const void* feat, int64_t
   using S = MlpShape<P>;
   const int lds = S::bytes_total(NHH) + 4 * S::feat_bytes_per_wave();
   auto kern = probe_mlp_kernel<P, NHH>;
-  static int max_blocks = 0;
-  if (max_blocks == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 256, lds);
-    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
-  }
+  static PersistentGrid pg;
+  const int max_blocks = persistent_blocks(kern, 256, lds, pg);
   const int64_t need = ((n + 63) / 64 + 3) / 4;
   const int grid = need < max_blocks ? (int)need : max_blocks;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, F, feat, n, out);

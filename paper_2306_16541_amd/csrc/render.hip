@@ -194,19 +194,6 @@ __global__ void __launch_bounds__(64 * NW) render_packet_kernel(const RenderArgs
   }
 }
 
-template <typename KernelT>
-static int persistent_blocks(KernelT kern, int threads, int lds, int* cache) {
-  if (*cache == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, threads, lds);
-    *cache = cus * (per_cu > 0 ? per_cu : 1);
-  }
-  return *cache;
-}
-
 template <typename TableT, int P, int NHH, bool RES, bool FREQ = false>
 static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
   constexpr int NW = block_waves<P, RES, FREQ, false>();
@@ -214,9 +201,9 @@ static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
   if (!a.r.pixel_ids) {  // full frame: 4x4 ray blocks
     const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NW * feat_bytes<P, FREQ>();
     auto kern = render_packet_kernel<TableT, P, NHH, NW, RES, FREQ>;
-    static int max_blocks = 0;
+    static PersistentGrid pg;
     const int n_tiles = n_slots / 256;
-    const int mb = persistent_blocks(kern, 64 * NW, lds, &max_blocks);
+    const int mb = persistent_blocks(kern, 64 * NW, lds, pg);
     const int groups = a.queues ? (n_tiles * 4 * FRAME_G + NW - 1) / NW : (n_tiles + NW / 4 - 1) / (NW / 4);
     const int grid = groups < mb ? groups : mb;
     hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(64 * NW), lds, st, a, n_tiles);
@@ -225,8 +212,8 @@ static hipError_t launch_fwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
   constexpr int NWR = block_waves<P, RES, FREQ, true>();
   const int lds = weight_lds_bytes<P, NHH, RES, FREQ>() + NWR * feat_bytes<P, FREQ>();
   auto kern = render_fwd_kernel<TableT, P, NHH, NWR, RES, FREQ>;
-  static int max_blocks = 0;
-  const int mb = persistent_blocks(kern, 64 * NWR, lds, &max_blocks);
+  static PersistentGrid pg;
+  const int mb = persistent_blocks(kern, 64 * NWR, lds, pg);
   const int need = (n_slots + NWR - 1) / NWR;
   int grid = need < mb ? need : mb;
   if (grid < 1) grid = 1;

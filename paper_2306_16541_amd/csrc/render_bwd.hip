@@ -506,15 +506,8 @@ static hipError_t launch_bwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
   constexpr int NW = (P == MNR_F32) ? 1 : 4;
   const int lds = BwdShape<P>::lds_bytes(NHH, NW);
   auto kern = render_bwd_kernel<TableT, P, NHH, NW>;
-  static int max_blocks = 0;
-  if (max_blocks == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 64 * NW, lds);
-    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
-  }
+  static PersistentGrid pg;
+  const int max_blocks = persistent_blocks(kern, 64 * NW, lds, pg);
   const int need = (n_slots + NW - 1) / NW;
   int grid = need < max_blocks ? need : max_blocks;
   if (grid < 1) grid = 1;

@@ -44,15 +44,8 @@ static hipError_t launch_serve_t(const RenderArgs* slots, WorkTable* wt, hipStre
   using S = MlpShape<P>;
   const int lds = S::bytes_total(NHH) + WAVES_PER_BLOCK * S::feat_bytes_per_wave();
   auto kern = serve_kernel<TableT, P, NHH>;
-  static int max_blocks = 0;
-  if (max_blocks == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds);
-    max_blocks = cus * (per_cu > 0 ? per_cu : 1);
-  }
+  static PersistentGrid pg;
+  const int max_blocks = persistent_blocks(kern, BLOCK, lds, pg);
   if (!slots) return hipGetLastError();
   hipLaunchKernelGGL(kern, dim3(max_blocks), dim3(BLOCK), lds, st, slots, wt);
   return hipGetLastError();
