@@ -236,6 +236,15 @@ mnr_status mnr_refiner_apply(const mnr_refiner* refiner, int32_t n_joints, const
  * grad_delta = dL/d(delta) (host [n][3]). */
 mnr_status mnr_refiner_backward(const mnr_refiner* refiner, int32_t n_joints, const float* omega,
                                 const float* grad_delta, float* const* grad_w);
+/* Adam (Sec. 5.2: beta1 = 0.9, beta2 = 0.99) on the refiner's host weights,
+ * one call per optimiser step.  w[k] must be the writable buffers that
+ * refiner->w[k] points to; grad_w[k], m[k], v[k] have the same shapes (host
+ * float, caller-owned, m and v zero before step 1).  step is 1-based (bias
+ * correction).  Updates w, m, v in place, computing in double precision,
+ * and clears grad_w for the next accumulation. */
+mnr_status mnr_refiner_adam(const mnr_refiner* refiner, int32_t n_joints, float* const* w, float* const* grad_w,
+                            float* const* m, float* const* v, int32_t step, float lr, float beta1, float beta2,
+                            float eps);
 
 /* Render rays (Sec. 4, Fig. 2; Eq. 3, 7-9, 13).  pixel_ids: dev int32
  * [n_rays] pixel indices of an H x W image, or NULL for the full frame in

@@ -480,12 +480,15 @@ class Refiner(C.Structure):
 
 _sig("mnr_refiner_apply", C.c_int, [C.POINTER(Refiner), C.c_int32, C.c_void_p, C.c_void_p])
 _sig("mnr_refiner_backward", C.c_int, [C.POINTER(Refiner), C.c_int32, C.c_void_p, C.c_void_p, _PL])
+_sig("mnr_refiner_adam", C.c_int, [C.POINTER(Refiner), C.c_int32, _PL, _PL, _PL, _PL, C.c_int32, C.c_float,
+                                   C.c_float, C.c_float, C.c_float])
 
 
 class PoseRefiner:
     """Host pose refiner MLP_theta (include/metanerf.h, mnr_refiner): FP32
     weights [out, in] held in numpy arrays, evaluated and differentiated by
-    the library in double precision; Adam (beta 0.9/0.99) on the host."""
+    the library in double precision; Adam (beta 0.9/0.99) by the library on
+    the host."""
 
     def __init__(self, weights: Sequence[np.ndarray], lr: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
                  eps: float = 1e-8):
@@ -517,15 +520,12 @@ class PoseRefiner:
                                        C.cast(ptrs, _PL)), "refiner_backward")
 
     def step(self) -> None:
-        """Adam on the accumulated gradients, then clear them."""
+        """Adam (the library's mnr_refiner_adam) on the accumulated gradients,
+        which it then clears."""
         self.t += 1
-        for w, g, m1, m2 in zip(self.w, self.g, self.m1, self.m2):
-            m1 *= self.b1; m1 += (1 - self.b1) * g
-            m2 *= self.b2; m2 += (1 - self.b2) * g * g
-            mh = m1 / (1 - self.b1 ** self.t)
-            vh = m2 / (1 - self.b2 ** self.t)
-            w -= (self.lr * mh / (np.sqrt(vh) + self.eps)).astype(np.float32)
-            g[:] = 0
+        arr = lambda xs: C.cast((C.c_void_p * len(xs))(*[x.ctypes.data for x in xs]), _PL)
+        check(lib.mnr_refiner_adam(C.byref(self.c), self.w[0].shape[1] // 3, arr(self.w), arr(self.g), arr(self.m1),
+                                   arr(self.m2), self.t, self.lr, self.b1, self.b2, self.eps), "refiner_adam")
 
 
 def mse_loss(rgba: torch.Tensor, target: torch.Tensor, grad_rgba: torch.Tensor,

@@ -253,3 +253,31 @@ extern "C" mnr_status mnr_refiner_backward(const mnr_refiner* r, int32_t n_joint
   }
   return MNR_OK;
 }
+
+extern "C" mnr_status mnr_refiner_adam(const mnr_refiner* r, int32_t n_joints, float* const* w, float* const* grad_w,
+                                       float* const* m, float* const* v, int32_t step, float lr, float beta1,
+                                       float beta2, float eps) {
+  clear_error();
+  if (mnr_status s = validate_refiner(r, n_joints)) return s;
+  if (!w || !grad_w || !m || !v) return fail(MNR_E_INVALID, "refiner_adam: null pointer");
+  if (step < 1) return fail(MNR_E_INVALID, "refiner_adam: step must be >= 1");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(MNR_E_INVALID, "refiner_adam: bad hyper-parameters");
+  for (int k = 0; k < r->n_layers; ++k)
+    if (!w[k] || !grad_w[k] || !m[k] || !v[k]) return fail(MNR_E_INVALID, "refiner_adam: null layer %d", k);
+  const double bc1 = 1.0 - std::pow((double)beta1, (double)step);
+  const double bc2 = 1.0 - std::pow((double)beta2, (double)step);
+  for (int k = 0; k < r->n_layers; ++k) {
+    const size_t n = (size_t)r->width[k] * r->width[k + 1];
+    for (size_t i = 0; i < n; ++i) {
+      const double g = grad_w[k][i];
+      const double mi = beta1 * (double)m[k][i] + (1.0 - beta1) * g;
+      const double vi = beta2 * (double)v[k][i] + (1.0 - beta2) * g * g;
+      m[k][i] = (float)mi;
+      v[k][i] = (float)vi;
+      w[k][i] = (float)((double)w[k][i] - lr * (mi / bc1) / (std::sqrt(vi / bc2) + eps));
+      grad_w[k][i] = 0.f;
+    }
+  }
+  return MNR_OK;
+}

@@ -67,3 +67,33 @@ def test_refiner_rejects_bad_shapes():
         assert "widths" in str(e)
     else:
         raise AssertionError("accepted a refiner whose input is not 3 n_joints wide")
+
+
+def test_refiner_adam_step_matches_adam_written_out():
+    # Two steps of the library's host Adam against the update written out
+    # here (Kingma and Ba 2015, with bias correction; beta = 0.9 / 0.99 as in
+    # Sec. 5.2); the gradients are cleared after each step.
+    m = _m()
+    g = np.random.default_rng(8)
+    ws = [(g.standard_normal((16, 72)) * 0.2).astype(np.float32), (g.standard_normal((72, 16)) * 0.2).astype(np.float32)]
+    lr, b1, b2, eps = 1e-2, 0.9, 0.99, 1e-8
+    ref = m.PoseRefiner(ws, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    w = [x.astype(np.float64) for x in ws]
+    mm = [np.zeros_like(x) for x in w]
+    vv = [np.zeros_like(x) for x in w]
+    for t in (1, 2):
+        grads = [g.standard_normal(x.shape).astype(np.float32) for x in ws]
+        for k in range(2):
+            ref.g[k][:] = grads[k]
+        ref.step()
+        for k in range(2):
+            gk = grads[k].astype(np.float64)
+            mm[k] = b1 * mm[k] + (1 - b1) * gk
+            vv[k] = b2 * vv[k] + (1 - b2) * gk * gk
+            w[k] = w[k] - lr * (mm[k] / (1 - b1 ** t)) / (np.sqrt(vv[k] / (1 - b2 ** t)) + eps)
+            np.testing.assert_allclose(ref.w[k], w[k], rtol=0, atol=2e-6)
+            assert not ref.g[k].any()
+        # the refiner reads the updated weights
+        aa = scenes.pose(7, 0.3).astype(np.float32)
+        np.testing.assert_allclose(ref.apply(aa), refine([torch.as_tensor(x) for x in w], aa.astype(np.float64)).numpy(),
+                                   rtol=1e-4, atol=1e-5)
