@@ -263,6 +263,26 @@ mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mn
                       float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
                       void* workspace, void* stream);
 
+/* mnr_render for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as
+ * mnr_render with a workspace, minus the workspace: the work-queue counters
+ * live in a library-owned device array of MNR_NOALLOC_SCRATCH_BYTES that
+ * each GPU holds from the first call on it until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); it clears the counters with a fill kernel on `stream` before
+ * the render.  The counters' size does not depend on the frame or ray
+ * count, so every size mnr_render accepts is accepted here.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (distinct
+ * streams, or host threads without ordering) race on it and must be
+ * serialised by the caller; calls in one stream are ordered. */
+#define MNR_NOALLOC_SCRATCH_BYTES 64
+mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                              const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
+                              const mnr_opts* opts, const int32_t* pixel_ids, int32_t n_rays,
+                              float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
+                              void* stream);
+
 /* Adjoint of mnr_render (hand-written; recomputes per-sample activations
  * instead of storing them).  Given t_chunks written by mnr_render with the
  * same arguments and dL/d(rgba) grad_rgba (dev [n_rays][4]), ACCUMULATES

@@ -95,6 +95,7 @@ _sig("mnr_fk_bones", C.c_int, [C.POINTER(Pose), C.c_void_p])
 _RENDER_COMMON = [C.POINTER(Field), C.POINTER(Motion), C.POINTER(Pose), C.POINTER(Camera), C.c_int32, C.c_int32,
                   C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_int32]
 _sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_sig("mnr_render_noalloc", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_render_backward", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
                                                        C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_fk_backward", C.c_int, [C.POINTER(Pose), C.c_void_p, C.c_void_p, C.c_void_p])
@@ -116,7 +117,8 @@ _sig("mnr_probe_atomic", C.c_int, [C.c_void_p, C.c_uint32, C.c_int32, C.c_int32,
 _sig("mnr_probe_mlp", C.c_int, [C.POINTER(Field), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
-EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_backward",
+EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_noalloc",
+            "mnr_render_backward",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
             "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_probe_mlp", "mnr_fk_backward", "mnr_refiner_apply",
@@ -377,6 +379,20 @@ def render(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp:
     check(lib.mnr_render(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                          None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(out), _ptr(t_chunks),
                          _ptr(counter), _ptr(_workspace(out.device)) if dynamic else None, _stream()), "render")
+    return out
+
+
+def render_noalloc(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int,
+                   opts: Optional[Opts] = None, pixel_ids: Optional[torch.Tensor] = None,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """render() through mnr_render_noalloc: the library's own work-queue
+    counters instead of a workspace (the library allocates nothing)."""
+    n = H * W if pixel_ids is None else int(pixel_ids.numel())
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=field.weights.device)
+    check(lib.mnr_render_noalloc(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
+                                 None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(out), None, None,
+                                 _stream()), "render_noalloc")
     return out
 
 

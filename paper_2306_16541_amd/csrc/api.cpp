@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "host_common.h"
 #include "kernels.h"
@@ -228,13 +229,43 @@ const char* mnr_last_error(void) { return g_err; }
 
 const char* mnr_version(void) { return "metanerf-gfx950 0.1"; }
 
-mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose, const mnr_camera* cam,
-                      int32_t H, int32_t W, int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
-                      int32_t n_rays, float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
-                      void* workspace, void* stream) {
-  clear_error();
-  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba)) return s;
-  if (n_rays == 0) return MNR_OK;
+}  // extern "C"
+
+// Work-queue counters of mnr_render_noalloc: a file-scope device array in
+// place of the caller's workspace, MNR_NOALLOC_SCRATCH_BYTES per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it only names the symbol): the address each device
+// gives it is looked up once per device and kept in g_scratch_dev.
+static __device__ __align__(256) int32_t scratch[MNR_NOALLOC_SCRATCH_BYTES / sizeof(int32_t)];
+static_assert(MNR_NOALLOC_SCRATCH_BYTES >= MNR_WORKSPACE_BYTES, "the queues need MNR_WORKSPACE_BYTES");
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+static mnr_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "render_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(MNR_E_UNSUPPORTED, "render_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e, "render_noalloc: hipGetSymbolAddress");
+    if (!p) return fail(MNR_E_HIP, "render_noalloc: null scratch address");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MNR_OK;
+}
+
+static mnr_status render_impl(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                              const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
+                              const int32_t* pixel_ids, int32_t n_rays, float* out_rgba, float* t_chunks,
+                              unsigned long long* n_evaluated, void* workspace, void* stream) {
   RenderArgs a;
   pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
   a.out = out_rgba;
@@ -248,6 +279,33 @@ mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mn
                                       field->n_layers - 2, (hipStream_t)stream),
                     "render launch");
 }
+
+extern "C" {
+
+mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose, const mnr_camera* cam,
+                      int32_t H, int32_t W, int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
+                      int32_t n_rays, float* out_rgba, float* t_chunks, unsigned long long* n_evaluated,
+                      void* workspace, void* stream) {
+  clear_error();
+  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba)) return s;
+  if (n_rays == 0) return MNR_OK;
+  return render_impl(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba, t_chunks, n_evaluated,
+                     workspace, stream);
+}
+
+mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
+                              const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
+                              const int32_t* pixel_ids, int32_t n_rays, float* out_rgba, float* t_chunks,
+                              unsigned long long* n_evaluated, void* stream) {
+  clear_error();
+  if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba)) return s;
+  if (n_rays == 0) return MNR_OK;
+  void* ws = nullptr;
+  if (mnr_status s = scratch_address(&ws)) return s;
+  return render_impl(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, out_rgba, t_chunks, n_evaluated,
+                     ws, stream);
+}
+
 
 mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
                                const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
