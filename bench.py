@@ -127,6 +127,18 @@ def roofline(res, sc, enc_key, mlp_key, widths):
     return (hbm, mf) if hbm["frac"] >= mf["frac"] else (mf, hbm)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def oracle_sample(sc, img_fp32, img_mixed, budget_s):
     """FP64 oracle on a bounded random sample of the frame's pixels."""
     import oracle
@@ -143,7 +155,7 @@ def oracle_sample(sc, img_fp32, img_mixed, budget_s):
     ref = np.concatenate(refs)
     hit = ref[:, 3] > 0
     out = {"value": done * sc.spp / el / 1e6, "unit": "Msamples/s (nominal)", "cores": torch.get_num_threads(),
-           "kind": "oracle",
+           "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
            "sample": f"{done} random pixels of the {sc.H}x{sc.W}x{sc.spp} frame ({done * sc.spp} nominal samples, "
                      f"{el:.1f} s, float64 torch CPU)"}
     par = {}
@@ -265,19 +277,20 @@ def train_bench(steps, warmup):
     m.mse_loss(rgba, tgt, g_rgba)
     b = tr.buf
 
-    def bwd():
+    def bwd(ws, gG=None):
         m.render_backward(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, g_rgba, b["table_grad"],
-                          b["w_grad"], b["weights_grad"])
+                          b["w_grad"], b["weights_grad"], grad_bones=gG, adjoint_ws=ws)
     for t in [b["table_grad"], b["weights_grad"]] + b["w_grad"]:
         t.zero_()
-    _, bwd_ms = timed_launches(bwd, steps, 1)
+    # the adjoint as the training step runs it (hashed levels through the
+    # binned scatter), and with every table gradient added by global atomics
+    _, bwd_ms = timed_launches(lambda: bwd(tr.adjoint_ws), steps, 1)
+    _, bwd_atomic_ms = timed_launches(lambda: bwd(None), steps, 1)
     gG = torch.zeros(24, 3, 4, device=dev)
-
-    def bwd_pose():
-        m.render_backward(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, g_rgba, b["table_grad"],
-                          b["w_grad"], b["weights_grad"], grad_bones=gG)
-    _, bwd_pose_ms = timed_launches(bwd_pose, steps, 1)
+    _, bwd_pose_ms = timed_launches(lambda: bwd(tr.adjoint_ws, gG), steps, 1)
     res["adjoint_with_bone_grads_ms"] = bwd_pose_ms
+    res["adjoint_atomic_scatter_ms"] = bwd_atomic_ms
+    res["binned_scatter"] = tr.adjoint_ws is not None
     # skeleton-motion CNN (32^3 x 25 logits from the 256-d latent): forward and adjoint per step
     cnn = m.SkeletonCNN(*scenes.skel_cnn_weights(5))
     glog = torch.ones(25, 32, 32, 32, device=dev)
@@ -286,12 +299,13 @@ def train_bench(steps, warmup):
     res["skel_cnn_ms"] = {"forward": cnn_f, "adjoint": cnn_b}
     atomics = n_eval * (16 * 8 * 2 + 24 * 8)
     res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
+    res["hashed_level_records"] = n_eval * 9 * 8
     res["evaluated_samples"] = n_eval
-    res["adjoint_atomics_per_s_upper"] = atomics / (bwd_ms * 1e-3)
+    res["adjoint_atomics_per_s_upper"] = atomics / (bwd_atomic_ms * 1e-3)
     return res
 
 
-def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 2.0, 2.0),
+def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 10.0, 10.0),
                 tiles_per_tick=1024):
     """Poisson arrivals from U users at rate_hz each; resolutions uniform over
     {256^2, 512^2, 1024^2}; per-user fields resident (FP16 table, BF16 MLP);

@@ -254,8 +254,9 @@ mnr_status mnr_refiner_adam(const mnr_refiner* refiner, int32_t n_joints, float*
  * t_chunks (optional, dev float [n_rays][ceil(spp/64) + 1]): the state the
  * adjoint needs -- transmittance at the start of each 64-sample chunk the
  * ray reached (-1 for chunks it never reached), then the number of samples
- * it processed.  Missed rays leave their rows untouched; the adjoint skips
- * them.  n_evaluated (optional, dev uint64, accumulated with atomics)
+ * it processed.  A ray that misses the box (or a listed id outside the
+ * image) gets -1 in every chunk entry and 0 processed samples; the adjoint
+ * skips it.  n_evaluated (optional, dev uint64, accumulated with atomics)
  * counts the samples actually evaluated. */
 mnr_status mnr_render(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
                       const mnr_camera* cam, int32_t H, int32_t W, int32_t spp,
@@ -295,13 +296,38 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
  *                blend weights, per wave summed before one atomic per entry;
  *                mnr_fk_backward carries it on to the pose.
  * Gradients are those of the forward actually computed (early termination
- * included).  Summation order of the atomics is not deterministic. */
+ * included).  Summation order of the atomics is not deterministic.
+ * grad_res (NULL unless motion->res_w[0] != NULL): dev float pointers for
+ * the residual motion network's gradients, W1..W5 and W_omega (shapes as
+ * motion->res_w), accumulated.  The adjoint then runs split: the warp and
+ * residual network forward, the field's adjoint at x_final, the residual
+ * network's adjoint (Sec. 4.3, Eq. 11-12, on BF16 MFMA) and the skinning
+ * adjoint at x_skel, passing per-sample values through the workspace.
+ * adjoint_ws (dev, 256-byte aligned, adjoint_ws_bytes >=
+ * mnr_adjoint_ws_bytes(field, motion, n_rays, spp); contents are scratch):
+ *   - with hashed grid levels, their gradient leaves the adjoint as (row,
+ *     value) records that are binned by table slice and summed in LDS,
+ *     instead of one global float atomic per sample, corner and feature
+ *     (the same sum in another order);
+ *   - with a residual network, the split adjoint's per-sample values.
+ * NULL: atomics for the table, and no residual network (MNR_E_INVALID). */
 mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                const mnr_pose* pose, const mnr_camera* cam, int32_t H, int32_t W,
                                int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
                                int32_t n_rays, const float* t_chunks, const float* grad_rgba,
                                float* grad_table, float* const* grad_w, float* grad_weights,
-                               float* grad_bones, void* workspace, void* stream);
+                               float* grad_bones, float* const* grad_res, void* workspace,
+                               void* adjoint_ws, uint64_t adjoint_ws_bytes, void* stream);
+
+/* Bytes of the adjoint workspace for a batch of n_rays rays of spp samples:
+ * binned-scatter records for every sample, hashed level and corner (12
+ * bytes each, twice) plus bin histograms -- about 200 bytes per sample for
+ * the 9 hashed levels of a 2^19-row, 16-level table, none when the batch
+ * (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14 rows)
+ * is too large for the binned path -- plus, with a residual network, 56 bytes per
+ * sample slot (n_rays * ceil(spp / 64) * 64 slots).  0: nothing to use it
+ * for. */
+uint64_t mnr_adjoint_ws_bytes(const mnr_field* field, const mnr_motion* motion, int32_t n_rays, int32_t spp);
 
 /* Patch ray batch for training (Sec. 5.2: n_patches patches of size x size
  * pixels per image, so that patch losses can be taken): patch k's top-left
@@ -386,6 +412,13 @@ typedef struct {
   float* t_chunks;                                    /* [n_rays][ceil(spp/64) + 1] scratch */
   float* loss;                                                            /* [1] */
   void* workspace;                                           /* MNR_WORKSPACE_BYTES, or NULL */
+  void* adjoint_ws; uint64_t adjoint_ws_bytes;   /* see mnr_render_backward; required with a residual network */
+  /* Residual motion network (when motion->res_w[0] != NULL): FP32 masters,
+   * gradients and Adam moments of W1..W5, W_omega (shapes as motion->res_w);
+   * Adam at lr_res updates the masters and rewrites the BF16 copies
+   * motion->res_w[k] (which the step therefore writes). */
+  float* res_master[6]; float* res_grad[6]; float* res_m[6]; float* res_v[6];
+  float lr_res;
   float lr_field, lr_motion, beta1, beta2, eps;
   int32_t step;                                                           /* 1-based */
   int32_t train_motion;  /* 0 = logits frozen; 1 = Adam on the logits; 2 = only dL/dlogits into logits_grad

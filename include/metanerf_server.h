@@ -28,9 +28,16 @@
  * All calls are thread-safe.  Device memory: the server allocates its
  * request slots and tile tables; users' fields and request outputs are
  * caller-owned and must stay valid while in use.  The server works on its
- * own streams, unordered with the caller's streams: a field or output
- * buffer must have no pending work on other streams when it is registered
- * or submitted, and must not be reused until the request has completed.
+ * own streams.  A field must have no pending work on other streams when it
+ * is registered.  An output buffer is ordered after the work queued on the
+ * stream passed to mnr_server_submit (if any) at the time of the call; it
+ * must stay allocated, and must not be read or reused, until poll or wait
+ * has reported the request finished.
+ * Request records live from submit until the poll or wait that reports
+ * them finished, which releases them: a ticket is reported finished once.
+ * After a GPU error every pending request finishes as failed (MNR_E_HIP);
+ * kernels already running may still write their outputs, and the server
+ * takes no new work.
  */
 #ifndef METANERF_SERVER_H
 #define METANERF_SERVER_H
@@ -45,8 +52,10 @@ typedef struct mnr_server mnr_server;
 
 typedef struct {
   uint64_t submitted, completed, rejected;
+  uint64_t failed;                 /* finished without a frame (GPU error, budget) */
   uint64_t ticks, tiles;
   int32_t queued, admitted;        /* right now */
+  int32_t tracked;                 /* request records not yet released */
   uint64_t resident_bytes;         /* registered users */
   uint64_t inflight_bytes;         /* outputs of admitted requests */
 } mnr_server_stats;
@@ -60,21 +69,29 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
 /* Register user `user` (0..1023) with a resident field and blend-weight
  * volume (dev pointers, caller-owned).  Every user of a server must share
  * the field format (dtypes, layer count).  MNR_E_OOM when the resident
- * bytes would exceed the budget; MNR_E_INVALID if the id is taken. */
+ * bytes plus the outputs of queued and admitted requests would exceed the
+ * budget (so that every queued request still fits once the ones ahead of
+ * it finish); MNR_E_INVALID if the id is taken. */
 mnr_status mnr_server_add_user(mnr_server* srv, int32_t user, const mnr_field* field, const mnr_motion* motion);
 
 /* Queue a frame: pose and camera are read during the call (FK runs here);
  * out_rgba: dev float [H*W][4], written when the request completes.
- * MNR_E_OOM when the output alone exceeds the budget, MNR_E_INVALID for a
- * bad pose/camera or unknown user. */
+ * after_stream (a hipStream_t, or NULL): the request's first tick waits for
+ * the work queued on that stream at the time of this call (e.g. the last
+ * reader of out_rgba).  MNR_E_OOM when the output alone exceeds the
+ * budget, MNR_E_INVALID for a bad pose/camera or unknown user. */
 mnr_status mnr_server_submit(mnr_server* srv, int32_t user, const mnr_pose* pose, const mnr_camera* cam,
                              int32_t H, int32_t W, int32_t spp, const mnr_opts* opts, float* out_rgba,
-                             uint64_t* ticket);
+                             void* after_stream, uint64_t* ticket);
 
-/* done = 1 once the frame is in out_rgba.  t_ns (optional, 4 entries):
- * arrival, admission, first tick launch, completion (steady clock, ns). */
+/* done = 1 once the request has finished (the frame is in out_rgba, or it
+ * failed: then the call returns MNR_E_HIP after a GPU error, or MNR_E_OOM
+ * for a request that can no longer fit the budget); reporting it releases
+ * the ticket.  t_ns (optional, 4 entries): arrival, admission, first tick
+ * launch, completion (steady clock, ns). */
 mnr_status mnr_server_poll(mnr_server* srv, uint64_t ticket, int32_t* done, int64_t* t_ns);
-/* Block until the ticket completes (or timeout_ms elapses: MNR_E_BUSY). */
+/* Block until the ticket finishes (or timeout_ms elapses: MNR_E_BUSY), then
+ * report it as poll does (and release it). */
 mnr_status mnr_server_wait(mnr_server* srv, uint64_t ticket, int32_t timeout_ms, int64_t* t_ns);
 mnr_status mnr_server_get_stats(mnr_server* srv, mnr_server_stats* stats);
 /* Finish admitted and queued work, stop the scheduler, free device memory. */

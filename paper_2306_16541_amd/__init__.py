@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libmetanerf.so")
 
 MAX_BONES, MAX_LEVELS, MAX_LAYERS = 32, 16, 5
 F32, F16, BF16 = 0, 1, 2
+MNR_E_BUSY = -6
 _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 
 
@@ -77,7 +78,9 @@ class TrainState(C.Structure):
                  ("w_v", _FP * MAX_LAYERS)] +
                 [("logits", _FP), ("logits_grad", _FP), ("logits_m", _FP), ("logits_v", _FP),
                  ("weights_grad", _FP), ("rgba", _FP), ("grad_rgba", _FP), ("t_chunks", _FP), ("loss", _FP),
-                 ("workspace", _FP),
+                 ("workspace", _FP), ("adjoint_ws", _FP), ("adjoint_ws_bytes", C.c_uint64),
+                 ("res_master", _FP * 6), ("res_grad", _FP * 6), ("res_m", _FP * 6), ("res_v", _FP * 6),
+                 ("lr_res", C.c_float),
                  ("lr_field", C.c_float), ("lr_motion", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                  ("eps", C.c_float), ("step", C.c_int32), ("train_motion", C.c_int32)])
 
@@ -97,7 +100,9 @@ _RENDER_COMMON = [C.POINTER(Field), C.POINTER(Motion), C.POINTER(Pose), C.POINTE
 _sig("mnr_render", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_render_noalloc", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_render_backward", C.c_int, _RENDER_COMMON + [C.c_void_p, C.c_void_p, C.c_void_p, _PL, C.c_void_p,
-                                                       C.c_void_p, C.c_void_p, C.c_void_p])
+                                                       C.c_void_p, _PL, C.c_void_p, C.c_void_p, C.c_uint64,
+                                                       C.c_void_p])
+_sig("mnr_adjoint_ws_bytes", C.c_uint64, [C.POINTER(Field), C.POINTER(Motion), C.c_int32, C.c_int32])
 _sig("mnr_fk_backward", C.c_int, [C.POINTER(Pose), C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_mse_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p])
 _sig("mnr_softmax_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p])
@@ -118,7 +123,7 @@ _sig("mnr_probe_mlp", C.c_int, [C.POINTER(Field), C.c_void_p, C.c_int64, C.c_voi
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
 EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "mnr_render", "mnr_render_noalloc",
-            "mnr_render_backward",
+            "mnr_render_backward", "mnr_adjoint_ws_bytes",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
             "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_probe_mlp", "mnr_fk_backward", "mnr_refiner_apply",
@@ -271,7 +276,7 @@ class DeviceField:
         FP32 W1..W5 and W_omega (arrays or tensors), stored as BF16 copies
         made by the library's conversion kernel; alpha = Hann window position."""
         dev = self.weights.device
-        ws = [torch.as_tensor(np.asarray(w, dtype=np.float32), device=dev) for w in list(weights) + [w_omega]]
+        ws = [torch.as_tensor(w, dtype=torch.float32, device=dev) for w in list(weights) + [w_omega]]
         self.res_w = [convert(w.contiguous(), BF16) for w in ws]
         for k, w in enumerate(self.res_w):
             self.m.res_w[k] = w.data_ptr()
@@ -396,18 +401,39 @@ def render_noalloc(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: i
     return out
 
 
+def adjoint_ws_bytes(field: DeviceField, n_rays: int, spp: int) -> int:
+    """Bytes of the adjoint workspace (0: nothing to use it for)."""
+    return int(lib.mnr_adjoint_ws_bytes(C.byref(field.c), C.byref(field.m), int(n_rays), int(spp)))
+
+
+def adjoint_workspace(field: DeviceField, n_rays: int, spp: int) -> Optional[torch.Tensor]:
+    """A device buffer for the adjoint (binned table scatter, split adjoint of
+    the residual network), or None when there is nothing to use it for."""
+    nb = adjoint_ws_bytes(field, n_rays, spp)
+    if nb == 0:
+        return None
+    return torch.empty(nb, dtype=torch.uint8, device=field.weights.device)
+
+
 def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts],
                     pixel_ids: Optional[torch.Tensor], t_chunks: torch.Tensor, grad_rgba: torch.Tensor,
                     grad_table: torch.Tensor, grad_w: List[torch.Tensor], grad_weights: torch.Tensor,
-                    grad_bones: Optional[torch.Tensor] = None) -> None:
+                    grad_bones: Optional[torch.Tensor] = None, adjoint_ws: Optional[torch.Tensor] = None,
+                    grad_res: Optional[List[torch.Tensor]] = None) -> None:
     """Accumulates the adjoint into the gradient buffers; grad_bones
-    (optional, [n_bones, 3, 4]) receives dL/dG of the bone transforms."""
+    (optional, [n_bones, 3, 4]) receives dL/dG of the bone transforms.
+    adjoint_ws (from adjoint_workspace): binned scatter of the hashed levels'
+    table gradient instead of atomics, and the residual network's split
+    adjoint, whose gradients (W1..W5, W_omega) go to grad_res."""
     n = H * W if pixel_ids is None else int(pixel_ids.numel())
     gw = (C.c_void_p * len(grad_w))(*[g.data_ptr() for g in grad_w])
+    gr = None if grad_res is None else C.cast((C.c_void_p * 6)(*[g.data_ptr() for g in grad_res]), _PL)
+    nb = 0 if adjoint_ws is None else adjoint_ws.numel() * adjoint_ws.element_size()
     check(lib.mnr_render_backward(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                                   None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(t_chunks),
                                   _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights),
-                                  _ptr(grad_bones), _ptr(_workspace(grad_table.device)), _stream()),
+                                  _ptr(grad_bones), gr, _ptr(_workspace(grad_table.device)), _ptr(adjoint_ws), nb,
+                                  _stream()),
           "render_backward")
 
 
@@ -596,10 +622,15 @@ class Trainer:
                  table_dtype: int = F32, mlp_dtype: int = F32, max_rays: int = 8192, spp: int = 128,
                  lr_field: float = 5e-4, lr_motion: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
                  eps: float = 1e-8, train_motion: bool = True, box_min=(-0.5,) * 3, box_max=(0.5,) * 3,
-                 skel_cnn: Optional["SkeletonCNN"] = None):
+                 skel_cnn: Optional["SkeletonCNN"] = None, binned_scatter: bool = True,
+                 residual: Optional[tuple] = None, lr_res: float = 5e-4):
         """skel_cnn: generate the blend-weight logits with the skeleton-motion
         CNN (logits32 is then ignored) and train its weights instead of free
-        logits (lr_motion applies to them)."""
+        logits (lr_motion applies to them).  binned_scatter: give the adjoint
+        a workspace for the binned scatter of the hashed levels' gradient
+        (else it adds them with atomics).  residual: (W1..W5, W_omega, alpha)
+        of the residual motion network, trained with Adam at lr_res (the
+        window position alpha is the caller's schedule: set_alpha)."""
         dev = table32.device
         self.table32 = table32.contiguous().clone()
         self.mlp32 = [w.contiguous().clone() for w in mlp32]
@@ -609,6 +640,12 @@ class Trainer:
         self.table = self.table32 if table_dtype == F32 else convert(self.table32, table_dtype)
         self.mlp = self.mlp32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in self.mlp32]
         self.field = DeviceField(self.table, self.mlp, self.weights, level_res, box_min, box_max)
+        self.res32 = None
+        if residual is not None:
+            rw, w_omega, alpha = residual
+            self.res32 = [torch.as_tensor(np.asarray(w, dtype=np.float32), device=dev).contiguous().clone()
+                          for w in list(rw) + [w_omega]]
+            self.field.set_residual(self.res32[:5], self.res32[5], alpha)
         z = lambda t: torch.zeros_like(t, dtype=torch.float32)
         self.buf = {
             "table_grad": z(self.table32), "table_m": z(self.table32), "table_v": z(self.table32),
@@ -632,6 +669,16 @@ class Trainer:
         s.weights_grad, s.rgba, s.grad_rgba = b["weights_grad"].data_ptr(), b["rgba"].data_ptr(), b["grad_rgba"].data_ptr()
         s.t_chunks, s.loss = b["t_chunks"].data_ptr(), b["loss"].data_ptr()
         s.workspace = b["workspace"].data_ptr()
+        self.adjoint_ws = (adjoint_workspace(self.field, max_rays, spp)
+                           if binned_scatter or residual is not None else None)
+        if self.adjoint_ws is not None:
+            s.adjoint_ws, s.adjoint_ws_bytes = self.adjoint_ws.data_ptr(), self.adjoint_ws.numel()
+        if self.res32 is not None:
+            b["res_grad"], b["res_m"], b["res_v"] = ([z(w) for w in self.res32] for _ in range(3))
+            for k in range(6):
+                s.res_master[k], s.res_grad[k] = self.res32[k].data_ptr(), b["res_grad"][k].data_ptr()
+                s.res_m[k], s.res_v[k] = b["res_m"][k].data_ptr(), b["res_v"][k].data_ptr()
+        s.lr_res = lr_res
         s.lr_field, s.lr_motion, s.beta1, s.beta2, s.eps = lr_field, lr_motion, beta1, beta2, eps
         s.step, s.train_motion = 0, (2 if skel_cnn is not None else 1) if train_motion else 0
         self.state = s
@@ -654,6 +701,10 @@ class Trainer:
             softmax_fwd(self.logits, out=self.weights)
             if self.field.packed is not None:
                 check(lib.mnr_motion_pack(C.byref(self.field.m), _stream()), "motion_pack")
+
+    def set_alpha(self, alpha: float) -> None:
+        """Window position of the residual network's frequency bands."""
+        self.field.m.res_alpha = float(alpha)
 
     def loss(self) -> float:
         return float(self.buf["loss"].item())
@@ -695,14 +746,15 @@ class Trainer:
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
-                ("ticks", C.c_uint64), ("tiles", C.c_uint64), ("queued", C.c_int32), ("admitted", C.c_int32),
-                ("resident_bytes", C.c_uint64), ("inflight_bytes", C.c_uint64)]
+                ("failed", C.c_uint64), ("ticks", C.c_uint64), ("tiles", C.c_uint64), ("queued", C.c_int32),
+                ("admitted", C.c_int32), ("tracked", C.c_int32), ("resident_bytes", C.c_uint64),
+                ("inflight_bytes", C.c_uint64)]
 
 
 _sig("mnr_server_create", C.c_int, [C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)])
 _sig("mnr_server_add_user", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Field), C.POINTER(Motion)])
 _sig("mnr_server_submit", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Pose), C.POINTER(Camera), C.c_int32, C.c_int32,
-                                    C.c_int32, C.POINTER(Opts), C.c_void_p, C.POINTER(C.c_uint64)])
+                                    C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)])
 _sig("mnr_server_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_void_p])
 _sig("mnr_server_wait", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p])
 _sig("mnr_server_get_stats", C.c_int, [C.c_void_p, C.POINTER(ServerStats)])
@@ -726,20 +778,31 @@ class Server:
 
     def submit(self, user: int, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, out: torch.Tensor,
                opts: Optional[Opts] = None) -> int:
+        """Queue a frame into `out`.  The server's write is ordered after the
+        work queued on torch's current stream, and `out` is kept alive here
+        until poll or wait reports the request finished."""
         t = C.c_uint64()
         check(lib.mnr_server_submit(self.h, int(user), C.byref(pose.c), C.byref(cam), H, W, spp,
-                                    None if opts is None else C.byref(opts), _ptr(out), C.byref(t)), "server_submit")
+                                    None if opts is None else C.byref(opts), _ptr(out), _stream(), C.byref(t)),
+              "server_submit")
+        self._keep[("out", int(t.value))] = out
         return int(t.value)
 
     def poll(self, ticket: int):
         done = C.c_int32()
         ts = (C.c_int64 * 4)()
-        check(lib.mnr_server_poll(self.h, C.c_uint64(ticket), C.byref(done), ts), "server_poll")
+        st = lib.mnr_server_poll(self.h, C.c_uint64(ticket), C.byref(done), ts)
+        if done.value:
+            self._keep.pop(("out", ticket), None)
+        check(st, "server_poll")
         return bool(done.value), list(ts)
 
     def wait(self, ticket: int, timeout_ms: int = 60000):
         ts = (C.c_int64 * 4)()
-        check(lib.mnr_server_wait(self.h, C.c_uint64(ticket), int(timeout_ms), ts), "server_wait")
+        st = lib.mnr_server_wait(self.h, C.c_uint64(ticket), int(timeout_ms), ts)
+        if st != MNR_E_BUSY:
+            self._keep.pop(("out", ticket), None)
+        check(st, "server_wait")
         return list(ts)
 
     def stats(self) -> dict:

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmetanerf.so")
-SOURCES = ["render.hip", "render_bwd.hip", "serve.hip", "train_ops.hip", "probe.hip", "skel_cnn.hip", "api.cpp", "fk.cpp",
-           "server.cpp"]
+SOURCES = ["render.hip", "render_bwd.hip", "res_bwd.hip", "scatter.hip", "serve.hip", "train_ops.hip", "probe.hip", "skel_cnn.hip",
+           "api.cpp", "fk.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

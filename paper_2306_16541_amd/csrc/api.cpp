@@ -262,6 +262,132 @@ static mnr_status scratch_address(void** out) {
   return MNR_OK;
 }
 
+// ---- binned scatter of the hashed levels' table gradient (scatter.hip) ----
+
+static int hashed_levels(const mnr_field* f) {
+  int n = 0;
+  for (int l = 0; l < f->n_levels; ++l) n += level_is_dense(f, l) ? 0 : 1;
+  return n;
+}
+
+static uint64_t align256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// Carves the caller's scatter workspace; returns its size (0: the field has
+// no hashed level, or the batch or table is too large for the binned path).
+static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws, ScatterPlan* p) {
+  const int nh = hashed_levels(f);
+  if (nh == 0 || n_rays <= 0 || spp <= 0) return 0;
+  const uint64_t cap = (uint64_t)n_rays * spp * nh * 8;
+  if (cap >= ((uint64_t)1 << 31)) return 0;
+  const int64_t n_keys = (int64_t)nh << f->log2_T;
+  const int shift = scatter_bin_shift(n_keys);
+  if (shift > MAX_BIN_SHIFT) return 0;
+  const int n_bins = (int)((n_keys + ((int64_t)1 << shift) - 1) >> shift);
+  const int n_tiles = (int)((cap + BIN_TILE_RECORDS - 1) / BIN_TILE_RECORDS);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off += align256(bytes);
+    return ws ? ws + o : nullptr;
+  };
+  char* cursor = take(256);
+  char* keys = take(cap * 4);
+  char* vals = take(cap * 8);
+  char* skeys = take(cap * 4);
+  char* svals = take(cap * 8);
+  char* hist = take((uint64_t)n_bins * n_tiles * 4);
+  char* total = take((uint64_t)n_bins * 4);
+  char* base = take((uint64_t)n_bins * 4);
+  if (p) {
+    p->cursor = (uint32_t*)cursor;
+    p->keys = (uint32_t*)keys;
+    p->vals = (f2*)vals;
+    p->skeys = (uint32_t*)skeys;
+    p->svals = (f2*)svals;
+    p->hist = (uint32_t*)hist;
+    p->total = (uint32_t*)total;
+    p->base = (uint32_t*)base;
+    p->cap = (uint32_t)cap;
+    p->shift = shift;
+    p->n_bins = n_bins;
+    p->n_tiles_cap = n_tiles;
+    p->n_keys = n_keys;
+    int h = 0;
+    for (int l = 0; l < f->n_levels; ++l)
+      if (!level_is_dense(f, l)) p->levels.level[h++] = l;
+    p->levels.log2_T = f->log2_T;
+  }
+  return off;
+}
+
+// Per-sample scratch of the split adjoint (residual motion network): the
+// SPLIT_N arrays of n_rays * ceil(spp / 64) * 64 floats, then 64 floats of
+// layer-1 bias gradient.
+static uint64_t split_layout(const mnr_motion* m, int n_rays, int spp, char* ws, SplitArgs* sp) {
+  if (!m || !m->res_w[0] || n_rays <= 0 || spp <= 0) return 0;
+  const int64_t stride = (int64_t)n_rays * ((spp + 63) / 64) * 64;
+  const uint64_t arrays = align256((uint64_t)SPLIT_N * stride * 4);
+  if (sp) {
+    sp->buf = (float*)ws;
+    sp->stride = stride;
+    sp->dbias = (float*)(ws + arrays);
+  }
+  return arrays + 256;
+}
+
+// The adjoint workspace: the binned scatter's part (when the field has
+// hashed levels), then the split adjoint's (when the motion has a residual
+// network).
+static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
+                               ScatterPlan* p, SplitArgs* sp) {
+  const uint64_t a = scatter_layout(f, n_rays, spp, ws, p);
+  const uint64_t b = split_layout(m, n_rays, spp, ws ? ws + a : nullptr, sp);
+  return a + b;
+}
+
+// Validates a caller's adjoint workspace and points the adjoint at it.
+static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
+                                uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp) {
+  rec = RecordSink{nullptr, nullptr, nullptr, 0};
+  sp = SplitArgs{nullptr, 0, nullptr};
+  if (!ws) {
+    if (m->res_w[0]) return fail(MNR_E_INVALID, "the residual network's adjoint needs the adjoint workspace");
+    return MNR_OK;
+  }
+  if ((uintptr_t)ws & 255) return fail(MNR_E_INVALID, "adjoint workspace not 256-byte aligned");
+  ScatterPlan pp{};
+  SplitArgs ss{nullptr, 0, nullptr};
+  const uint64_t need = adjoint_layout(f, m, n_rays, spp, (char*)ws, &pp, &ss);
+  if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (no hashed level, no residual network, or a batch or table too large)");
+  if (ws_bytes < need)
+    return fail(MNR_E_SHAPE, "adjoint workspace has %llu bytes, needs %llu", (unsigned long long)ws_bytes,
+                (unsigned long long)need);
+  if (scatter_layout(f, n_rays, spp, nullptr, nullptr)) {
+    p = pp;
+    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap};
+  }
+  sp = ss;
+  return MNR_OK;
+}
+
+// The adjoint's launches: with the residual network, the split chain
+// (residual forward, field adjoint, residual and skinning adjoints), else
+// the fused kernel; the binned scatter after the field adjoint.
+static hipError_t adjoint_launches(const RenderArgs& a, const ScatterPlan& plan, int slots, const mnr_field* f,
+                                   float* grad_table, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  if (a.rec.keys) ok(launch_zero(plan.cursor, 256, st));
+  if (a.split.buf) {
+    ok(launch_zero(a.split.dbias, 64 * sizeof(float), st));
+    ok(launch_res_forward(a, slots, st));
+  }
+  ok(launch_render_bwd(a, slots, f->table_dtype, f->mlp_dtype, f->n_layers - 2, st));
+  if (a.rec.keys) ok(launch_binned_scatter(plan, grad_table, st));
+  if (a.split.buf) ok(launch_res_backward(a, slots, st));
+  return e;
+}
+
 static mnr_status render_impl(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
                               const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
                               const int32_t* pixel_ids, int32_t n_rays, float* out_rgba, float* t_chunks,
@@ -306,15 +432,24 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
                      ws, stream);
 }
 
+uint64_t mnr_adjoint_ws_bytes(const mnr_field* field, const mnr_motion* motion, int32_t n_rays, int32_t spp) {
+  if (!field || field->encoding != MNR_ENC_GRID || validate_field(field) != MNR_OK) return 0;
+  return adjoint_layout(field, motion, n_rays, spp, nullptr, nullptr, nullptr);
+}
 
 mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion, const mnr_pose* pose,
                                const mnr_camera* cam, int32_t H, int32_t W, int32_t spp, const mnr_opts* opts,
                                const int32_t* pixel_ids, int32_t n_rays, const float* t_chunks,
                                const float* grad_rgba, float* grad_table, float* const* grad_w, float* grad_weights,
-                               float* grad_bones, void* workspace, void* stream) {
+                               float* grad_bones, float* const* grad_res, void* workspace, void* adjoint_ws,
+                               uint64_t adjoint_ws_bytes, void* stream) {
   clear_error();
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, t_chunks)) return s;
-  if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the residual motion network");
+  if (motion->res_w[0]) {
+    if (!grad_res) return fail(MNR_E_INVALID, "backward: null grad_res with a residual network");
+    for (int k = 0; k < 6; ++k)
+      if (!grad_res[k]) return fail(MNR_E_INVALID, "backward: null grad_res[%d]", k);
+  }
   if (field->encoding == MNR_ENC_FREQ) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the frequency-encoded field");
   if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
   for (int k = 0; k < field->n_layers; ++k)
@@ -328,12 +463,17 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
   for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = grad_w[k];
   a.grad_weights = grad_weights;
   a.grad_G = grad_bones;
+  if (motion->res_w[0])
+    for (int k = 0; k < 6; ++k) a.grad_res[k] = grad_res[k];
+  ScatterPlan plan{};
+  if (mnr_status s = adjoint_setup(field, motion, n_rays, spp, adjoint_ws, adjoint_ws_bytes, a.rec, plan, a.split))
+    return s;
   a.queues = (int32_t*)workspace;
+  hipStream_t st = (hipStream_t)stream;
   if (workspace) {
-    if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, (hipStream_t)stream), "workspace")) return s;
+    if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, st), "workspace")) return s;
   }
-  return hip_status(launch_render_bwd(a, slot_count(H, W, pixel_ids, n_rays), field->table_dtype, field->mlp_dtype,
-                                      field->n_layers - 2, (hipStream_t)stream),
+  return hip_status(adjoint_launches(a, plan, slot_count(H, W, pixel_ids, n_rays), field, grad_table, st),
                     "backward launch");
 }
 
@@ -459,9 +599,12 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   clear_error();
   if (!st || !target) return fail(MNR_E_INVALID, "train_step: null state or target");
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, st->rgba)) return s;
-  if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the residual motion network");
   if (field->encoding == MNR_ENC_FREQ)
     return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the frequency-encoded field");
+  if (motion->res_w[0])
+    for (int k = 0; k < 6; ++k)
+      if (!st->res_master[k] || !st->res_grad[k] || !st->res_m[k] || !st->res_v[k])
+        return fail(MNR_E_INVALID, "train_step: null residual-network state buffer %d", k);
   if (!st->table_master || !st->table_grad || !st->table_m || !st->table_v || !st->weights_grad || !st->grad_rgba ||
       !st->loss || !st->t_chunks)
     return fail(MNR_E_INVALID, "train_step: null state buffer");
@@ -479,6 +622,11 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
       return fail(MNR_E_INVALID, "train_step: F32 weights must be the master copies themselves");
   if (st->step < 1) return fail(MNR_E_SHAPE, "train_step: step must be >= 1");
   if (n_rays == 0) return MNR_OK;
+  ScatterPlan plan{};
+  RecordSink rec{};
+  SplitArgs split{};
+  if (mnr_status r = adjoint_setup(field, motion, n_rays, spp, st->adjoint_ws, st->adjoint_ws_bytes, rec, plan, split))
+    return r;
   hipStream_t s = (hipStream_t)stream;
   const int64_t T = int64_t(1) << field->log2_T;
   const int64_t n_table = (int64_t)field->n_levels * T * field->n_feat;
@@ -490,6 +638,10 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   for (int k = 0; k < field->n_layers; ++k)
     ok(launch_zero(st->w_grad[k], (size_t)field->width[k] * field->width[k + 1] * 4, s));
   ok(launch_zero(st->weights_grad, n_wc * 4, s));
+  const int64_t n_omega = 3 * (int64_t)motion->n_bones;
+  const int64_t res_n[6] = {64 * 32, 64 * 64, 64 * 64, 64 * 96, 3 * 64, 64 * n_omega};  // W1..W5, W_omega
+  if (motion->res_w[0])
+    for (int k = 0; k < 6; ++k) ok(launch_zero(st->res_grad[k], res_n[k] * 4, s));
   RenderArgs a;
   pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
   const int slots = slot_count(H, W, pixel_ids, n_rays);
@@ -503,8 +655,16 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   a.grad_table = st->table_grad;
   for (int k = 0; k < field->n_layers; ++k) a.grad_w[k] = st->w_grad[k];
   a.grad_weights = st->weights_grad;
+  a.rec = rec;
+  a.split = split;
+  if (motion->res_w[0])
+    for (int k = 0; k < 6; ++k) a.grad_res[k] = st->res_grad[k];
   if (st->workspace) ok(launch_zero(st->workspace, MNR_WORKSPACE_BYTES, s));
-  ok(launch_render_bwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
+  ok(adjoint_launches(a, plan, slots, field, st->table_grad, s));
+  if (motion->res_w[0])  // Adam on the residual network's FP32 masters, then its BF16 copies
+    for (int k = 0; k < 6; ++k)
+      ok(launch_adam(st->res_master[k], st->res_grad[k], st->res_m[k], st->res_v[k], res_n[k], st->lr_res, st->beta1,
+                     st->beta2, st->eps, st->step, (void*)motion->res_w[k], MNR_BF16, s));
   ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
                  st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
                  field->table_dtype, s));

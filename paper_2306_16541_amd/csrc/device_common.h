@@ -78,6 +78,35 @@ struct ResArgs {
   int32_t n_omega;
 };
 
+// Where the adjoint writes the gradient records of the hashed grid levels
+// (keys == NULL: it adds them with global atomics instead).  Record i:
+// keys[i] = level * T + row, vals[i] = the two features' gradients.
+struct RecordSink {
+  uint32_t* cursor;  // records written so far (zero before the adjoint)
+  uint32_t* keys;
+  f2* vals;
+  uint32_t cap;      // capacity in records
+};
+
+// Per-sample scratch of the split adjoint (used with the residual motion
+// network): SoA arrays of `stride` floats, sample i of ray slot r at
+// r * (nchunks * 64) + i.  Written and read by the adjoint's kernels in
+// turn (the forward pass stores nothing per sample).
+enum SplitField {
+  SPLIT_X = 0,    // observed point x (3)
+  SPLIT_XS = 3,   // skinned point x_skel (3)
+  SPLIT_XF = 6,   // x_final = x_skel + x_res (3)
+  SPLIT_L = 9,    // weight sum L; 0 for samples that are not live
+  SPLIT_G = 10,   // dL/dx_final (3), then dL/dx_skel
+  SPLIT_GL = 13,  // dL/dL
+  SPLIT_N = 14
+};
+struct SplitArgs {
+  float* buf;      // [SPLIT_N][stride], or NULL (fused adjoint)
+  int64_t stride;
+  float* dbias;    // [64]: sum over samples of dL/d(pre-activation of the residual network's layer 1)
+};
+
 struct RenderArgs {
   FieldArgs f;
   MotionArgs m;
@@ -94,6 +123,9 @@ struct RenderArgs {
   float* grad_w[MNR_MAX_LAYERS];
   float* grad_weights;
   float* grad_G;                     // optional [n_bones][12]
+  RecordSink rec;                    // optional: hashed-level table gradient as records
+  SplitArgs split;                   // split adjoint (residual motion network)
+  float* grad_res[6];                // residual network: W1..W5, W_omega (FP32)
 };
 
 // Server tick work table (device memory, uploaded per tick).

@@ -668,12 +668,16 @@ __device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt
   return o[0];
 }
 
-template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false>
+// PRE: the caller has already set st.xs (the point the field is queried at)
+// and st.L (0 for samples that are not live); the warp is skipped.
+template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false, bool PRE = false>
 __device__ __forceinline__ uint64_t field_eval(const RenderArgs& a, bool valid, int lane, const char* wl, char* feat,
                                                f4* obuf, SampleState& st, f4& out) {
-  st.L = 0.f;
-  st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
-  if (valid) warp_sample(a.m, a.G, st.x, st.xs, st.L);
+  if constexpr (!PRE) {
+    st.L = 0.f;
+    st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
+    if (valid) warp_sample(a.m, a.G, st.x, st.xs, st.L);
+  }
   st.live = valid && st.L > 0.f;
   const uint64_t live_mask = __ballot(st.live);
   if (live_mask == 0) return 0;

@@ -42,9 +42,40 @@ hipError_t launch_render_fwd(const RenderArgs& a, int n_slots, mnr_dtype table_d
 hipError_t launch_render_bwd(const RenderArgs& a, int n_slots, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
                              hipStream_t st);
 
+// Split adjoint with the residual motion network (res_bwd.hip): the warp
+// and residual forward into the split scratch before the field's adjoint,
+// and after it the residual network's and the skinning adjoints.
+hipError_t launch_res_forward(const RenderArgs& a, int n_slots, hipStream_t st);
+hipError_t launch_res_backward(const RenderArgs& a, int n_slots, hipStream_t st);
+
 // Server tick: render the (slot, tile) items of wt with the requests' descriptors.
 hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
                         hipStream_t st);
+
+// Binned scatter-add of the adjoint's hashed-level records (scatter.hip).
+constexpr int MAX_BINS = 4096;
+constexpr int MAX_BIN_SHIFT = 14;       // a bin's LDS slice: 2^14 rows x 2 floats = 128 KiB
+constexpr int BIN_TILE_RECORDS = 8192;  // records per histogram / scatter block
+struct HashedLevels {  // the table level of each hashed level h (keys h * T + row)
+  int32_t level[MNR_MAX_LEVELS];
+  int32_t log2_T;
+};
+struct ScatterPlan {
+  uint32_t* cursor;          // records written by the adjoint
+  uint32_t* keys;            // [cap]
+  f2* vals;                  // [cap]
+  uint32_t* skeys;           // [cap] records in bin order
+  f2* svals;                 // [cap]
+  uint32_t* hist;            // [n_bins][n_tiles_cap]
+  uint32_t* total;           // [n_bins]
+  uint32_t* base;            // [n_bins]
+  uint32_t cap;
+  int shift, n_bins, n_tiles_cap;
+  int64_t n_keys;            // hashed levels * T
+  HashedLevels levels;
+};
+int scatter_bin_shift(int64_t n_keys);
+hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st);
 
 hipError_t launch_mse(const float* rgba, const float* target, int n, float* grad, float* loss, hipStream_t st);
 hipError_t launch_softmax_fwd(const float* logits, float* w, int C, int64_t V, hipStream_t st);

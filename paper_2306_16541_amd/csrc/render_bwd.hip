@@ -16,67 +16,16 @@
 //   3. encoding adjoint: scatter-add into the table gradient and the
 //      encoding's spatial derivative back to the skinned point x_skel;
 //      consecutive samples in the same cell are summed in the wave first;
+//      with a record sink the hashed levels write (row, gradient) records
+//      instead, summed afterwards without float atomics (scatter.hip);
 //   4. skinning adjoint (Eq. 7, 9): dx_skel/dw_i = (y_i - x_skel)/L and the
 //      likelihood term dalpha'/dL = alpha [L < 1], scattered through the
 //      trilinear weights into dL/dW^c; optionally dL/dG_i through the
 //      points y_i = G_i x and the weights' spatial gradient.
-#include "field_device.h"
+#include "adjoint_device.h"
 #include "kernels.h"
 
 namespace mnr {
-
-// Gradient scatter with fewer atomics.  The 64 lanes of a wave are 64
-// consecutive samples of one ray, so at coarse grid levels (and in the
-// blend-weight volume) neighbouring lanes often fall in the same cell and
-// would add to the same addresses.  Such runs are summed across the wave
-// first and only the first lane of a run issues the atomics.  Global float
-// atomics are executed at the memory side on this GPU (its eight L2s are
-// not coherent with each other), so their count bounds the adjoint.
-struct CellRuns {
-  int seg;    // run index of the lane (number of run starts at lanes <= lane)
-  int steps;  // suffix-scan steps needed to sum the longest run
-  bool head;  // first lane of its run
-};
-
-__device__ __forceinline__ CellRuns cell_runs(bool live, int x, int y, int z) {
-  const int lane = lane_id();
-  const int px = __shfl_up(x, 1, WAVE), py = __shfl_up(y, 1, WAVE), pz = __shfl_up(z, 1, WAVE);
-  const int plive = __shfl_up(live ? 1 : 0, 1, WAVE);
-  CellRuns r;
-  r.head = !live || lane == 0 || !plive || px != x || py != y || pz != z;
-  const uint64_t heads = __ballot(r.head);
-  r.seg = (int)__popcll(heads & (~0ull >> (63 - lane)));
-  // Longest run: a run of length >= 2^j + 1 needs 2^j non-start lanes in a
-  // row after its start; count the doublings (bits past lane 63 are starts).
-  uint64_t z0 = ~heads;
-  int steps = 0;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    if (z0 == 0) break;
-    ++steps;
-    z0 &= z0 >> (1 << j);
-  }
-  r.steps = steps;
-  return r;
-}
-
-// In-run suffix sums: afterwards the first lane of every run holds the sum
-// of the run's values (segmented Hillis-Steele scan over the wave).
-template <int NV>
-__device__ __forceinline__ void run_sums(const CellRuns& r, float (&v)[NV]) {
-  const int lane = lane_id();
-#pragma unroll 1
-  for (int j = 0; j < r.steps; ++j) {
-    const int d = 1 << j;
-    const int seg_d = __shfl_down(r.seg, d, WAVE);
-    const bool same = lane + d < WAVE && seg_d == r.seg;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const float o = __shfl_down(v[k], d, WAVE);
-      v[k] += same ? o : 0.f;
-    }
-  }
-}
 
 template <int P>
 struct BwdShape {
@@ -233,7 +182,11 @@ __device__ __forceinline__ int bwd_ray_slot(int blk, int nblk, int w, int it, in
   return slot < n_slots ? slot : -1;
 }
 
-template <typename TableT, int P, int NHH, int NW>
+// SPLIT (the residual motion network is on): the sample's query point
+// x_final and its weight sum come from the split scratch, written by
+// res_fwd_kernel, and instead of the skinning adjoint the kernel stores
+// dL/dx_final and dL/dL there for res_bwd_kernel and skin_bwd_kernel.
+template <typename TableT, int P, int NHH, int NW, bool SPLIT = false>
 __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a, int n_slots) {
   using S = MlpShape<P>;
   using B = BwdShape<P>;
@@ -290,12 +243,23 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       SampleState st;
       f4 out;
       const int i = ch * 64 + lane;
-      const float s = ((float)i + sample_jitter(a.r, orow, i)) * rs.delta;
-      st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
-      st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
-      st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
-      const uint64_t live_mask =
-          field_eval<TableT, P, NHH>(a, i < n_done, lane, wl, feat, (f4*)dfeat, st, out);
+      const int64_t sj = ((int64_t)orow * nchunks + ch) * 64 + lane;  // split scratch slot
+      uint64_t live_mask;
+      if constexpr (SPLIT) {
+        const float* sb = a.split.buf;
+        const int64_t ss = a.split.stride;
+        st.xs[0] = sb[SPLIT_XF * ss + sj];
+        st.xs[1] = sb[(SPLIT_XF + 1) * ss + sj];
+        st.xs[2] = sb[(SPLIT_XF + 2) * ss + sj];
+        st.L = i < n_done ? sb[SPLIT_L * ss + sj] : 0.f;
+        live_mask = field_eval<TableT, P, NHH, false, false, true>(a, i < n_done, lane, wl, feat, (f4*)dfeat, st, out);
+      } else {
+        const float s = ((float)i + sample_jitter(a.r, orow, i)) * rs.delta;
+        st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+        st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+        st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+        live_mask = field_eval<TableT, P, NHH>(a, i < n_done, lane, wl, feat, (f4*)dfeat, st, out);
+      }
       if (live_mask == 0) continue;  // alpha' = 0 everywhere: S passes through unchanged
 
       // ---- 1. compositing adjoint -------------------------------------------------
@@ -368,18 +332,34 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 #pragma unroll
       for (int q = 0; q < 3; ++q) u[q] = live ? u[q] : 0.f;
       const float* df = dfeat + lane * IN_FEAT;
+      // With a record sink, the hashed levels' gradient leaves as records
+      // (binned and summed after this kernel) instead of global atomics:
+      // one reservation per chunk, then for hashed level h and corner k the
+      // live lanes write records base + (8 h + k) n_live + rank.
+      uint32_t rec_base = 0, n_live = 0, rank = 0;
+      bool rec_ok = false;
+      if (a.rec.keys) {
+        const uint64_t lm = __ballot(live);
+        n_live = (uint32_t)__popcll(lm);
+        rank = (uint32_t)__popcll(lm & ((1ull << lane) - 1ull));
+        const uint32_t n_hashed = (uint32_t)__popc(~a.f.dense_mask & ((1u << a.f.n_levels) - 1u));
+        const uint32_t cnt = n_live * n_hashed * 8u;
+        uint32_t b = 0;
+        if (lane == 0 && cnt) b = atomicAdd(a.rec.cursor, cnt);
+        rec_base = __builtin_amdgcn_readfirstlane(b);
+        rec_ok = (uint64_t)rec_base + cnt <= (uint64_t)a.rec.cap;
+      }
+      // (a) spatial derivative of the encoding: table reads only.  (b) then
+      // the gradient scatter, which reads nothing: on this GPU one counter
+      // covers loads and stores, so stores issued between loads would hold
+      // up every later wait on a load.
+      if (live) {
 #pragma unroll 1
-      for (int l = 0; l < a.f.n_levels; ++l) {
-        const int N = a.f.level_res[l];
-        const bool dense = (a.f.dense_mask >> l) & 1u;
-        const GridCell gc = grid_cell(u, N);
-        const float d0 = live ? df[2 * l] : 0.f, d1 = live ? df[2 * l + 1] : 0.f;
-        float wk[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          wk[k] = ((k & 1) ? gc.f[0] : 1.f - gc.f[0]) * ((k & 2) ? gc.f[1] : 1.f - gc.f[1]) *
-                  ((k & 4) ? gc.f[2] : 1.f - gc.f[2]);
-        if (live) {  // spatial derivative of the encoding (reads only)
+        for (int l = 0; l < a.f.n_levels; ++l) {
+          const int N = a.f.level_res[l];
+          const bool dense = (a.f.dense_mask >> l) & 1u;
+          const GridCell gc = grid_cell(u, N);
+          const float d0 = df[2 * l], d1 = df[2 * l + 1];
           const __amdgpu_buffer_rsrc_t lrs = level_rsrc<TableT>(a.f, l);
           float gp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -395,6 +375,31 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           }
 #pragma unroll
           for (int q = 0; q < 3; ++q) g_u[q] = fmaf(gp[q], (float)N, g_u[q]);
+        }
+      }
+#pragma unroll 1
+      for (int l = 0; l < a.f.n_levels; ++l) {
+        const int N = a.f.level_res[l];
+        const bool dense = (a.f.dense_mask >> l) & 1u;
+        const GridCell gc = grid_cell(u, N);
+        const float d0 = live ? df[2 * l] : 0.f, d1 = live ? df[2 * l + 1] : 0.f;
+        float wk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          wk[k] = ((k & 1) ? gc.f[0] : 1.f - gc.f[0]) * ((k & 2) ? gc.f[1] : 1.f - gc.f[1]) *
+                  ((k & 4) ? gc.f[2] : 1.f - gc.f[2]);
+        if (a.rec.keys && !dense) {  // hashed level: records
+          if (live && rec_ok) {
+            const uint32_t h = (uint32_t)__popc(~a.f.dense_mask & ((1u << l) - 1u));
+            const uint32_t key0 = h << a.f.log2_T;  // keys number the hashed levels only
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint32_t idx = rec_base + (h * 8u + (uint32_t)k) * n_live + rank;
+              a.rec.keys[idx] = key0 + grid_row(gc, N, dense, tmask, k);
+              a.rec.vals[idx] = f2{wk[k] * d0, wk[k] * d1};
+            }
+          }
+          continue;
         }
         // Table gradient: one atomic per corner and feature per run of
         // consecutive samples in the same cell, carrying the run's sum.
@@ -421,60 +426,17 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       }
 
       // ---- 4. skinning adjoint ------------------------------------------------------
-      const bool above = st.L > EPS_L;
-      const float invL = 1.f / (above ? st.L : EPS_L);
-      const float gL = live ? g_L : 0.f;
-#pragma unroll 1
-      for (int b = 0; b < a.m.n_bones; ++b) {
-        float y[3];
-        bone_apply(a.G[b], st.x, y);
-        const float dx = above ? y[0] - st.xs[0] : y[0];
-        const float dy = above ? y[1] - st.xs[1] : y[1];
-        const float dz = above ? y[2] - st.xs[2] : y[2];
-        const float gw = live ? (g_xs[0] * dx + g_xs[1] * dy + g_xs[2] * dz) * invL + gL : 0.f;
-        const Tri t = bone_cell(a.m, y);
-        float v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          v[k] = gw * ((k & 1) ? t.f[0] : 1.f - t.f[0]) * ((k & 2) ? t.f[1] : 1.f - t.f[1]) *
-                 ((k & 4) ? t.f[2] : 1.f - t.f[2]);
-        if (a.grad_G) {  // uniform: dL/dG_b = dL/dy_b [x 1]^T, summed over the wave, then the block
-          // dL/dy_b = w_b / max(L, eps) dL/dx_skel + dL/dw_b grad_y w_b(y_b)
-          float c[8];
-          bone_corners(a.m, b, t, c);
-          const float w = trilerp(c, t.f);
-          const float fx = t.f[0], fy = t.f[1], fz = t.f[2];
-          const float x00 = c[0] + fx * (c[1] - c[0]), x10 = c[2] + fx * (c[3] - c[2]);
-          const float x01 = c[4] + fx * (c[5] - c[4]), x11 = c[6] + fx * (c[7] - c[6]);
-          const float y0 = x00 + fy * (x10 - x00), y1 = x01 + fy * (x11 - x01);
-          const float dqx = ((1.f - fy) * (1.f - fz)) * (c[1] - c[0]) + (fy * (1.f - fz)) * (c[3] - c[2]) +
-                            ((1.f - fy) * fz) * (c[5] - c[4]) + (fy * fz) * (c[7] - c[6]);
-          const float dqy = (1.f - fz) * (x10 - x00) + fz * (x11 - x01);
-          const float dqz = y1 - y0;
-          // (cells clamped to the volume's padding hold zeros: no weight, no gradient)
-          const float gy[3] = {w * invL * g_xs[0] + gw * dqx * a.m.mscale[0],
-                               w * invL * g_xs[1] + gw * dqy * a.m.mscale[1],
-                               w * invL * g_xs[2] + gw * dqz * a.m.mscale[2]};
-          const float xh[4] = {st.x[0], st.x[1], st.x[2], 1.f};
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const float s = wave_sum(live ? gy[r] * xh[k] : 0.f);
-              if (lane == 0) atomicAdd(dg + b * 12 + r * 4 + k, s);
-            }
+      if constexpr (SPLIT) {  // hand dL/dx_final and dL/dL to the residual network's adjoint
+        float* sb = a.split.buf;
+        const int64_t ss = a.split.stride;
+        if (i < n_done) {
+          sb[SPLIT_G * ss + sj] = g_xs[0];
+          sb[(SPLIT_G + 1) * ss + sj] = g_xs[1];
+          sb[(SPLIT_G + 2) * ss + sj] = g_xs[2];
+          sb[SPLIT_GL * ss + sj] = live ? g_L : 0.f;
         }
-        const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
-        run_sums<8>(cr, v);
-        if (live && cr.head) {
-          float* gplane = a.grad_weights + b * plane;
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int ix = t.i0[0] + (k & 1), iy = t.i0[1] + ((k >> 1) & 1), iz = t.i0[2] + (k >> 2);
-            if ((unsigned)ix < (unsigned)R && (unsigned)iy < (unsigned)R && (unsigned)iz < (unsigned)R)
-              unsafeAtomicAdd(gplane + ((size_t)iz * R + iy) * R + ix, v[k]);
-          }
-        }
+      } else {
+        skin_adjoint(a, st.x, st.xs, st.L, g_xs, g_L, live, dg);
       }
       wave_sync_lds();
     }
@@ -501,11 +463,11 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   }
 }
 
-template <typename TableT, int P, int NHH>
-static hipError_t launch_bwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+template <typename TableT, int P, int NHH, bool SPLIT>
+static hipError_t launch_bwd_s(const RenderArgs& a, int n_slots, hipStream_t st) {
   constexpr int NW = (P == MNR_F32) ? 1 : 4;
   const int lds = BwdShape<P>::lds_bytes(NHH, NW);
-  auto kern = render_bwd_kernel<TableT, P, NHH, NW>;
+  auto kern = render_bwd_kernel<TableT, P, NHH, NW, SPLIT>;
   static PersistentGrid pg;
   const int max_blocks = persistent_blocks(kern, 64 * NW, lds, pg);
   const int need = (n_slots + NW - 1) / NW;
@@ -513,6 +475,13 @@ static hipError_t launch_bwd_t(const RenderArgs& a, int n_slots, hipStream_t st)
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, st, a, n_slots);
   return hipGetLastError();
+}
+
+template <typename TableT, int P, int NHH>
+static hipError_t launch_bwd_t(const RenderArgs& a, int n_slots, hipStream_t st) {
+  if constexpr (P == MNR_BF16)  // the residual motion network (hence the split) is BF16 only
+    if (a.split.buf) return launch_bwd_s<TableT, P, NHH, true>(a, n_slots, st);
+  return launch_bwd_s<TableT, P, NHH, false>(a, n_slots, st);
 }
 
 template <int P, int NHH>

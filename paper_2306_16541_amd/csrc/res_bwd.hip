@@ -1,0 +1,430 @@
+// Adjoint of the residual non-rigid motion network (Sec. 4.3, Eq. 11-12),
+// as a split adjoint (training, Sec. 5.2).
+//
+// With the residual network the field is queried at x_final = x_skel +
+// MLP_res(gamma(x_skel), Omega), so the adjoint has to pass through a second
+// MLP between the field's adjoint and the skinning adjoint.  The fused
+// adjoint kernel has no LDS left for its weights, so the chain runs as four
+// kernels over the same ray chunks, handing per-sample values through a
+// scratch buffer (SplitArgs); the forward pass still saves nothing per
+// sample:
+//   res_fwd_kernel   x -> inverse LBS -> x_skel, L -> residual network ->
+//                    x_final (stored with x, x_skel, L);
+//   render_bwd_kernel<SPLIT>  the field's adjoint at x_final (compositing,
+//                    MLP, encoding), storing dL/dx_final and dL/dL;
+//   res_bwd_kernel   the residual network recomputed on MFMA and
+//                    differentiated: dL/dW1..W5 (block sums in LDS), the
+//                    sum of the first layer's pre-activation gradients (for
+//                    dL/dW_omega), and dL/dx_skel = dL/dx_final +
+//                    (d x_res / d x_skel)^T dL/dx_final;
+//   skin_bwd_kernel  the skinning adjoint with dL/dx_skel (dL/dW^c, dL/dG);
+//   omega_grad_kernel  dL/dW_omega = (sum of layer-1 gradients) Omega^T.
+#include "adjoint_device.h"
+#include "kernels.h"
+
+namespace mnr {
+
+constexpr int RES_FWD_WAVES = 8;
+constexpr int SKIN_WAVES = 8;
+
+// Ray slot r of a split-adjoint kernel: waves take slots in turn.
+__device__ __forceinline__ bool split_ray(const RenderArgs& a, int slot, int& orow, RaySetup& rs, int& n_done,
+                                          int nchunks) {
+  const int pix = ray_pixel(a.r, slot);
+  if (!a.r.pixel_ids && pix < 0) return false;
+  orow = a.r.pixel_ids ? slot : pix;
+  if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) return false;
+  n_done = (int)a.t_chunks[(size_t)orow * (nchunks + 1) + nchunks];
+  return true;
+}
+
+// ---- 1. forward of the warp and the residual network ------------------------
+
+__global__ void __launch_bounds__(64 * RES_FWD_WAVES) res_fwd_kernel(const RenderArgs a, int n_slots) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* rl = lds;
+  char* feat = lds + ResShape::bytes() + wave * MlpShape<MNR_BF16>::feat_bytes_per_wave();
+  stage_residual(rl, a.res);
+  __syncthreads();
+  const int nchunks = (a.r.spp + 63) >> 6;
+  float* sb = a.split.buf;
+  const int64_t ss = a.split.stride;
+  for (int slot = blockIdx.x * RES_FWD_WAVES + wave; slot < n_slots; slot += gridDim.x * RES_FWD_WAVES) {
+    int orow, n_done;
+    RaySetup rs;
+    if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    for (int ch = 0; ch < nchunks && ch * 64 < n_done; ++ch) {
+      if (tc[ch] < 0.f) continue;
+      const int i = ch * 64 + lane;
+      const bool valid = i < n_done;
+      const int64_t sj = ((int64_t)orow * nchunks + ch) * 64 + lane;
+      SampleState st;
+      const float s = ((float)i + sample_jitter(a.r, orow, i)) * rs.delta;
+      st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+      st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+      st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+      st.L = 0.f;
+      st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
+      if (valid) warp_sample(a.m, a.G, st.x, st.xs, st.L);
+      st.live = valid && st.L > 0.f;
+      const float xs0 = st.xs[0], xs1 = st.xs[1], xs2 = st.xs[2];
+      const uint64_t live_mask = __ballot(st.live);
+      if (live_mask) residual_step(a.res, rl, feat, (f4*)feat, st, live_mask, lane);
+      if (valid) {
+        sb[SPLIT_X * ss + sj] = st.x[0];
+        sb[(SPLIT_X + 1) * ss + sj] = st.x[1];
+        sb[(SPLIT_X + 2) * ss + sj] = st.x[2];
+        sb[SPLIT_XS * ss + sj] = xs0;
+        sb[(SPLIT_XS + 1) * ss + sj] = xs1;
+        sb[(SPLIT_XS + 2) * ss + sj] = xs2;
+        sb[SPLIT_XF * ss + sj] = st.xs[0];
+        sb[(SPLIT_XF + 1) * ss + sj] = st.xs[1];
+        sb[(SPLIT_XF + 2) * ss + sj] = st.xs[2];
+        sb[SPLIT_L * ss + sj] = st.live ? st.L : 0.f;
+      }
+      wave_sync_lds();
+    }
+  }
+}
+
+// ---- 2. the residual network's adjoint ---------------------------------------
+
+// Transposed weights W_k^T as A operands (BF16 fragment layout), for
+// dX = W^T dY: W1^T (32 x 64), W2^T, W3^T (64 x 64), W4^T (96 x 64), W5^T
+// (64 x 3, padded to 32 columns).
+struct ResTShape {
+  static constexpr int FRAG = 64 * 16;
+  static constexpr int T1 = 2 * 2 * FRAG, T2 = 4 * 2 * FRAG, T3 = 4 * 2 * FRAG, T4 = 6 * 2 * FRAG, T5 = 4 * 1 * FRAG;
+  static constexpr int o2 = T1, o3 = o2 + T2, o4 = o3 + T3, o5 = o4 + T4;
+  static constexpr int bytes() { return o5 + T5; }
+};
+
+// Block sums of the weight gradients (FP32): W1 [64][32] (column 27, an
+// input that gamma never uses, carries the bias gradient: see below), W2,
+// W3 [64][64], W4 [64][96], W5 [3][64].
+struct ResGrad {
+  static constexpr int n1 = 64 * 32, n2 = 64 * 64, n3 = 64 * 64, n4 = 64 * 96, n5 = 3 * 64;
+  static constexpr int o2 = n1, o3 = o2 + n2, o4 = o3 + n3, o5 = o4 + n4;
+  static constexpr int floats() { return o5 + n5; }
+};
+constexpr int BIAS_COL = 27;  // gamma has 27 values; inputs 27..31 are zero padding
+
+template <typename WT>
+__device__ void stage_t(char* lds, const WT* __restrict__ w, int M, int K, int Kpad) {
+  for (int e = threadIdx.x; e < K * Kpad; e += blockDim.x) {
+    const int m = e / Kpad, k = e - m * Kpad;  // element (m, k) of W^T = W[k][m]
+    const float v = (k < M) ? (float)w[(size_t)k * K + m] : 0.0f;
+    *(__bf16*)(lds + frag_offset<MNR_BF16>(m, k, Kpad / 32)) = (__bf16)v;
+  }
+}
+
+__device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
+  return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
+}
+
+// dW[M_out x K_in] (row stride K_in) += d (MT tiles) x h^T (NT tiles) over
+// the 16 samples of one tile, through the wave's transpose buffer tb
+// (2 x 64 x 16 bf16) and LDS float atomics.
+template <int MT, int NT>
+__device__ __forceinline__ void res_dw(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int K_in,
+                                       int lane) {
+  __bf16* td = tb;            // [64 rows][16 samples]
+  __bf16* th = tb + 64 * 16;  // [64 columns][16 samples]
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) td[(16 * t + 4 * g + j) * 16 + c] = (__bf16)d[t][j];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
+  wave_sync_lds();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+      bf16x8 av, bv;
+      if (g < 2) {
+        av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
+        bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
+      }
+      const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * mt + 4 * g + j;
+        if (row < M_out) atomicAdd(dw + row * K_in + 16 * kt + c, acc[j]);
+      }
+    }
+  }
+  wave_sync_lds();
+}
+
+// out[mt] = W^T-fragments (MT m-tiles, KS 32-wide k steps) x x (2 KS tiles).
+template <int MT, int KS>
+__device__ __forceinline__ void res_mm(const char* wl, const f4* x, f4* out, int lane) {
+  const bf16x8* W = (const bf16x8*)wl;
+  bf16x8 b[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+    out[mt] = acc;
+  }
+}
+
+constexpr int RES_BWD_LDS = ResShape::bytes() + ResTShape::bytes() + ResGrad::floats() * 4 +
+                            MlpShape<MNR_BF16>::feat_bytes_per_wave() + 2 * 64 * 16 * 2 + 64 * 32 * 4;
+static_assert(RES_BWD_LDS <= 160 * 1024, "LDS of the residual adjoint");
+
+// One wave per block (the weights, their transposes and the gradient sums
+// fill the LDS).  Per 64-sample chunk: gamma(x_skel) into the feature
+// buffer; per 16-sample tile the forward pass again (activations kept in
+// registers), then the backward pass layer by layer; dL/dgamma to LDS and
+// from there, per lane, through gamma's derivative to dL/dx_skel.
+__global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_slots) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int lane = threadIdx.x;
+  char* rl = lds;
+  char* rt = rl + ResShape::bytes();
+  float* dw = (float*)(rt + ResTShape::bytes());
+  char* feat = (char*)(dw + ResGrad::floats());
+  __bf16* tb = (__bf16*)(feat + MlpShape<MNR_BF16>::feat_bytes_per_wave());
+  float* dgam = (float*)(tb + 2 * 64 * 16);  // [64 samples][32]
+  stage_residual(rl, a.res);
+  stage_t(rt, a.res.w[0], HIDDEN, 32, HIDDEN);
+  stage_t(rt + ResTShape::o2, a.res.w[1], HIDDEN, HIDDEN, HIDDEN);
+  stage_t(rt + ResTShape::o3, a.res.w[2], HIDDEN, HIDDEN, HIDDEN);
+  stage_t(rt + ResTShape::o4, a.res.w[3], HIDDEN, HIDDEN + 32, HIDDEN);
+  stage_t(rt + ResTShape::o5, a.res.w[4], 3, HIDDEN, 32);
+  for (int i = lane; i < ResGrad::floats(); i += 64) dw[i] = 0.f;
+  __syncthreads();
+  const float* bias = (const float*)(rl + ResShape::obias);
+  const int nchunks = (a.r.spp + 63) >> 6;
+  float* sb = a.split.buf;
+  const int64_t ss = a.split.stride;
+  const int c = lane & 15, g = lane >> 4;
+  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+    int orow, n_done;
+    RaySetup rs;
+    if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    for (int ch = 0; ch < nchunks && ch * 64 < n_done; ++ch) {
+      if (tc[ch] < 0.f) continue;
+      const int i = ch * 64 + lane;
+      const int64_t sj = ((int64_t)orow * nchunks + ch) * 64 + lane;
+      const bool live = i < n_done && sb[SPLIT_L * ss + sj] > 0.f;
+      const uint64_t live_mask = __ballot(live);
+      if (live_mask == 0) continue;
+      float xs[3] = {0.f, 0.f, 0.f}, gf[3] = {0.f, 0.f, 0.f};
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          xs[q] = sb[(SPLIT_XS + q) * ss + sj];
+          gf[q] = sb[(SPLIT_G + q) * ss + sj];
+        }
+      }
+      // gamma(x_skel), as the forward pass builds it
+      float gm[32], sn[4][3], cs[4][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) gm[q] = xs[q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          sincospif((float)(1 << k) * xs[q], &sn[k][q], &cs[k][q]);
+          gm[3 + 6 * k + q] = a.res.win[k] * sn[k][q];
+          gm[6 + 6 * k + q] = a.res.win[k] * cs[k][q];
+        }
+#pragma unroll
+      for (int q = 27; q < 32; ++q) gm[q] = 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        store_feat2<MNR_BF16>(feat, lane, 2 * q, live ? f2{gm[2 * q], gm[2 * q + 1]} : f2{0.f, 0.f});
+      wave_sync_lds();
+#pragma unroll 1
+      for (int nt = 0; nt < 4; ++nt) {
+        f4 dg2[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        if ((live_mask >> (16 * nt)) & 0xFFFFull) {
+          // forward, as residual_step
+          f4 x[4], h1[4], h2[4], h3[4], h4[4], tmp[6];
+          load_input<MNR_BF16>(feat, nt, lane, x);
+          mma_layer<MNR_BF16, 4, 2>(rl, x, h1, lane, bias);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) h1[mt] = relu4(h1[mt]);
+          mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o2, h1, h2, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+          mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o3, h2, h3, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) h3[mt] = relu4(h3[mt]);
+          const f4 cat[6] = {h3[0], h3[1], h3[2], h3[3], x[0], x[1]};
+          mma_layer<MNR_BF16, 4, 6>(rl + ResShape::o4, cat, h4, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) h4[mt] = relu4(h4[mt]);
+          // output gradient: rows 0..2 of sample 16 nt + c are dL/dx_res = dL/dx_final
+          const float q0 = __shfl(gf[0], 16 * nt + c, WAVE), q1 = __shfl(gf[1], 16 * nt + c, WAVE),
+                      q2 = __shfl(gf[2], 16 * nt + c, WAVE);
+          f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : f4{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+          res_dw<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, 64, lane);
+          f4 d[4];
+          res_mm<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
+          // layer 4: input [h3; gamma]
+          res_dw<4, 4>(tb, d, h3, dw + ResGrad::o4, 64, 96, lane);
+          res_dw<4, 2>(tb, d, x, dw + ResGrad::o4 + 64, 64, 96, lane);
+          res_mm<6, 2>(rt + ResTShape::o4, d, tmp, lane);
+          dg2[0] = tmp[4];
+          dg2[1] = tmp[5];
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
+          // layer 3
+          res_dw<4, 4>(tb, d, h2, dw + ResGrad::o3, 64, 64, lane);
+          res_mm<4, 2>(rt + ResTShape::o3, d, tmp, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
+          // layer 2
+          res_dw<4, 4>(tb, d, h1, dw + ResGrad::o2, 64, 64, lane);
+          res_mm<4, 2>(rt + ResTShape::o2, d, tmp, lane);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
+          // layer 1: the pose term enters as a bias, so the bias gradient is
+          // the sum of d over the samples: gamma's unused input 27 is set to
+          // 1 here (it is 0 in the forward pass) and its column of dW1
+          // collects exactly that sum
+          f4 xb[2] = {x[0], x[1]};
+          if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
+          res_dw<4, 2>(tb, d, xb, dw, 64, 32, lane);
+          res_mm<2, 2>(rt, d, tmp, lane);
+          dg2[0] += tmp[0];
+          dg2[1] += tmp[1];
+        }
+        // dL/dgamma of the tile's samples: lane c + 16 g holds inputs 16 t + 4 g + e of sample c
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dgam[(16 * nt + c) * 32 + 16 * t + 4 * g + e] = dg2[t][e];
+      }
+      wave_sync_lds();
+      if (live) {  // dL/dx_skel = dL/dx_final + (d gamma / d x_skel)^T dL/dgamma
+        const float* dgm = dgam + lane * 32;
+        float gs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          float acc = gf[q] + dgm[q];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float f = a.res.win[k] * (float)(1 << k) * 3.14159265358979f;
+            acc = fmaf(f * cs[k][q], dgm[3 + 6 * k + q], acc);
+            acc = fmaf(-f * sn[k][q], dgm[6 + 6 * k + q], acc);
+          }
+          gs[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sb[(SPLIT_G + q) * ss + sj] = gs[q];
+      }
+      wave_sync_lds();
+    }
+  }
+  __syncthreads();
+  // flush the block's sums; column 27 of dW1 is the bias gradient
+  for (int i = lane; i < ResGrad::floats(); i += 64) {
+    const float v = dw[i];
+    if (v == 0.f) continue;
+    if (i < ResGrad::o2) {
+      if ((i & 31) == BIAS_COL) unsafeAtomicAdd(a.split.dbias + (i >> 5), v);
+      else unsafeAtomicAdd(a.grad_res[0] + i, v);
+    } else if (i < ResGrad::o3) {
+      unsafeAtomicAdd(a.grad_res[1] + (i - ResGrad::o2), v);
+    } else if (i < ResGrad::o4) {
+      unsafeAtomicAdd(a.grad_res[2] + (i - ResGrad::o3), v);
+    } else if (i < ResGrad::o5) {
+      unsafeAtomicAdd(a.grad_res[3] + (i - ResGrad::o4), v);
+    } else {
+      unsafeAtomicAdd(a.grad_res[4] + (i - ResGrad::o5), v);
+    }
+  }
+}
+
+// ---- 3. the skinning adjoint with dL/dx_skel ----------------------------------
+
+__global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderArgs a, int n_slots) {
+  __shared__ float dg[MNR_MAX_BONES * 12];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < MNR_MAX_BONES * 12; i += blockDim.x) dg[i] = 0.f;
+  __syncthreads();
+  const int nchunks = (a.r.spp + 63) >> 6;
+  const float* sb = a.split.buf;
+  const int64_t ss = a.split.stride;
+  for (int slot = blockIdx.x * SKIN_WAVES + wave; slot < n_slots; slot += gridDim.x * SKIN_WAVES) {
+    int orow, n_done;
+    RaySetup rs;
+    if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    for (int ch = 0; ch < nchunks && ch * 64 < n_done; ++ch) {
+      if (tc[ch] < 0.f) continue;
+      const int i = ch * 64 + lane;
+      const int64_t sj = ((int64_t)orow * nchunks + ch) * 64 + lane;
+      const float L = i < n_done ? sb[SPLIT_L * ss + sj] : 0.f;
+      const bool live = L > 0.f;
+      if (__ballot(live) == 0) continue;
+      float x[3] = {0.f, 0.f, 0.f}, xs[3] = {0.f, 0.f, 0.f}, gs[3] = {0.f, 0.f, 0.f}, gL = 0.f;
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          x[q] = sb[(SPLIT_X + q) * ss + sj];
+          xs[q] = sb[(SPLIT_XS + q) * ss + sj];
+          gs[q] = sb[(SPLIT_G + q) * ss + sj];
+        }
+        gL = sb[SPLIT_GL * ss + sj];
+      }
+      skin_adjoint(a, x, xs, L, gs, gL, live, dg);
+    }
+  }
+  __syncthreads();
+  if (a.grad_G)
+    for (int i = threadIdx.x; i < a.m.n_bones * 12; i += blockDim.x)
+      if (dg[i] != 0.f) unsafeAtomicAdd(a.grad_G + i, dg[i]);
+}
+
+// dL/dW_omega[i][j] += dbias[i] Omega[j].
+__global__ void omega_grad_kernel(const RenderArgs a) {
+  const int n = a.res.n_omega;
+  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < HIDDEN * n; e += blockDim.x * gridDim.x)
+    a.grad_res[5][e] += a.split.dbias[e / n] * a.res.omega[e % n];
+}
+
+hipError_t launch_res_forward(const RenderArgs& a, int n_slots, hipStream_t st) {
+  const int lds = ResShape::bytes() + RES_FWD_WAVES * MlpShape<MNR_BF16>::feat_bytes_per_wave();
+  static PersistentGrid pg;
+  const int mb = persistent_blocks(res_fwd_kernel, 64 * RES_FWD_WAVES, lds, pg);
+  const int need = (n_slots + RES_FWD_WAVES - 1) / RES_FWD_WAVES;
+  hipLaunchKernelGGL(res_fwd_kernel, dim3(need < mb ? (need > 0 ? need : 1) : mb), dim3(64 * RES_FWD_WAVES), lds, st,
+                     a, n_slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_res_backward(const RenderArgs& a, int n_slots, hipStream_t st) {
+  static PersistentGrid pg;
+  const int mb = persistent_blocks(res_bwd_kernel, 64, RES_BWD_LDS, pg);
+  hipLaunchKernelGGL(res_bwd_kernel, dim3(n_slots < mb ? (n_slots > 0 ? n_slots : 1) : mb), dim3(64), RES_BWD_LDS,
+                     st, a, n_slots);
+  static PersistentGrid pg2;
+  const int mb2 = persistent_blocks(skin_bwd_kernel, 64 * SKIN_WAVES, 0, pg2);
+  const int need = (n_slots + SKIN_WAVES - 1) / SKIN_WAVES;
+  hipLaunchKernelGGL(skin_bwd_kernel, dim3(need < mb2 ? (need > 0 ? need : 1) : mb2), dim3(64 * SKIN_WAVES), 0, st, a,
+                     n_slots);
+  hipLaunchKernelGGL(omega_grad_kernel, dim3(16), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace mnr

@@ -1,0 +1,284 @@
+// Binned scatter-add of the grid-table gradient (training, Sec. 5.2).
+//
+// The adjoint's gradient with respect to the hashed grid levels is a
+// scatter-add: every evaluated sample adds to 8 rows of each hashed level,
+// and the rows are spread over the whole table by the spatial hash, so
+// consecutive samples of a ray almost never share one.  Done with global
+// float atomics, which this GPU executes at the memory side at ~20 G/s, the
+// scatter costs more than the rest of the adjoint.  Instead the adjoint
+// writes one record (key, two feature gradients) per sample, hashed level
+// and corner, and the records are summed here without global float
+// atomics:
+//   1. bin_histogram: per tile of records, a histogram of the key bins
+//      (a bin = 2^shift consecutive keys, up to a 128 KiB slice of the table
+//      gradient), written bin-major to H[bin][tile];
+//   2. bin_totals / bin_offsets: exclusive scan of H in (bin, tile) order,
+//      giving every (bin, tile) pair its place in bin order;
+//   3. bin_scatter: each tile sorts its records by bin in LDS and writes
+//      them to their places, bin run by bin run;
+//   4. bin_accumulate: one block per bin sums its records into an LDS copy
+//      of the bin's slice with LDS atomics, then adds the slice to the
+//      table gradient (each slice has one owner: plain read-add-write).
+// Keys count hashed levels only: key = h * T + row for the h-th hashed
+// level, so no bin is spent on the dense levels (which keep atomics).
+// Traffic is a few passes over the records (12 bytes each) instead of two
+// memory-side atomics per record.
+#include "kernels.h"
+
+namespace mnr {
+
+constexpr int BIN_THREADS = 512;
+constexpr int BIN_TILE = BIN_TILE_RECORDS;  // records per tile
+constexpr int BIN_PER_THREAD = BIN_TILE / BIN_THREADS;
+constexpr int SCAN_THREADS = 256;           // the per-bin scans
+constexpr int ACC_THREADS = 1024;           // the per-bin sums
+
+int scatter_bin_shift(int64_t n_keys) {
+  // slices of 2^13 keys (64 KiB of gradient in LDS: two summing blocks per
+  // CU), larger only when that would make more than MAX_BINS of them
+  int shift = 13;
+  while ((n_keys + ((int64_t)1 << shift) - 1) >> shift > MAX_BINS) ++shift;
+  return shift;
+}
+
+// Records written: the adjoint reserves space with the cursor and writes
+// nothing past the capacity, so the count is clamped to it.
+__device__ __forceinline__ uint32_t record_count(const uint32_t* cursor, uint32_t cap) {
+  const uint32_t c = *cursor;
+  return c < cap ? c : cap;
+}
+
+__global__ void __launch_bounds__(BIN_THREADS) bin_histogram_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                    const uint32_t* __restrict__ keys, int shift,
+                                                                    int n_bins, int n_tiles_cap,
+                                                                    uint32_t* __restrict__ H) {
+  __shared__ uint32_t hist[MAX_BINS];
+  const uint32_t count = record_count(cursor, cap);
+  const int tile = blockIdx.x;
+  if ((int64_t)tile * BIN_TILE >= count) return;
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) hist[b] = 0;
+  __syncthreads();
+  const uint32_t t0 = (uint32_t)tile * BIN_TILE;
+  uint32_t k[BIN_PER_THREAD];
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const uint32_t i = t0 + j * BIN_THREADS + threadIdx.x;
+    k[j] = i < count ? keys[i] >> shift : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j)
+    if (k[j] < (uint32_t)n_bins) atomicAdd(&hist[k[j]], 1u);  // keys are < n_keys by construction
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) H[(size_t)b * n_tiles_cap + tile] = hist[b];
+}
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
+#pragma unroll
+  for (int k = WAVE / 2; k > 0; k >>= 1) v += __shfl_xor(v, k, WAVE);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t s = 0;
+  for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// total[b] = number of records in bin b.
+__global__ void __launch_bounds__(SCAN_THREADS) bin_totals_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                 const uint32_t* __restrict__ H, int n_tiles_cap,
+                                                                 uint32_t* __restrict__ total) {
+  __shared__ uint32_t red[SCAN_THREADS / WAVE];
+  const int n_tiles = (int)((record_count(cursor, cap) + BIN_TILE - 1) / BIN_TILE);
+  const uint32_t* row = H + (size_t)blockIdx.x * n_tiles_cap;
+  uint32_t s = 0;
+  for (int t = threadIdx.x; t < n_tiles; t += SCAN_THREADS) s += row[t];
+  s = block_sum_u32(s, red);
+  if (threadIdx.x == 0) total[blockIdx.x] = s;
+}
+
+// base[b] = records in bins before b; H[b][t] becomes the place of tile t's
+// first record of bin b (exclusive scan in (bin, tile) order).
+__global__ void __launch_bounds__(SCAN_THREADS) bin_offsets_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                  uint32_t* __restrict__ H, int n_tiles_cap,
+                                                                  const uint32_t* __restrict__ total,
+                                                                  uint32_t* __restrict__ base) {
+  __shared__ uint32_t red[SCAN_THREADS / WAVE];
+  __shared__ uint32_t scan[SCAN_THREADS];
+  const int b = blockIdx.x;
+  const int n_tiles = (int)((record_count(cursor, cap) + BIN_TILE - 1) / BIN_TILE);
+  uint32_t s = 0;
+  for (int k = threadIdx.x; k < b; k += SCAN_THREADS) s += total[k];
+  uint32_t carry = block_sum_u32(s, red);
+  if (threadIdx.x == 0) base[b] = carry;
+  uint32_t* row = H + (size_t)b * n_tiles_cap;
+  for (int t0 = 0; t0 < n_tiles; t0 += SCAN_THREADS) {
+    const int t = t0 + threadIdx.x;
+    const uint32_t v = t < n_tiles ? row[t] : 0u;
+    scan[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_THREADS; d <<= 1) {  // inclusive Hillis-Steele scan
+      const uint32_t o = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0u;
+      __syncthreads();
+      scan[threadIdx.x] += o;
+      __syncthreads();
+    }
+    if (t < n_tiles) row[t] = carry + scan[threadIdx.x] - v;
+    const uint32_t chunk = scan[SCAN_THREADS - 1];
+    __syncthreads();
+    carry += chunk;
+  }
+}
+
+// Each tile's records are first sorted by bin in LDS (a counting sort), then
+// written out bin run by bin run, so that consecutive lanes write
+// consecutive places (about BIN_TILE / n_bins records per run).
+constexpr int SCATTER_LDS = MAX_BINS * 4 * 2 + BIN_TILE * (4 + 8);
+
+__global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                  const uint32_t* __restrict__ keys,
+                                                                  const f2* __restrict__ vals, int shift, int n_bins,
+                                                                  int n_tiles_cap, const uint32_t* __restrict__ H,
+                                                                  uint32_t* __restrict__ skeys,
+                                                                  f2* __restrict__ svals) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  uint32_t* start = (uint32_t*)lds;            // [n_bins] first local place of each bin
+  uint32_t* cur = start + MAX_BINS;            // [n_bins] counts, then global places
+  uint32_t* lkeys = cur + MAX_BINS;            // [BIN_TILE] records in bin order
+  f2* lvals = (f2*)(lkeys + BIN_TILE);
+  __shared__ uint32_t red[BIN_THREADS / WAVE];
+  const uint32_t count = record_count(cursor, cap);
+  const int tile = blockIdx.x;
+  if ((int64_t)tile * BIN_TILE >= count) return;
+  const uint32_t t0 = (uint32_t)tile * BIN_TILE;
+  const int n_here = (int)min((uint32_t)BIN_TILE, count - t0);
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) cur[b] = 0;
+  __syncthreads();
+  uint32_t k[BIN_PER_THREAD], rank[BIN_PER_THREAD];
+  f2 v[BIN_PER_THREAD];
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const int i = j * BIN_THREADS + threadIdx.x;
+    k[j] = i < n_here ? keys[t0 + i] : 0xFFFFFFFFu;
+    v[j] = i < n_here ? vals[t0 + i] : f2{0.f, 0.f};
+  }
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const uint32_t b = k[j] >> shift;
+    rank[j] = b < (uint32_t)n_bins ? atomicAdd(&cur[b], 1u) : 0u;
+  }
+  __syncthreads();
+  // exclusive scan of the counts: start[b]
+  const int per = (n_bins + BIN_THREADS - 1) / BIN_THREADS;
+  const int b0 = threadIdx.x * per;
+  uint32_t local = 0;
+  for (int b = b0; b < b0 + per && b < n_bins; ++b) local += cur[b];
+  uint32_t incl = local;  // inclusive scan of the per-thread sums across the block
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, WAVE);
+    if ((int)(threadIdx.x & 63) >= d) incl += o;
+  }
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  uint32_t wave_base = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wave_base += red[w];
+  uint32_t run = wave_base + incl - local;
+  for (int b = b0; b < b0 + per && b < n_bins; ++b) {
+    start[b] = run;
+    run += cur[b];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const uint32_t b = k[j] >> shift;
+    if (b < (uint32_t)n_bins) {
+      const uint32_t p = start[b] + rank[j];
+      lkeys[p] = k[j];
+      lvals[p] = v[j];
+    }
+  }
+  __shared__ uint32_t n_sorted;
+  if (threadIdx.x == 0) n_sorted = start[n_bins - 1] + cur[n_bins - 1];
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) cur[b] = H[(size_t)b * n_tiles_cap + tile];
+  __syncthreads();
+  for (int p = threadIdx.x; p < (int)n_sorted; p += BIN_THREADS) {
+    const uint32_t kk = lkeys[p];
+    const uint32_t b = kk >> shift;
+    if (b < (uint32_t)n_bins) {
+      const uint32_t g = cur[b] + ((uint32_t)p - start[b]);
+      skeys[g] = kk;
+      svals[g] = lvals[p];
+    }
+  }
+}
+
+// One block per bin: LDS copy of the bin's gradient slice.  Key
+// h * T + row is row `row` of hashed level h, i.e. of table level
+// levels.level[h].
+__global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint32_t* __restrict__ skeys,
+                                                                     const f2* __restrict__ svals, int shift,
+                                                                     int64_t n_keys, const uint32_t* __restrict__ total,
+                                                                     const uint32_t* __restrict__ base,
+                                                                     const HashedLevels levels,
+                                                                     float* __restrict__ grad) {
+  extern __shared__ float acc[];  // [2^shift][2]
+  const int b = blockIdx.x;
+  const uint32_t n = total[b];
+  if (n == 0) return;
+  const int rows = 1 << shift;
+  for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0.f;
+  __syncthreads();
+  const uint32_t s0 = base[b], mask = (uint32_t)rows - 1u;
+  constexpr int U = 4;  // records in flight per thread
+  for (uint32_t i0 = 0; i0 < n; i0 += U * ACC_THREADS) {
+    uint32_t r[U];
+    f2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = i0 + u * ACC_THREADS + threadIdx.x;
+      r[u] = i < n ? skeys[s0 + i] & mask : 0xFFFFFFFFu;
+      v[u] = i < n ? svals[s0 + i] : f2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (r[u] != 0xFFFFFFFFu) {
+        atomicAdd(&acc[2 * r[u]], v[u][0]);
+        atomicAdd(&acc[2 * r[u] + 1], v[u][1]);
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t k0 = (int64_t)b << shift;
+  const uint32_t tmask = (1u << levels.log2_T) - 1u;
+  for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
+    const f2 v = f2{acc[2 * r], acc[2 * r + 1]};
+    const int64_t key = k0 + r;
+    if ((v[0] != 0.f || v[1] != 0.f) && key < n_keys) {
+      const int h = (int)(key >> levels.log2_T);
+      const int64_t row = (int64_t)levels.level[h] * ((int64_t)tmask + 1) + (key & tmask);
+      f2* g = (f2*)grad + row;
+      *g = *g + v;
+    }
+  }
+}
+
+hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st) {
+  const int lds = (2 << p.shift) * (int)sizeof(float);
+  static PersistentGrid once_acc, once_sc;  // raise the LDS limits once (to the largest slice)
+  persistent_blocks(bin_accumulate_kernel, ACC_THREADS, (2 << MAX_BIN_SHIFT) * (int)sizeof(float), once_acc);
+  persistent_blocks(bin_scatter_kernel, BIN_THREADS, SCATTER_LDS, once_sc);
+  hipLaunchKernelGGL(bin_histogram_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), 0, st, p.cursor, p.cap, p.keys,
+                     p.shift, p.n_bins, p.n_tiles_cap, p.hist);
+  hipLaunchKernelGGL(bin_totals_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
+                     p.n_tiles_cap, p.total);
+  hipLaunchKernelGGL(bin_offsets_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
+                     p.n_tiles_cap, p.total, p.base);
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
+                     p.keys, p.vals, p.shift, p.n_bins, p.n_tiles_cap, p.hist, p.skeys, p.svals);
+  hipLaunchKernelGGL(bin_accumulate_kernel, dim3(p.n_bins), dim3(ACC_THREADS), lds, st, p.skeys, p.svals, p.shift,
+                     p.n_keys, p.total, p.base, p.levels, grad_table);
+  return hipGetLastError();
+}
+
+}  // namespace mnr

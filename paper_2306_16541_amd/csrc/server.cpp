@@ -5,8 +5,8 @@
 // admits queued requests (free slot + memory budget), and launches the next
 // tick whenever fewer than two are in flight.  A tick renders up to
 // tiles_per_tick 16x16 tiles taken from admitted requests; a request
-// completes with the tick that renders its last tile (tick composition: see
-// launch_locked).  Ticks are replayed from two captured hipGraphs (tile-table
+// completes with the tick that renders its last tile (request bookkeeping
+// and tick composition: scheduler.h).  Ticks are replayed from two captured hipGraphs (tile-table
 // upload + tick kernel), alternating between two tile tables so the host can
 // fill one while the GPU reads the other.  Each table has its own stream, so
 // the next tick's blocks take over compute units as the previous tick's
@@ -19,7 +19,6 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -28,6 +27,7 @@
 #include "../../include/metanerf_server.h"
 #include "host_common.h"
 #include "kernels.h"
+#include "scheduler.h"
 
 namespace mnr {
 
@@ -36,27 +36,18 @@ static int64_t now_ns() {
       .count();
 }
 
-struct Request {
-  uint64_t ticket = 0;
-  int user = 0;
+// What the scheduler carries per request: the kernel's arguments and an
+// event on the caller's stream that the request's first tick waits on.
+struct Payload {
   RenderArgs args;
-  int n_tiles = 0, next_tile = 0;
-  int slot = -1;
-  uint64_t out_bytes = 0;
-  int64_t t[4] = {0, 0, 0, 0};  // arrival, admission, first tick, completion
-  bool done = false;
+  hipEvent_t ready = nullptr;
 };
+using Sched = Scheduler<Payload>;
 
 struct User {
   mnr_field field;
   mnr_motion motion;
   uint64_t bytes;
-};
-
-struct Tick {
-  hipEvent_t ev = nullptr;
-  bool inflight = false;
-  std::vector<uint64_t> finishing;
 };
 
 static uint64_t field_bytes(const mnr_field& f, const mnr_motion& m) {
@@ -80,18 +71,14 @@ struct mnr_server {
   bool stop = false;
   hipError_t gpu_err = hipSuccess;
   int device = 0;
-  uint64_t budget = 0, resident = 0, inflight_bytes = 0;
-  int max_slots = 0, tick_cap = 0;
+  int tick_cap = 0;
   bool have_format = false;
   mnr_dtype table_dt = MNR_F32, mlp_dt = MNR_F32;
   int nhh = 0;
   std::map<int, User> users;
-  std::map<uint64_t, Request> reqs;
-  std::deque<uint64_t> queue;    // waiting for admission
-  std::vector<uint64_t> active;  // admitted, oldest first
-  std::vector<int> free_slots;
-  uint64_t next_ticket = 1;
-  mnr_server_stats st{};
+  Sched* sched = nullptr;
+  std::vector<TileRef> items;           // composition scratch of the next tick
+  std::vector<Sched::Request*> starting;
   // device side
   hipStream_t stream[2] = {nullptr, nullptr};  // one per tick buffer
   hipStream_t copy_stream = nullptr;            // request arguments
@@ -103,37 +90,27 @@ struct mnr_server {
   WorkTable* h_wt[2] = {nullptr, nullptr};
   size_t wt_bytes = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
-  Tick ticks[2];
+  hipEvent_t tick_ev[2] = {nullptr, nullptr};
   int next_buf = 0;
 
   void loop();
   bool retire_locked();
   bool admit_locked();
   bool launch_locked();
+  void set_error(hipError_t e) {
+    if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
+  }
 };
-
-static void complete_locked(mnr_server* s, uint64_t ticket, int64_t t_done) {
-  Request& r = s->reqs[ticket];
-  r.done = true;
-  r.t[3] = t_done;
-  s->free_slots.push_back(r.slot);
-  s->inflight_bytes -= r.out_bytes;
-  s->active.erase(std::find(s->active.begin(), s->active.end(), ticket));
-  s->st.completed++;
-}
 
 bool mnr_server::retire_locked() {
   bool any = false;
   for (int k = 0; k < 2; ++k) {
-    Tick& t = ticks[(next_buf + k) & 1];  // oldest first
-    if (!t.inflight) continue;
-    const hipError_t q = hipEventQuery(t.ev);
+    const int buf = (next_buf + k) & 1;  // oldest first
+    if (!sched->tick_busy(buf)) continue;
+    const hipError_t q = hipEventQuery(tick_ev[buf]);
     if (q == hipErrorNotReady) break;
-    if (q != hipSuccess && gpu_err == hipSuccess) gpu_err = q;
-    const int64_t tn = now_ns();
-    for (uint64_t id : t.finishing) complete_locked(this, id, tn);
-    t.finishing.clear();
-    t.inflight = false;
+    set_error(q);
+    sched->retire(buf, now_ns());
     any = true;
   }
   if (any) cv_done.notify_all();
@@ -141,66 +118,28 @@ bool mnr_server::retire_locked() {
 }
 
 bool mnr_server::admit_locked() {
-  bool any = false;
-  while (!queue.empty() && !free_slots.empty()) {
-    Request& r = reqs[queue.front()];
-    if (resident + inflight_bytes + r.out_bytes > budget) break;  // wait for memory
-    r.slot = free_slots.back();
-    free_slots.pop_back();
-    inflight_bytes += r.out_bytes;
-    r.t[1] = now_ns();
-    h_slots[r.slot] = r.args;
-    const hipError_t e = hipMemcpyAsync(d_slots + r.slot, h_slots + r.slot, sizeof(RenderArgs),
-                                        hipMemcpyHostToDevice, copy_stream);
-    if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
-    active.push_back(r.ticket);
-    queue.pop_front();
-    any = true;
+  const std::vector<Sched::Request*> adm = sched->admit(now_ns());
+  for (Sched::Request* r : adm) {
+    h_slots[r->slot] = r->payload.args;
+    set_error(hipMemcpyAsync(d_slots + r->slot, h_slots + r->slot, sizeof(RenderArgs), hipMemcpyHostToDevice,
+                             copy_stream));
   }
-  if (any) {  // a slot is rewritten only after every tick that read it retired
-    const hipError_t e = hipEventRecord(copy_ev, copy_stream);
-    if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
+  if (!adm.empty()) {  // a slot is rewritten only after every tick that read it retired
+    set_error(hipEventRecord(copy_ev, copy_stream));
     copy_wait[0] = copy_wait[1] = true;
   }
-  return any;
+  return !adm.empty();
 }
 
+// Tick composition is the scheduler's (Scheduler::compose); this uploads
+// the tile table and replays the buffer's captured graph.
 bool mnr_server::launch_locked() {
   const int buf = next_buf;
-  Tick& t = ticks[buf];
-  if (t.inflight) return false;
-  WorkTable* w = h_wt[buf];
-  int n = 0;
-  const int64_t tn = now_ns();
-  // Tick composition: the oldest unfinished request first takes up to a
-  // quarter of the tile budget (no request starves), then the rest of the
-  // budget goes to requests with the fewest remaining tiles, so small
-  // frames overtake large ones instead of queueing behind them.
-  std::vector<Request*> cand;
-  for (uint64_t id : active) {
-    Request& r = reqs[id];
-    if (r.next_tile < r.n_tiles) cand.push_back(&r);  // else: launched, awaiting completion
-  }
-  auto take_from = [&](Request& r, int budget) {
-    const int take = std::min(r.n_tiles - r.next_tile, budget);
-    if (take <= 0) return;
-    if (r.next_tile == 0) r.t[2] = tn;
-    for (int k = 0; k < take; ++k) w->items[n + k] = WorkItem{r.slot, r.next_tile + k};
-    n += take;
-    r.next_tile += take;
-    if (r.next_tile == r.n_tiles) t.finishing.push_back(r.ticket);
-  };
-  if (!cand.empty()) {
-    take_from(*cand.front(), std::max(tick_cap / 4, 1));
-    std::stable_sort(cand.begin(), cand.end(), [](const Request* a, const Request* b) {
-      return a->n_tiles - a->next_tile < b->n_tiles - b->next_tile;
-    });
-    for (Request* r : cand) {
-      if (n >= tick_cap) break;
-      take_from(*r, tick_cap - n);
-    }
-  }
+  if (sched->tick_busy(buf)) return false;
+  const int n = sched->compose(buf, now_ns(), items, starting);
   if (n == 0) return false;
+  WorkTable* w = h_wt[buf];
+  for (int k = 0; k < n; ++k) w->items[k] = WorkItem{items[k].slot, items[k].tile};
   w->counter = 0;
   w->n_items = n;
   hipStream_t sb = stream[buf];
@@ -215,8 +154,8 @@ bool mnr_server::launch_locked() {
     if (e == hipSuccess) e = hipGraphInstantiate(&graph[buf], g, nullptr, nullptr, 0);
     if (g) hipGraphDestroy(g);
     if (e != hipSuccess) {
-      if (gpu_err == hipSuccess) gpu_err = e;
-      return false;
+      set_error(e);
+      return true;  // the tick counts as in flight; the error path fails it
     }
   }
   hipError_t e = hipSuccess;
@@ -224,13 +163,12 @@ bool mnr_server::launch_locked() {
     e = hipStreamWaitEvent(sb, copy_ev, 0);
     copy_wait[buf] = false;
   }
+  for (Sched::Request* r : starting)  // work the caller queued on the output first
+    if (e == hipSuccess && r->payload.ready) e = hipStreamWaitEvent(sb, r->payload.ready, 0);
   if (e == hipSuccess) e = hipGraphLaunch(graph[buf], sb);
-  if (e == hipSuccess) e = hipEventRecord(t.ev, sb);
-  if (e != hipSuccess && gpu_err == hipSuccess) gpu_err = e;
-  t.inflight = true;
+  if (e == hipSuccess) e = hipEventRecord(tick_ev[buf], sb);
+  set_error(e);
   next_buf ^= 1;
-  st.ticks++;
-  st.tiles += n;
   return true;
 }
 
@@ -238,18 +176,18 @@ void mnr_server::loop() {
   hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    bool progress = retire_locked();
-    progress |= admit_locked();
-    progress |= launch_locked();
-    const bool idle = queue.empty() && active.empty() && !ticks[0].inflight && !ticks[1].inflight;
-    if (stop && idle) break;
-    if (gpu_err != hipSuccess) {  // fail every pending request rather than hang
-      for (auto& kv : reqs) kv.second.done = true;
-      queue.clear();
-      active.clear();
-      cv_done.notify_all();
-      if (stop) break;
+    bool progress = false;
+    if (gpu_err == hipSuccess) {
+      progress = retire_locked();
+      if (gpu_err == hipSuccess) progress |= admit_locked();
+      if (gpu_err == hipSuccess) progress |= launch_locked();
     }
+    if (gpu_err != hipSuccess && !sched->idle()) {  // fail every pending request rather than hang
+      sched->fail_all(now_ns());
+      cv_done.notify_all();
+    }
+    const bool idle = sched->idle();
+    if (stop && idle) break;
     if (!progress) {
       if (idle)
         cv_work.wait(lk);
@@ -268,10 +206,9 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
   if (tiles_per_tick == 0) tiles_per_tick = 1024;
   if (tiles_per_tick < 16 || tiles_per_tick > 16384) return fail(MNR_E_SHAPE, "server: tiles_per_tick out of range");
   mnr_server* s = new mnr_server();
-  s->budget = mem_budget;
-  s->max_slots = max_slots;
+  s->sched = new Sched(mem_budget, max_slots, tiles_per_tick);
   s->tick_cap = tiles_per_tick;
-  for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  s->items.reserve(tiles_per_tick);
   s->wt_bytes = sizeof(WorkTable) + sizeof(WorkItem) * (size_t)tiles_per_tick;
   hipError_t e = hipGetDevice(&s->device);
   for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipStreamCreateWithFlags(&s->stream[b], hipStreamNonBlocking);
@@ -282,7 +219,7 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
   for (int b = 0; b < 2 && e == hipSuccess; ++b) {
     e = hipMalloc((void**)&s->d_wt[b], s->wt_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_wt[b], s->wt_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ticks[b].ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->tick_ev[b], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
     mnr_server_destroy(s);
@@ -306,11 +243,12 @@ mnr_status mnr_server_add_user(mnr_server* s, int32_t user, const mnr_field* fie
   if (s->have_format && (field->table_dtype != s->table_dt || field->mlp_dtype != s->mlp_dt ||
                          field->n_layers - 2 != s->nhh))
     return fail(MNR_E_DTYPE, "server: every user must share the field format");
-  if (s->resident + bytes > s->budget)
-    return fail(MNR_E_OOM, "server: user needs %llu bytes, %llu of %llu in use", (unsigned long long)bytes,
-                (unsigned long long)s->resident, (unsigned long long)s->budget);
+  if (!s->sched->reserve_resident(bytes))
+    return fail(MNR_E_OOM, "server: user needs %llu bytes; %llu resident and %llu queued or in flight of %llu",
+                (unsigned long long)bytes, (unsigned long long)s->sched->resident_bytes(),
+                (unsigned long long)(s->sched->inflight_bytes() + s->sched->queued_bytes()),
+                (unsigned long long)s->sched->budget());
   s->users[user] = User{*field, *motion, bytes};
-  s->resident += bytes;
   s->have_format = true;
   s->table_dt = field->table_dtype;
   s->mlp_dt = field->mlp_dtype;
@@ -319,7 +257,8 @@ mnr_status mnr_server_add_user(mnr_server* s, int32_t user, const mnr_field* fie
 }
 
 mnr_status mnr_server_submit(mnr_server* s, int32_t user, const mnr_pose* pose, const mnr_camera* cam, int32_t H,
-                             int32_t W, int32_t spp, const mnr_opts* opts, float* out_rgba, uint64_t* ticket) {
+                             int32_t W, int32_t spp, const mnr_opts* opts, float* out_rgba, void* after_stream,
+                             uint64_t* ticket) {
   clear_error();
   if (!s || !ticket) return fail(MNR_E_INVALID, "server: null argument");
   const int64_t arrive = now_ns();
@@ -328,34 +267,59 @@ mnr_status mnr_server_submit(mnr_server* s, int32_t user, const mnr_pose* pose, 
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->users.find(user);
     if (it == s->users.end()) {
-      s->st.rejected++;
+      s->sched->count_rejected();
       return fail(MNR_E_INVALID, "server: unknown user %d", user);
     }
     u = it->second;
   }
   if (mnr_status st = validate_common(&u.field, &u.motion, pose, cam, H, W, spp, opts, nullptr, H * W, out_rgba)) {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->st.rejected++;
+    s->sched->count_rejected();
     return st;
   }
-  Request r;
-  pack_args(r.args, &u.field, &u.motion, pose, cam, H, W, spp, opts, nullptr, H * W);  // FK here
-  r.args.out = out_rgba;
-  r.user = user;
-  r.n_tiles = slot_count(H, W, nullptr, H * W) / 256;
-  r.out_bytes = (uint64_t)H * W * 16;
-  r.t[0] = arrive;
+  Payload p;
+  pack_args(p.args, &u.field, &u.motion, pose, cam, H, W, spp, opts, nullptr, H * W);  // FK here
+  p.args.out = out_rgba;
+  if (after_stream) {  // the first tick of this request waits for what is queued there now
+    hipError_t e = hipEventCreateWithFlags(&p.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(p.ready, (hipStream_t)after_stream);
+    if (e != hipSuccess) {
+      if (p.ready) hipEventDestroy(p.ready);
+      return fail(MNR_E_HIP, "server: ordering event: %s", hipGetErrorString(e));
+    }
+  }
+  const int n_tiles = slot_count(H, W, nullptr, H * W) / 256;
+  const uint64_t out_bytes = (uint64_t)H * W * 16;
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->resident + r.out_bytes > s->budget) {
-    s->st.rejected++;
+  if (s->gpu_err != hipSuccess) {
+    if (p.ready) hipEventDestroy(p.ready);
+    return fail(MNR_E_HIP, "server: %s", hipGetErrorString(s->gpu_err));
+  }
+  if (s->sched->submit(p, n_tiles, out_bytes, arrive, ticket) != Sched::SUBMIT_OK) {
+    if (p.ready) hipEventDestroy(p.ready);
     return fail(MNR_E_OOM, "server: a %dx%d frame does not fit the memory budget", H, W);
   }
-  r.ticket = s->next_ticket++;
-  *ticket = r.ticket;
-  s->reqs.emplace(r.ticket, r);
-  s->queue.push_back(r.ticket);
-  s->st.submitted++;
   s->cv_work.notify_one();
+  return MNR_OK;
+}
+
+// A finished ticket is released (forgotten) by the poll or wait that
+// reports it finished.
+static mnr_status report_locked(mnr_server* s, uint64_t ticket, int32_t* done, int64_t* t_ns) {
+  const Sched::Request* r = s->sched->find(ticket);
+  if (!r) return fail(MNR_E_INVALID, "server: unknown ticket %llu", (unsigned long long)ticket);
+  const hipEvent_t ready = r->payload.ready;
+  const Sched::Poll p = s->sched->poll(ticket, t_ns, true);
+  if (p == Sched::POLL_PENDING) {
+    if (done) *done = 0;
+    return MNR_OK;
+  }
+  if (ready) hipEventDestroy(ready);
+  if (done) *done = 1;
+  if (p == Sched::POLL_FAILED) {
+    if (s->gpu_err != hipSuccess) return fail(MNR_E_HIP, "server: %s", hipGetErrorString(s->gpu_err));
+    return fail(MNR_E_OOM, "server: request can no longer fit the memory budget");
+  }
   return MNR_OK;
 }
 
@@ -363,37 +327,39 @@ mnr_status mnr_server_poll(mnr_server* s, uint64_t ticket, int32_t* done, int64_
   clear_error();
   if (!s || !done) return fail(MNR_E_INVALID, "server: null argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return fail(MNR_E_INVALID, "server: unknown ticket");
-  if (s->gpu_err != hipSuccess) return fail(MNR_E_HIP, "server: %s", hipGetErrorString(s->gpu_err));
-  *done = it->second.done ? 1 : 0;
-  if (t_ns) std::memcpy(t_ns, it->second.t, sizeof(it->second.t));
-  return MNR_OK;
+  return report_locked(s, ticket, done, t_ns);
 }
 
 mnr_status mnr_server_wait(mnr_server* s, uint64_t ticket, int32_t timeout_ms, int64_t* t_ns) {
   clear_error();
   if (!s) return fail(MNR_E_INVALID, "server: null argument");
   std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return fail(MNR_E_INVALID, "server: unknown ticket");
-  const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms),
-                                      [&] { return it->second.done || s->gpu_err != hipSuccess; });
-  if (s->gpu_err != hipSuccess) return fail(MNR_E_HIP, "server: %s", hipGetErrorString(s->gpu_err));
+  if (!s->sched->find(ticket)) return fail(MNR_E_INVALID, "server: unknown ticket %llu", (unsigned long long)ticket);
+  const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms), [&] {
+    const Sched::Request* r = s->sched->find(ticket);
+    return !r || r->done;
+  });
   if (!ok) return fail(MNR_E_BUSY, "server: ticket not done after %d ms", timeout_ms);
-  if (t_ns) std::memcpy(t_ns, it->second.t, sizeof(it->second.t));
-  return MNR_OK;
+  return report_locked(s, ticket, nullptr, t_ns);
 }
 
 mnr_status mnr_server_get_stats(mnr_server* s, mnr_server_stats* out) {
   clear_error();
   if (!s || !out) return fail(MNR_E_INVALID, "server: null argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  *out = s->st;
-  out->queued = (int32_t)s->queue.size();
-  out->admitted = (int32_t)s->active.size();
-  out->resident_bytes = s->resident;
-  out->inflight_bytes = s->inflight_bytes;
+  const Sched& q = *s->sched;
+  *out = mnr_server_stats{};
+  out->submitted = q.submitted();
+  out->completed = q.completed();
+  out->rejected = q.rejected();
+  out->failed = q.failed();
+  out->ticks = q.ticks();
+  out->tiles = q.tiles();
+  out->queued = q.queued();
+  out->admitted = q.admitted();
+  out->tracked = (int32_t)q.tracked();
+  out->resident_bytes = q.resident_bytes();
+  out->inflight_bytes = q.inflight_bytes();
   return MNR_OK;
 }
 
@@ -411,9 +377,15 @@ mnr_status mnr_server_destroy(mnr_server* s) {
   for (int b = 0; b < 2; ++b)
     if (s->stream[b]) hipStreamSynchronize(s->stream[b]);
   if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
+  if (s->sched) {
+    s->sched->for_each([](const Sched::Request& r) {
+      if (r.payload.ready) hipEventDestroy(r.payload.ready);
+    });
+    delete s->sched;
+  }
   for (int b = 0; b < 2; ++b) {
     if (s->graph[b]) hipGraphExecDestroy(s->graph[b]);
-    if (s->ticks[b].ev) hipEventDestroy(s->ticks[b].ev);
+    if (s->tick_ev[b]) hipEventDestroy(s->tick_ev[b]);
     if (s->d_wt[b]) hipFree(s->d_wt[b]);
     if (s->h_wt[b]) hipHostFree(s->h_wt[b]);
   }

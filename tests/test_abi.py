@@ -126,8 +126,14 @@ def test_invalid_calls_are_rejected_before_launch():
     f.mlp_dtype = 2
     gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)
     assert m.lib.mnr_render_backward(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), 8, 8, 8, None, None, 64,
-                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None, None) == -7
-    assert "adjoint" in m.lib.mnr_last_error().decode()
+                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None, None, None,
+                                     0, None) == -1
+    assert "grad_res" in m.lib.mnr_last_error().decode()
+    gr = (C.c_void_p * 6)(*[0x5000 + 0x100 * k for k in range(6)])
+    assert m.lib.mnr_render_backward(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), 8, 8, 8, None, None, 64,
+                                     0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, C.cast(gr, m._PL),
+                                     None, None, 0, None) == -1
+    assert "workspace" in m.lib.mnr_last_error().decode()
     f.mlp_dtype = 0
     for k in range(6):
         mo.res_w[k] = None
@@ -203,3 +209,40 @@ def test_build_script_loads_without_the_package():
             "import inspect; assert 'spec_from_file_location' in inspect.getsource(g.build)\n")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 0, r.stderr
+
+
+def test_adjoint_workspace_size_and_checks():
+    # Adjoint workspace: binned-scatter records for every sample, hashed
+    # level and corner, twice, plus per-tile bin histograms; with a residual
+    # network, 14 floats per sample slot and 64 floats of bias gradient
+    # (include/metanerf.h).
+    m = _lib()
+    sc = scenes.scene_body(H=8, W=8, spp=8, res=8, log2_T=19)
+    _, f, mo, pose, cam = _args(sc)
+    nh = sum(1 for n in sc.level_res if (int(n) + 1) ** 3 > 1 << 19)
+    assert nh == 9
+    a256 = lambda b: (b + 255) // 256 * 256
+    for n_rays, spp in ((8192, 128), (100, 7)):
+        cap = n_rays * spp * nh * 8
+        n_keys = nh << 19                   # keys number the hashed levels only
+        n_bins = -(-n_keys // (1 << 13))      # slices of 2^13 rows
+        tiles = -(-cap // 8192)
+        want = (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + 2 * a256(n_bins * 4))
+        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
+        for k in range(6):
+            mo.res_w[k] = 0x7000 + 0x100 * k
+        split = a256(14 * n_rays * -(-spp // 64) * 64 * 4) + 256
+        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split
+        for k in range(6):
+            mo.res_w[k] = None
+    assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
+    f.log2_T = 24       # the largest table: 4 hashed levels of 2^24 rows, 4096 slices of 2^14 rows
+    assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 64, 8) > 0
+    f.log2_T = 19
+    gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)
+    # a misaligned workspace and a too-small one are rejected before any launch
+    for ws, nb, code in ((0x12345, 1 << 30, -1), (0x100000, 1024, -2)):
+        r = m.lib.mnr_render_backward(C.byref(f), C.byref(mo), C.byref(pose.c), C.byref(cam), 8, 8, 8, None, None,
+                                      64, 0x4000, 0x4100, 0x4200, C.cast(gw, m._PL), 0x4300, None, None, None, ws,
+                                      nb, None)
+        assert r == code, (r, m.lib.mnr_last_error().decode())

@@ -4,8 +4,9 @@ oracle's autograd, and a pose refiner trained on the GPU through the whole
 chain (render, adjoint, host forward-kinematics adjoint, refiner adjoint)
 that brings the image of a perturbed pose back to the true pose's image.
 
-Tolerance for dL/dG: relative L2 2e-3 on the FP32 path, as for the other
-adjoint outputs (FP32 forward and adjoint, unordered float atomics).
+Tolerances for dL/dG, as for the other adjoint outputs: relative L2 2e-3
+(FP32 path) and 5e-2 (BF16 MLP); every entry within 1e-4 (FP32) or 1e-1
+(BF16, as for the field's gradients) of the largest oracle entry.
 """
 import numpy as np
 import pytest
@@ -88,18 +89,9 @@ def test_bone_transform_gradient_matches_oracle(mlp_dtype, tol):
     print(f"[dL/dG mlp={mlp_dtype}] rel-L2 {err:.2e}, |dL/dG| {np.linalg.norm(want):.3e}", flush=True)
     assert np.linalg.norm(want) > 1e-4
     assert err <= tol
-
-
-def _joint_positions(parents, rest, R):
-    """World positions of the joints (translations of A_j) for rotations R [J,3,3]."""
-    J = torch.as_tensor(np.asarray(rest, dtype=np.float64))
-    rot, pos = [], []
-    for j, p in enumerate(parents):
-        if p < 0:
-            rot.append(R[j]); pos.append(J[j])
-        else:
-            rot.append(rot[p] @ R[j]); pos.append(rot[p] @ (J[j] - J[p]) + pos[p])
-    return torch.stack(pos)
+    ew = float(np.abs(got - want).max() / np.abs(want).max())
+    print(f"  every entry: max|dG_gpu - dG_oracle| / max|dG_oracle| = {ew:.2e}", flush=True)
+    assert ew <= (1e-4 if mlp_dtype == 0 else 1e-1)
 
 
 def _joint_positions(parents, rest, R):

@@ -68,6 +68,19 @@ def test_alone_equals_mix_equals_render():
     print(f"server vs mnr_render max-abs {d:.3e}; first differing pixels {bad}: "
           f"server {alone[bad].tolist()} render {ref[bad].tolist()}")
     assert d <= 1e-6
+    # the request from the mix against the FP64 oracle on the FP32 master
+    # parameters (FP16 table, BF16 MLP on the GPU): PSNR >= 45 dB on a
+    # sample of its pixels
+    import dataclasses
+    from helpers import oracle_render, psnr
+    sc_req = dataclasses.replace(sc0, H=H, W=W, spp=spp)
+    pid = np.arange(0, H * W, 7)
+    want = oracle_render(sc_req, pixel_ids=pid, axis_angle=scenes.pose(1, 0.3), cam=scenes.camera(H, W, yaw=0.3))
+    got = mixed.cpu().numpy()[pid]
+    q = psnr(got[:, :3], want[:, :3])
+    print(f"server request in the mix vs oracle: PSNR {q:.1f} dB, max-abs {np.abs(got - want).max():.2e} "
+          f"({pid.size} pixels, opacity > 0.5 on {(want[:, 3] > 0.5).mean():.0%})", flush=True)
+    assert q >= 45.0
     for u, p, c, hh, ww, o in outs:     # every mixed request matches its own plain render
         r = m.render(users[u][1], p, c, hh, ww, spp, m.make_opts())
         assert float((o - r).abs().max()) <= 1e-6
