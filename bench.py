@@ -299,10 +299,50 @@ def train_bench(steps, warmup):
     res["skel_cnn_ms"] = {"forward": cnn_f, "adjoint": cnn_b}
     atomics = n_eval * (16 * 8 * 2 + 24 * 8)
     res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
+    res.update(train_variants(sc, pose, cam, pid, tgt, steps))
     res["hashed_level_records"] = n_eval * 9 * 8
     res["evaluated_samples"] = n_eval
     res["adjoint_atomics_per_s_upper"] = atomics / (bwd_atomic_ms * 1e-3)
     return res
+
+
+def train_variants(sc, pose, cam, pid, tgt, steps):
+    """The same 8192-ray batch with the residual motion network on (grid
+    field) and with the paper's frequency-encoded field: step time and the
+    adjoint alone (both split adjoints, through the adjoint workspace)."""
+    dev = "cuda"
+    out = {}
+    rw, w_omega = scenes.residual_weights(21)
+    trainers = {
+        "residual_network": m.Trainer(torch.as_tensor(sc.table, device=dev),
+                                      [torch.as_tensor(w, device=dev) for w in sc.mlp],
+                                      torch.as_tensor(sc.logits, device=dev), sc.level_res, m.F32, m.BF16,
+                                      max_rays=8192, spp=sc.spp, residual=(rw, w_omega, 4.0)),
+        "frequency_field": m.Trainer.frequency([torch.as_tensor(w, device=dev) for w in scenes.freq_field_weights(31)],
+                                               torch.as_tensor(sc.logits, device=dev), max_rays=8192, spp=sc.spp),
+    }
+    opts = m.make_opts(stratified=True, seed=1)
+    for name, tr in trainers.items():
+        k = [0]
+
+        def step():
+            k[0] += 1
+            tr.step(pose, cam, sc.H, sc.W, sc.spp, pid, tgt, seed=k[0])
+        wall, _ = timed_launches(step, steps, 2)
+        b = tr.buf
+        tch = b["t_chunks"][: 8192 * m.saved_size(sc.spp)].view(8192, -1)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        m.render(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, out=b["rgba"], counter=cnt, t_chunks=tch)
+        m.mse_loss(b["rgba"], tgt, b["grad_rgba"])
+        gres = b.get("res_grad")
+        _, bwd_ms = timed_launches(
+            lambda: m.render_backward(tr.field, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, b["grad_rgba"],
+                                      b.get("table_grad"), b["w_grad"], b["weights_grad"], adjoint_ws=tr.adjoint_ws,
+                                      grad_res=gres), steps, 1)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": wall, "adjoint_ms": bwd_ms, "evaluated_samples": int(cnt.item()),
+                     "loss": tr.loss()}
+    return out
 
 
 def serve_bench(user_counts=(1, 2, 4, 8), spp=128, rate_hz=30.0, warmup_s=1.0, window_s=(10.0, 10.0, 10.0, 10.0),

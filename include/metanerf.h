@@ -91,8 +91,9 @@ typedef enum { MNR_ENC_GRID = 0, MNR_ENC_FREQ = 1 } mnr_encoding;
  *   h4 = ReLU(W4 [h3; gamma]), o = W5 h4  (c = sigmoid(o[0:3]), sigma = ReLU(o[3])).
  * Then n_layers = 5, width = {64, 64, 64, 64, 64, 4} (w[3] is [64][128]:
  * h3 and gamma), mlp_dtype = MNR_BF16 (BF16 MFMA, FP32 accumulation); the
- * grid fields (n_levels .. table, dense_packed) are ignored.  Forward only:
- * mnr_render_backward, mnr_train_step and the server return
+ * grid fields (n_levels .. table, dense_packed) are ignored.  It trains:
+ * mnr_render_backward and mnr_train_step run its adjoint (split, through
+ * the adjoint workspace, which it requires); the server returns
  * MNR_E_UNSUPPORTED for it. */
 typedef struct {
   int32_t n_levels, n_feat, log2_T;
@@ -139,14 +140,17 @@ typedef struct {
    *   res_w[3] W4 [64][96], res_w[4] W5 [3][64], res_w[5] W_omega [64][3 n_bones]
    * of  h1 = ReLU(W1 g + W_omega Omega), h2 = ReLU(W2 h1), h3 = ReLU(W3 h2),
    *     h4 = ReLU(W4 [h3; g]) (skip connection at the 4th layer), x_res = W5 h4,
-   * where Omega is the rendered pose's axis angles (joint-major) and
+   * where Omega is the observed pose's joint angles (joint-major): the
+   * axis angles, or with a refiner adjustment (mnr_pose.delta) the
+   * axis-angle of R(delta_j) R(axis_angle_j), angle in [0, pi], and
    *   g = [x, for k = 0..3: w_k sin(2^k pi x_c), w_k cos(2^k pi x_c) (c = 0..2),
    *        five zeros],  w_k = (1 - cos(pi clamp(res_alpha - k, 0, 1))) / 2
    * (a truncated Hann window over the frequency bands; res_alpha = 4 opens
    * all of them), x = x_skel.  The field is then queried at x_skel + x_res.
    * Runs on BF16 MFMA with FP32 accumulation, so it needs mlp_dtype ==
-   * MNR_BF16; forward only: mnr_render_backward, mnr_train_step and the
-   * server return MNR_E_UNSUPPORTED when it is on. */
+   * MNR_BF16.  It trains (mnr_render_backward's grad_res, mnr_train_step's
+   * res_* state; gradients reach W1..W5 and W_omega, not Omega); the server
+   * returns MNR_E_UNSUPPORTED when it is on. */
   const void* res_w[6];
   float res_alpha;
 } mnr_motion;
@@ -297,6 +301,13 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
  *                mnr_fk_backward carries it on to the pose.
  * Gradients are those of the forward actually computed (early termination
  * included).  Summation order of the atomics is not deterministic.
+ * Frequency-encoded field (encoding = MNR_ENC_FREQ): grad_table is unused
+ * (may be NULL) and grad_w[0..4] are W1..W5 (grad_w[3] [64][128]); the
+ * adjoint runs split: the forward pass again with its four hidden
+ * activations saved (BF16) and the compositing adjoint, then the skip
+ * MLP's adjoint on BF16 MFMA from the saved activations (weight gradients
+ * and dL/dx_final through gamma's derivative), then the skinning adjoint;
+ * it needs adjoint_ws.
  * grad_res (NULL unless motion->res_w[0] != NULL): dev float pointers for
  * the residual motion network's gradients, W1..W5 and W_omega (shapes as
  * motion->res_w), accumulated.  The adjoint then runs split: the warp and
@@ -309,8 +320,10 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
  *     value) records that are binned by table slice and summed in LDS,
  *     instead of one global float atomic per sample, corner and feature
  *     (the same sum in another order);
- *   - with a residual network, the split adjoint's per-sample values.
- * NULL: atomics for the table, and no residual network (MNR_E_INVALID). */
+ *   - with a residual network or the frequency-encoded field, the split
+ *     adjoint's per-sample values.
+ * NULL: atomics for the table; with a residual network or the
+ * frequency-encoded field, MNR_E_INVALID. */
 mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                const mnr_pose* pose, const mnr_camera* cam, int32_t H, int32_t W,
                                int32_t spp, const mnr_opts* opts, const int32_t* pixel_ids,
@@ -324,9 +337,11 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
  * bytes each, twice) plus bin histograms -- about 200 bytes per sample for
  * the 9 hashed levels of a 2^19-row, 16-level table, none when the batch
  * (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14 rows)
- * is too large for the binned path -- plus, with a residual network, 56 bytes per
- * sample slot (n_rays * ceil(spp / 64) * 64 slots).  0: nothing to use it
- * for. */
+ * is too large for the binned path -- plus, with a residual network or the
+ * frequency-encoded field, 72 bytes per sample slot (n_rays * ceil(spp / 64)
+ * * 64 slots, rounded up to 256 bytes) and 256 bytes, and for the
+ * frequency-encoded field 512 bytes more per sample slot (its saved hidden
+ * activations).  0: nothing to use it for. */
 uint64_t mnr_adjoint_ws_bytes(const mnr_field* field, const mnr_motion* motion, int32_t n_rays, int32_t spp);
 
 /* Patch ray batch for training (Sec. 5.2: n_patches patches of size x size
@@ -403,7 +418,8 @@ mnr_status mnr_zero(void* dst, size_t n_bytes, void* stream);
  * table and MLP, lr_motion for the logits.  All buffers are caller-owned
  * device memory; the state struct lists them. */
 typedef struct {
-  float* table_master; float* table_grad; float* table_m; float* table_v; /* [L*T*F] */
+  float* table_master; float* table_grad; float* table_m; float* table_v; /* [L*T*F]; NULL for the
+                                                                             frequency-encoded field */
   float* w_master[MNR_MAX_LAYERS]; float* w_grad[MNR_MAX_LAYERS];
   float* w_m[MNR_MAX_LAYERS]; float* w_v[MNR_MAX_LAYERS];
   float* logits; float* logits_grad; float* logits_m; float* logits_v;    /* [(n_bones+1)*res^3] */
@@ -412,7 +428,8 @@ typedef struct {
   float* t_chunks;                                    /* [n_rays][ceil(spp/64) + 1] scratch */
   float* loss;                                                            /* [1] */
   void* workspace;                                           /* MNR_WORKSPACE_BYTES, or NULL */
-  void* adjoint_ws; uint64_t adjoint_ws_bytes;   /* see mnr_render_backward; required with a residual network */
+  void* adjoint_ws; uint64_t adjoint_ws_bytes;   /* see mnr_render_backward; required with a residual network
+                                                    or the frequency-encoded field */
   /* Residual motion network (when motion->res_w[0] != NULL): FP32 masters,
    * gradients and Adam moments of W1..W5, W_omega (shapes as motion->res_w);
    * Adam at lr_res updates the masters and rewrites the BF16 copies

@@ -417,14 +417,16 @@ def adjoint_workspace(field: DeviceField, n_rays: int, spp: int) -> Optional[tor
 
 def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, opts: Optional[Opts],
                     pixel_ids: Optional[torch.Tensor], t_chunks: torch.Tensor, grad_rgba: torch.Tensor,
-                    grad_table: torch.Tensor, grad_w: List[torch.Tensor], grad_weights: torch.Tensor,
+                    grad_table: Optional[torch.Tensor], grad_w: List[torch.Tensor], grad_weights: torch.Tensor,
                     grad_bones: Optional[torch.Tensor] = None, adjoint_ws: Optional[torch.Tensor] = None,
                     grad_res: Optional[List[torch.Tensor]] = None) -> None:
     """Accumulates the adjoint into the gradient buffers; grad_bones
     (optional, [n_bones, 3, 4]) receives dL/dG of the bone transforms.
     adjoint_ws (from adjoint_workspace): binned scatter of the hashed levels'
     table gradient instead of atomics, and the residual network's split
-    adjoint, whose gradients (W1..W5, W_omega) go to grad_res."""
+    adjoint, whose gradients (W1..W5, W_omega) go to grad_res.  The
+    frequency-encoded field has no table (grad_table None) and needs
+    adjoint_ws."""
     n = H * W if pixel_ids is None else int(pixel_ids.numel())
     gw = (C.c_void_p * len(grad_w))(*[g.data_ptr() for g in grad_w])
     gr = None if grad_res is None else C.cast((C.c_void_p * 6)(*[g.data_ptr() for g in grad_res]), _PL)
@@ -432,7 +434,7 @@ def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: 
     check(lib.mnr_render_backward(C.byref(field.c), C.byref(field.m), C.byref(pose.c), C.byref(cam), H, W, spp,
                                   None if opts is None else C.byref(opts), _ptr(pixel_ids), n, _ptr(t_chunks),
                                   _ptr(grad_rgba), _ptr(grad_table), C.cast(gw, _PL), _ptr(grad_weights),
-                                  _ptr(grad_bones), gr, _ptr(_workspace(grad_table.device)), _ptr(adjoint_ws), nb,
+                                  _ptr(grad_bones), gr, _ptr(_workspace(grad_rgba.device)), _ptr(adjoint_ws), nb,
                                   _stream()),
           "render_backward")
 
@@ -640,6 +642,32 @@ class Trainer:
         self.table = self.table32 if table_dtype == F32 else convert(self.table32, table_dtype)
         self.mlp = self.mlp32 if mlp_dtype == F32 else [convert(w, mlp_dtype) for w in self.mlp32]
         self.field = DeviceField(self.table, self.mlp, self.weights, level_res, box_min, box_max)
+        self._setup(dev, max_rays, spp, lr_field, lr_motion, beta1, beta2, eps, train_motion,
+                    binned_scatter or residual is not None, residual, lr_res)
+
+    @classmethod
+    def frequency(cls, mlp32: Sequence[torch.Tensor], logits32: torch.Tensor, max_rays: int = 8192, spp: int = 128,
+                  lr_field: float = 5e-4, lr_motion: float = 5e-5, beta1: float = 0.9, beta2: float = 0.99,
+                  eps: float = 1e-8, train_motion: bool = True, box_min=(-0.5,) * 3, box_max=(0.5,) * 3,
+                  skel_cnn: Optional["SkeletonCNN"] = None, residual: Optional[tuple] = None,
+                  lr_res: float = 5e-4) -> "Trainer":
+        """Trainer of the paper's own field (DeviceField.frequency): FP32
+        masters of W1..W5 (W4 [64][128]) with BF16 copies for the renderer,
+        no grid table; its adjoint always uses the adjoint workspace."""
+        self = cls.__new__(cls)
+        dev = mlp32[0].device
+        self.table32 = self.table = None
+        self.mlp32 = [w.to(torch.float32).contiguous().clone() for w in mlp32]
+        self.cnn = skel_cnn
+        self.logits = logits32.contiguous().clone() if skel_cnn is None else skel_cnn.forward()
+        self.weights = softmax_fwd(self.logits)
+        self.mlp = [convert(w, BF16) for w in self.mlp32]
+        self.field = DeviceField.frequency(self.mlp, self.weights, box_min, box_max)
+        self._setup(dev, max_rays, spp, lr_field, lr_motion, beta1, beta2, eps, train_motion, True, residual, lr_res)
+        return self
+
+    def _setup(self, dev, max_rays, spp, lr_field, lr_motion, beta1, beta2, eps, train_motion, with_ws, residual,
+               lr_res) -> None:
         self.res32 = None
         if residual is not None:
             rw, w_omega, alpha = residual
@@ -648,7 +676,6 @@ class Trainer:
             self.field.set_residual(self.res32[:5], self.res32[5], alpha)
         z = lambda t: torch.zeros_like(t, dtype=torch.float32)
         self.buf = {
-            "table_grad": z(self.table32), "table_m": z(self.table32), "table_v": z(self.table32),
             "w_grad": [z(w) for w in self.mlp32], "w_m": [z(w) for w in self.mlp32], "w_v": [z(w) for w in self.mlp32],
             "logits_grad": z(self.logits), "logits_m": z(self.logits), "logits_v": z(self.logits),
             "weights_grad": z(self.logits),
@@ -656,11 +683,14 @@ class Trainer:
             "t_chunks": torch.zeros(max_rays * saved_size(spp), device=dev), "loss": torch.zeros(1, device=dev),
             "workspace": torch.zeros(WORKSPACE_BYTES // 4, dtype=torch.int32, device=dev),
         }
+        if self.table32 is not None:
+            self.buf.update({"table_grad": z(self.table32), "table_m": z(self.table32), "table_v": z(self.table32)})
         self.max_rays, self.max_spp = max_rays, spp
         s = TrainState()
         b = self.buf
-        s.table_master, s.table_grad, s.table_m, s.table_v = (t.data_ptr() for t in
-                                                              (self.table32, b["table_grad"], b["table_m"], b["table_v"]))
+        if self.table32 is not None:
+            s.table_master, s.table_grad, s.table_m, s.table_v = (
+                t.data_ptr() for t in (self.table32, b["table_grad"], b["table_m"], b["table_v"]))
         for k in range(len(self.mlp32)):
             s.w_master[k], s.w_grad[k] = self.mlp32[k].data_ptr(), b["w_grad"][k].data_ptr()
             s.w_m[k], s.w_v[k] = b["w_m"][k].data_ptr(), b["w_v"][k].data_ptr()
@@ -669,8 +699,7 @@ class Trainer:
         s.weights_grad, s.rgba, s.grad_rgba = b["weights_grad"].data_ptr(), b["rgba"].data_ptr(), b["grad_rgba"].data_ptr()
         s.t_chunks, s.loss = b["t_chunks"].data_ptr(), b["loss"].data_ptr()
         s.workspace = b["workspace"].data_ptr()
-        self.adjoint_ws = (adjoint_workspace(self.field, max_rays, spp)
-                           if binned_scatter or residual is not None else None)
+        self.adjoint_ws = adjoint_workspace(self.field, max_rays, spp) if with_ws else None
         if self.adjoint_ws is not None:
             s.adjoint_ws, s.adjoint_ws_bytes = self.adjoint_ws.data_ptr(), self.adjoint_ws.numel()
         if self.res32 is not None:
@@ -680,7 +709,7 @@ class Trainer:
                 s.res_m[k], s.res_v[k] = b["res_m"][k].data_ptr(), b["res_v"][k].data_ptr()
         s.lr_res = lr_res
         s.lr_field, s.lr_motion, s.beta1, s.beta2, s.eps = lr_field, lr_motion, beta1, beta2, eps
-        s.step, s.train_motion = 0, (2 if skel_cnn is not None else 1) if train_motion else 0
+        s.step, s.train_motion = 0, (2 if self.cnn is not None else 1) if train_motion else 0
         self.state = s
 
     def step(self, pose: PoseHost, cam: Camera, H: int, W: int, spp: int, pixel_ids: torch.Tensor,
@@ -711,27 +740,30 @@ class Trainer:
 
     def state_dict(self) -> dict:
         b = self.buf
-        return {"step": int(self.state.step), "table": self.table32.cpu(), "mlp": [w.cpu() for w in self.mlp32],
-                "logits": self.logits.cpu(), "table_m": b["table_m"].cpu(), "table_v": b["table_v"].cpu(),
-                "w_m": [t.cpu() for t in b["w_m"]], "w_v": [t.cpu() for t in b["w_v"]],
-                "logits_m": b["logits_m"].cpu(), "logits_v": b["logits_v"].cpu()}
+        sd = {"step": int(self.state.step), "mlp": [w.cpu() for w in self.mlp32],
+              "logits": self.logits.cpu(), "w_m": [t.cpu() for t in b["w_m"]], "w_v": [t.cpu() for t in b["w_v"]],
+              "logits_m": b["logits_m"].cpu(), "logits_v": b["logits_v"].cpu()}
+        if self.table32 is not None:
+            sd.update({"table": self.table32.cpu(), "table_m": b["table_m"].cpu(), "table_v": b["table_v"].cpu()})
+        return sd
 
     def load_state_dict(self, sd: dict) -> None:
         """Restore masters and Adam moments in place, then refresh the
         renderer's copies (softmax and precision conversion kernels)."""
         b = self.buf
-        self.table32.copy_(sd["table"])
+        if self.table32 is not None:
+            self.table32.copy_(sd["table"])
         for w, v in zip(self.mlp32, sd["mlp"]):
             w.copy_(v)
         self.logits.copy_(sd["logits"])
-        for key in ("table_m", "table_v", "logits_m", "logits_v"):
+        for key in (("table_m", "table_v") if self.table32 is not None else ()) + ("logits_m", "logits_v"):
             b[key].copy_(sd[key])
         for key in ("w_m", "w_v"):
             for t, v in zip(b[key], sd[key]):
                 t.copy_(v)
         self.state.step = int(sd["step"])
         softmax_fwd(self.logits, out=self.weights)
-        if self.table is not self.table32:
+        if self.table is not None and self.table is not self.table32:
             check(lib.mnr_convert(_ptr(self.table32), _ptr(self.table), self.field.c.table_dtype, self.table32.numel(),
                                   _stream()), "convert")
         for w32, w in zip(self.mlp32, self.mlp):

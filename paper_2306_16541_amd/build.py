@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmetanerf.so")
-SOURCES = ["render.hip", "render_bwd.hip", "res_bwd.hip", "scatter.hip", "serve.hip", "train_ops.hip", "probe.hip", "skel_cnn.hip",
+SOURCES = ["render.hip", "render_bwd.hip", "res_bwd.hip", "freq_bwd.hip", "scatter.hip", "serve.hip", "train_ops.hip", "probe.hip", "skel_cnn.hip",
            "api.cpp", "fk.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

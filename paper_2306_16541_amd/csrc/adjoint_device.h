@@ -1,7 +1,9 @@
 // Device helpers of the adjoint kernels (training, Sec. 5.2): segmented
-// run sums that cut the number of gradient atomics, and the skinning
-// adjoint of one sample per lane (Eq. 7 and 9), shared by the fused adjoint
-// and the split one used with the residual motion network.
+// run sums that cut the number of gradient atomics, the skinning adjoint of
+// one sample per lane (Eq. 7 and 9), the compositing adjoint of a chunk
+// (Eq. 3), and the BF16 MFMA pieces of an MLP adjoint, shared by the fused
+// adjoint and the split ones (residual motion network, frequency-encoded
+// field).
 #pragma once
 #include "field_device.h"
 
@@ -127,6 +129,155 @@ __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[
           unsafeAtomicAdd(gplane + ((size_t)iz * R + iy) * R + ix, v[k]);
       }
     }
+  }
+}
+
+// Compositing adjoint (Eq. 3 with alpha' = alpha min(L, 1)) of one
+// 64-sample chunk of a ray, lane i holding sample i: raw outputs o (three
+// colour logits, density), weight sum L and liveness.  With
+// S_i = alpha'_i c_i + (1 - alpha'_i) S_{i+1} (the opacity channel uses
+// c = 1), dC/dc_i = T_i alpha'_i and dC/dalpha'_i = T_i (c_i - S_{i+1}):
+// S_{i+1} comes from a reverse affine scan across the wave (division-free),
+// T_i from the chunk-start transmittance T0 and a forward prefix product.
+// Sc holds S after the chunk's last sample on entry and S at its first
+// sample on return.  g_o: dL/do (zero for lanes that are not live); g_L:
+// dL/dL through the likelihood factor.
+__device__ __forceinline__ void composite_adjoint(float T0, float delta, const f4& out, float L, bool live,
+                                                  const f4& gout, float (&Sc)[4], float (&g_o)[4], float& g_L) {
+  const int lane = lane_id();
+  const float sigma = fmaxf(out[3], 0.f);
+  const float alpha = -expm1f(-sigma * delta);
+  const float mL = fminf(L, 1.f);
+  const float ap = live ? alpha * mL : 0.f;
+  float c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c[k] = 1.f / (1.f + expf(-out[k]));
+  const float incl = wave_prefix_prod(1.f - ap);
+  float excl = shfl_up(incl, 1);
+  if (lane == 0) excl = 1.f;
+  const float Ti = T0 * excl;
+  // reverse affine scan: S_i = b_i + a_i S_{i+1}
+  float A_ = 1.f - ap;
+  float Bv[4] = {ap * c[0], ap * c[1], ap * c[2], ap};
+#pragma unroll
+  for (int k = 1; k < WAVE; k <<= 1) {
+    const float Ak = shfl_down(A_, k);
+    float Bk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bk[q] = shfl_down(Bv[q], k);
+    if (lane + k < WAVE) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bv[q] = fmaf(A_, Bk[q], Bv[q]);
+      A_ *= Ak;
+    }
+  }
+  float Si[4], Snext[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Si[q] = fmaf(A_, Sc[q], Bv[q]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Snext[q] = shfl_down(Si[q], 1);
+    if (lane == WAVE - 1) Snext[q] = Sc[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Sc[q] = __shfl(Si[q], 0, WAVE);
+  float g_ap = gout[3] * Ti * (1.f - Snext[3]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g_ap += gout[k] * Ti * (c[k] - Snext[k]);
+    g_o[k] = gout[k] * Ti * ap * c[k] * (1.f - c[k]);
+  }
+  const float g_sigma = g_ap * mL * delta * (1.f - alpha);
+  g_o[3] = out[3] > 0.f ? g_sigma : 0.f;
+  g_L = (L < 1.f) ? g_ap * alpha : 0.f;
+  if (!live) g_o[0] = g_o[1] = g_o[2] = g_o[3] = 0.f;
+}
+
+// Ray slot r of a split-adjoint kernel: waves take slots in turn.
+__device__ __forceinline__ bool split_ray(const RenderArgs& a, int slot, int& orow, RaySetup& rs, int& n_done,
+                                          int nchunks) {
+  const int pix = ray_pixel(a.r, slot);
+  if (!a.r.pixel_ids && pix < 0) return false;
+  orow = a.r.pixel_ids ? slot : pix;
+  if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) return false;
+  n_done = (int)a.t_chunks[(size_t)orow * (nchunks + 1) + nchunks];
+  return true;
+}
+
+// ---- BF16 MLP adjoint helpers of the split kernels ---------------------------
+
+constexpr int RES_TB_BYTES = 2 * 64 * 16 * 2;  // a wave's transpose buffer (2 x 64 x 16 bf16)
+
+// Stage W^T of a layer W [M][K] (BF16 fragments) as the A operand of
+// dX = W^T dY, its output dimension padded to Kpad.
+template <typename WT>
+__device__ void stage_t(char* lds, const WT* __restrict__ w, int M, int K, int Kpad) {
+  for (int e = threadIdx.x; e < K * Kpad; e += blockDim.x) {
+    const int m = e / Kpad, k = e - m * Kpad;  // element (m, k) of W^T = W[k][m]
+    const float v = (k < M) ? (float)w[(size_t)k * K + m] : 0.0f;
+    *(__bf16*)(lds + frag_offset<MNR_BF16>(m, k, Kpad / 32)) = (__bf16)v;
+  }
+}
+
+__device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
+  return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
+}
+
+// dW[M_out x K] (row stride ld) += d (MT tiles) x h^T (NT tiles) over the
+// 16 samples of one tile, through the wave's transpose buffer tb
+// (2 x 64 x 16 bf16) and LDS float atomics.  With ld = 4 (mod 16) the 64
+// lanes of one atomic (rows 4g + j, columns c) fall in distinct banks.
+template <int MT, int NT>
+__device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int ld,
+                                        int lane) {
+  __bf16* td = tb;            // [64 rows][16 samples]
+  __bf16* th = tb + 64 * 16;  // [64 columns][16 samples]
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) td[(16 * t + 4 * g + j) * 16 + c] = (__bf16)d[t][j];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
+  wave_sync_lds();
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+      bf16x8 av, bv;
+      if (g < 2) {
+        av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
+        bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
+      }
+      const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * mt + 4 * g + j;
+        if (row < M_out) atomicAdd(dw + row * ld + 16 * kt + c, acc[j]);
+      }
+    }
+  }
+  wave_sync_lds();
+}
+
+// out[mt] = W^T-fragments (MT m-tiles, KS 32-wide k steps) x x (2 KS tiles).
+template <int MT, int KS>
+__device__ __forceinline__ void mm_t(const char* wl, const f4* x, f4* out, int lane) {
+  const bf16x8* W = (const bf16x8*)wl;
+  bf16x8 b[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+    out[mt] = acc;
   }
 }
 

@@ -88,7 +88,6 @@ mnr_status validate_common(const mnr_field* f, const mnr_motion* m, const mnr_po
     return fail(MNR_E_SHAPE, "motion: packed copy needs res <= %d, got %d", MAX_PACKED_RES, m->res);
   if (m->packed && ((uintptr_t)m->packed & 15)) return fail(MNR_E_INVALID, "motion: packed copy not 16-byte aligned");
   if (m->res_w[0]) {
-    if (p->delta) return fail(MNR_E_UNSUPPORTED, "motion: residual motion network together with a refined pose");
     for (int k = 1; k < 6; ++k)
       if (!m->res_w[k]) return fail(MNR_E_INVALID, "motion: residual weight %d is null", k);
     if (!std::isfinite(m->res_alpha)) return fail(MNR_E_INVALID, "motion: non-finite res_alpha");
@@ -172,8 +171,10 @@ void pack_args(RenderArgs& a, const mnr_field* f, const mnr_motion* m, const mnr
       const double t = std::fmin(std::fmax((double)m->res_alpha - k, 0.0), 1.0);
       a.res.win[k] = (float)(0.5 * (1.0 - std::cos(M_PI * t)));
     }
-    a.res.n_omega = 3 * p->n_joints;
-    for (int j = 0; j < 3 * p->n_joints; ++j) a.res.omega[j] = p->axis_angle[j];
+    a.res.n_omega = 3 * p->n_joints;  // Omega: the observed pose theta^o's joint angles (Eq. 11)
+    double om[3 * MNR_MAX_BONES];
+    pose_angles_f64(p, om);
+    for (int j = 0; j < 3 * p->n_joints; ++j) a.res.omega[j] = (float)om[j];
   }
   double G[MNR_MAX_BONES * 12];
   fk_bones_f64(p, G);
@@ -265,12 +266,20 @@ static mnr_status scratch_address(void** out) {
 // ---- binned scatter of the hashed levels' table gradient (scatter.hip) ----
 
 static int hashed_levels(const mnr_field* f) {
+  if (f->encoding == MNR_ENC_FREQ) return 0;
   int n = 0;
   for (int l = 0; l < f->n_levels; ++l) n += level_is_dense(f, l) ? 0 : 1;
   return n;
 }
 
 static uint64_t align256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// Elements of MLP layer k: width[k+1] x width[k], except the frequency-
+// encoded field's W4, whose input is [h3; gamma] (64 x 128).
+static int64_t layer_elems(const mnr_field* f, int k) {
+  if (f->encoding == MNR_ENC_FREQ && k == 3) return 64 * 128;
+  return (int64_t)f->width[k] * f->width[k + 1];
+}
 
 // Carves the caller's scatter workspace; returns its size (0: the field has
 // no hashed level, or the batch or table is too large for the binned path).
@@ -320,19 +329,26 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
   return off;
 }
 
-// Per-sample scratch of the split adjoint (residual motion network): the
-// SPLIT_N arrays of n_rays * ceil(spp / 64) * 64 floats, then 64 floats of
-// layer-1 bias gradient.
-static uint64_t split_layout(const mnr_motion* m, int n_rays, int spp, char* ws, SplitArgs* sp) {
-  if (!m || !m->res_w[0] || n_rays <= 0 || spp <= 0) return 0;
-  const int64_t stride = (int64_t)n_rays * ((spp + 63) / 64) * 64;
+// Per-sample scratch of the split adjoints (residual motion network,
+// frequency-encoded field): the SPLIT_N arrays of n_rays * ceil(spp / 64) *
+// 64 floats, 64 floats of layer-1 bias gradient, and for the
+// frequency-encoded field the saved hidden activations (FREQ_ACT_BYTES per
+// 64-sample chunk).
+static uint64_t split_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
+                             SplitArgs* sp) {
+  const bool res = m && m->res_w[0], freq = f && f->encoding == MNR_ENC_FREQ;
+  if (!(res || freq) || n_rays <= 0 || spp <= 0) return 0;
+  const int64_t chunks = (int64_t)n_rays * ((spp + 63) / 64);
+  const int64_t stride = chunks * 64;
   const uint64_t arrays = align256((uint64_t)SPLIT_N * stride * 4);
+  const uint64_t act = freq ? (uint64_t)chunks * FREQ_ACT_BYTES : 0;
   if (sp) {
     sp->buf = (float*)ws;
     sp->stride = stride;
     sp->dbias = (float*)(ws + arrays);
+    sp->act = act ? (void*)(ws + arrays + 256) : nullptr;
   }
-  return arrays + 256;
+  return arrays + 256 + act;
 }
 
 // The adjoint workspace: the binned scatter's part (when the field has
@@ -341,7 +357,7 @@ static uint64_t split_layout(const mnr_motion* m, int n_rays, int spp, char* ws,
 static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
                                ScatterPlan* p, SplitArgs* sp) {
   const uint64_t a = scatter_layout(f, n_rays, spp, ws, p);
-  const uint64_t b = split_layout(m, n_rays, spp, ws ? ws + a : nullptr, sp);
+  const uint64_t b = split_layout(f, m, n_rays, spp, ws ? ws + a : nullptr, sp);
   return a + b;
 }
 
@@ -349,16 +365,18 @@ static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_ra
 static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
                                 uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp) {
   rec = RecordSink{nullptr, nullptr, nullptr, 0};
-  sp = SplitArgs{nullptr, 0, nullptr};
+  sp = SplitArgs{nullptr, 0, nullptr, nullptr};
   if (!ws) {
     if (m->res_w[0]) return fail(MNR_E_INVALID, "the residual network's adjoint needs the adjoint workspace");
+    if (f->encoding == MNR_ENC_FREQ)
+      return fail(MNR_E_INVALID, "the frequency-encoded field's adjoint needs the adjoint workspace");
     return MNR_OK;
   }
   if ((uintptr_t)ws & 255) return fail(MNR_E_INVALID, "adjoint workspace not 256-byte aligned");
   ScatterPlan pp{};
-  SplitArgs ss{nullptr, 0, nullptr};
+  SplitArgs ss{nullptr, 0, nullptr, nullptr};
   const uint64_t need = adjoint_layout(f, m, n_rays, spp, (char*)ws, &pp, &ss);
-  if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (no hashed level, no residual network, or a batch or table too large)");
+  if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (no hashed level, no residual network, not the frequency-encoded field, or a batch or table too large)");
   if (ws_bytes < need)
     return fail(MNR_E_SHAPE, "adjoint workspace has %llu bytes, needs %llu", (unsigned long long)ws_bytes,
                 (unsigned long long)need);
@@ -378,13 +396,16 @@ static hipError_t adjoint_launches(const RenderArgs& a, const ScatterPlan& plan,
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; };
   if (a.rec.keys) ok(launch_zero(plan.cursor, 256, st));
-  if (a.split.buf) {
+  const bool res = a.res.w[0] != nullptr;
+  if (res) {
     ok(launch_zero(a.split.dbias, 64 * sizeof(float), st));
     ok(launch_res_forward(a, slots, st));
   }
-  ok(launch_render_bwd(a, slots, f->table_dtype, f->mlp_dtype, f->n_layers - 2, st));
+  if (a.f.freq) ok(launch_freq_backward(a, slots, st));
+  else ok(launch_render_bwd(a, slots, f->table_dtype, f->mlp_dtype, f->n_layers - 2, st));
   if (a.rec.keys) ok(launch_binned_scatter(plan, grad_table, st));
-  if (a.split.buf) ok(launch_res_backward(a, slots, st));
+  if (res) ok(launch_res_backward(a, slots, st));
+  if (a.split.buf) ok(launch_skin_backward(a, slots, st));
   return e;
 }
 
@@ -433,7 +454,7 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
 }
 
 uint64_t mnr_adjoint_ws_bytes(const mnr_field* field, const mnr_motion* motion, int32_t n_rays, int32_t spp) {
-  if (!field || field->encoding != MNR_ENC_GRID || validate_field(field) != MNR_OK) return 0;
+  if (!field || validate_field(field) != MNR_OK) return 0;
   return adjoint_layout(field, motion, n_rays, spp, nullptr, nullptr, nullptr);
 }
 
@@ -450,8 +471,9 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
     for (int k = 0; k < 6; ++k)
       if (!grad_res[k]) return fail(MNR_E_INVALID, "backward: null grad_res[%d]", k);
   }
-  if (field->encoding == MNR_ENC_FREQ) return fail(MNR_E_UNSUPPORTED, "backward: no adjoint of the frequency-encoded field");
-  if (!grad_rgba || !grad_table || !grad_w || !grad_weights) return fail(MNR_E_INVALID, "backward: null gradient buffer");
+  const bool freq = field->encoding == MNR_ENC_FREQ;
+  if (!grad_rgba || (!grad_table && !freq) || !grad_w || !grad_weights)
+    return fail(MNR_E_INVALID, "backward: null gradient buffer");
   for (int k = 0; k < field->n_layers; ++k)
     if (!grad_w[k]) return fail(MNR_E_INVALID, "backward: null grad_w[%d]", k);
   if (n_rays == 0) return MNR_OK;
@@ -599,14 +621,13 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   clear_error();
   if (!st || !target) return fail(MNR_E_INVALID, "train_step: null state or target");
   if (mnr_status s = validate_common(field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays, st->rgba)) return s;
-  if (field->encoding == MNR_ENC_FREQ)
-    return fail(MNR_E_UNSUPPORTED, "train_step: no adjoint of the frequency-encoded field");
+  const bool freq = field->encoding == MNR_ENC_FREQ;  // no grid table: only the MLP (and motion) train
   if (motion->res_w[0])
     for (int k = 0; k < 6; ++k)
       if (!st->res_master[k] || !st->res_grad[k] || !st->res_m[k] || !st->res_v[k])
         return fail(MNR_E_INVALID, "train_step: null residual-network state buffer %d", k);
-  if (!st->table_master || !st->table_grad || !st->table_m || !st->table_v || !st->weights_grad || !st->grad_rgba ||
-      !st->loss || !st->t_chunks)
+  if ((!freq && (!st->table_master || !st->table_grad || !st->table_m || !st->table_v)) || !st->weights_grad ||
+      !st->grad_rgba || !st->loss || !st->t_chunks)
     return fail(MNR_E_INVALID, "train_step: null state buffer");
   for (int k = 0; k < field->n_layers; ++k)
     if (!st->w_master[k] || !st->w_grad[k] || !st->w_m[k] || !st->w_v[k])
@@ -615,7 +636,7 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   if (st->train_motion == 2 && !st->logits_grad) return fail(MNR_E_INVALID, "train_step: null logits_grad");
   if (st->train_motion == 1 && (!st->logits || !st->logits_grad || !st->logits_m || !st->logits_v))
     return fail(MNR_E_INVALID, "train_step: null logits state");
-  if (field->table_dtype == MNR_F32 && field->table != st->table_master)
+  if (!freq && field->table_dtype == MNR_F32 && field->table != st->table_master)
     return fail(MNR_E_INVALID, "train_step: an F32 table must be the master copy itself");
   for (int k = 0; k < field->n_layers; ++k)
     if (field->mlp_dtype == MNR_F32 && field->w[k] != st->w_master[k])
@@ -629,14 +650,13 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
     return r;
   hipStream_t s = (hipStream_t)stream;
   const int64_t T = int64_t(1) << field->log2_T;
-  const int64_t n_table = (int64_t)field->n_levels * T * field->n_feat;
+  const int64_t n_table = freq ? 0 : (int64_t)field->n_levels * T * field->n_feat;
   const int64_t n_vox = (int64_t)motion->res * motion->res * motion->res;
   const int64_t n_wc = (int64_t)(motion->n_bones + 1) * n_vox;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; return r == hipSuccess; };
-  ok(launch_zero(st->table_grad, n_table * 4, s));
-  for (int k = 0; k < field->n_layers; ++k)
-    ok(launch_zero(st->w_grad[k], (size_t)field->width[k] * field->width[k + 1] * 4, s));
+  if (n_table) ok(launch_zero(st->table_grad, n_table * 4, s));
+  for (int k = 0; k < field->n_layers; ++k) ok(launch_zero(st->w_grad[k], layer_elems(field, k) * 4, s));
   ok(launch_zero(st->weights_grad, n_wc * 4, s));
   const int64_t n_omega = 3 * (int64_t)motion->n_bones;
   const int64_t res_n[6] = {64 * 32, 64 * 64, 64 * 64, 64 * 96, 3 * 64, 64 * n_omega};  // W1..W5, W_omega
@@ -665,14 +685,15 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
     for (int k = 0; k < 6; ++k)
       ok(launch_adam(st->res_master[k], st->res_grad[k], st->res_m[k], st->res_v[k], res_n[k], st->lr_res, st->beta1,
                      st->beta2, st->eps, st->step, (void*)motion->res_w[k], MNR_BF16, s));
-  ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
-                 st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
-                 field->table_dtype, s));
+  if (n_table)
+    ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
+                   st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
+                   field->table_dtype, s));
   if (field->dense_packed && a.f.dense_mask) ok(launch_pack_dense(a.f, field->table_dtype, s));
   for (int k = 0; k < field->n_layers; ++k)
-    ok(launch_adam(st->w_master[k], st->w_grad[k], st->w_m[k], st->w_v[k],
-                   (int64_t)field->width[k] * field->width[k + 1], st->lr_field, st->beta1, st->beta2, st->eps,
-                   st->step, field->mlp_dtype == MNR_F32 ? nullptr : (void*)field->w[k], field->mlp_dtype, s));
+    ok(launch_adam(st->w_master[k], st->w_grad[k], st->w_m[k], st->w_v[k], layer_elems(field, k), st->lr_field,
+                   st->beta1, st->beta2, st->eps, st->step,
+                   field->mlp_dtype == MNR_F32 ? nullptr : (void*)field->w[k], field->mlp_dtype, s));
   if (st->train_motion) {
     ok(launch_zero(st->logits_grad, n_wc * 4, s));
     ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));

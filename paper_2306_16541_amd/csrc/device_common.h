@@ -99,12 +99,18 @@ enum SplitField {
   SPLIT_L = 9,    // weight sum L; 0 for samples that are not live
   SPLIT_G = 10,   // dL/dx_final (3), then dL/dx_skel
   SPLIT_GL = 13,  // dL/dL
-  SPLIT_N = 14
+  SPLIT_GO = 14,  // dL/d(raw field outputs) (4), frequency-encoded field
+  SPLIT_N = 18
 };
+// Saved hidden activations of the frequency-encoded field's MLP per
+// 64-sample chunk: 4 layers x 4 tiles x 2 halves x 64 lanes of 8 BF16.
+constexpr int FREQ_ACT_VECS = 4 * 4 * 2 * 64;
+constexpr int64_t FREQ_ACT_BYTES = FREQ_ACT_VECS * 16;
 struct SplitArgs {
   float* buf;      // [SPLIT_N][stride], or NULL (fused adjoint)
   int64_t stride;
   float* dbias;    // [64]: sum over samples of dL/d(pre-activation of the residual network's layer 1)
+  void* act;       // frequency-encoded field: FREQ_ACT_BYTES per chunk (chunk = ray row x nchunks + chunk)
 };
 
 struct RenderArgs {
@@ -124,7 +130,7 @@ struct RenderArgs {
   float* grad_weights;
   float* grad_G;                     // optional [n_bones][12]
   RecordSink rec;                    // optional: hashed-level table gradient as records
-  SplitArgs split;                   // split adjoint (residual motion network)
+  SplitArgs split;                   // split adjoint (residual motion network, frequency-encoded field)
   float* grad_res[6];                // residual network: W1..W5, W_omega (FP32)
 };
 

@@ -646,8 +646,17 @@ __device__ __forceinline__ void store_posenc10(char* feat, int lane, const float
   }
 }
 
-// Raw outputs (o0..o3) of the 16 samples of tile nt, lanes 0..15.
-__device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt, int lane) {
+// Hidden activation h (four D-layout tiles) of layer `layer`, tile nt, as
+// the BF16 operands the next layer consumes, into a chunk's save area.
+__device__ __forceinline__ void save_act(bf16x8* save, int layer, int nt, int lane, const f4* h) {
+  save[(layer * 4 + nt) * 128 + lane] = pack_bf16(h[0], h[1]);
+  save[(layer * 4 + nt) * 128 + 64 + lane] = pack_bf16(h[2], h[3]);
+}
+
+// Raw outputs (o0..o3) of the 16 samples of tile nt, lanes 0..15.  SAVE:
+// also store the four hidden activations for the adjoint.
+template <bool SAVE = false>
+__device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt, int lane, bf16x8* save = nullptr) {
   f4 xa[4], xb[4], h[4], h2[4];
   load_input<MNR_BF16>(feat, nt, lane, xa);
   load_input<MNR_BF16>(feat + 4096, nt, lane, xb);
@@ -655,14 +664,18 @@ __device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt
   mma_layer<MNR_BF16, 4, 4>(wl, g, h, lane);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) h[mt] = relu4(h[mt]);
+  if constexpr (SAVE) save_act(save, 0, nt, lane, h);
   mma_layer<MNR_BF16, 4, 4>(wl + FreqShape::o2, h, h2, lane);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+  if constexpr (SAVE) save_act(save, 1, nt, lane, h2);
   mma_layer<MNR_BF16, 4, 4>(wl + FreqShape::o3, h2, h, lane);
   const f4 cat[8] = {relu4(h[0]), relu4(h[1]), relu4(h[2]), relu4(h[3]), g[0], g[1], g[2], g[3]};
+  if constexpr (SAVE) save_act(save, 2, nt, lane, cat);
   mma_layer<MNR_BF16, 4, 8>(wl + FreqShape::o4, cat, h2, lane);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+  if constexpr (SAVE) save_act(save, 3, nt, lane, h2);
   f4 o[4];
   mma_layer<MNR_BF16, 1, 4>(wl + FreqShape::o5, h2, o, lane);
   return o[0];

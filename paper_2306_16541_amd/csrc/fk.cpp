@@ -141,6 +141,56 @@ void fk_bones_f64(const mnr_pose* pose, double* G /* [n][12] */) {
   fk_t<double>(pose, w, pose->delta ? dl : nullptr, G);
 }
 
+// Axis-angle of a rotation (principal branch: angle theta in [0, pi]).
+// With R = cos(theta) I + sin(theta) [a]x + (1 - cos(theta)) a a^T, the
+// skew part gives v = sin(theta) a and the trace cos(theta); theta =
+// atan2(|v|, cos(theta)).  Near theta = pi, where v vanishes, the axis
+// comes from the symmetric part, a a^T = (S - cos(theta) I) /
+// (1 - cos(theta)), its sign from v.
+static void rotation_log(const double R[9], double w[3]) {
+  const double v[3] = {0.5 * (R[7] - R[5]), 0.5 * (R[2] - R[6]), 0.5 * (R[3] - R[1])};
+  const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+  const double s = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double th = std::atan2(s, c);
+  if (th < 1e-6) {  // theta / sin(theta) = 1 + theta^2 / 6 + O(theta^4)
+    for (int i = 0; i < 3; ++i) w[i] = v[i] * (1.0 + th * th / 6.0);
+    return;
+  }
+  if (c > -0.9) {
+    for (int i = 0; i < 3; ++i) w[i] = v[i] * (th / s);
+    return;
+  }
+  double M[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = (0.5 * (R[3 * i + j] + R[3 * j + i]) - (i == j ? c : 0.0)) / (1.0 - c);
+  int k = 0;
+  for (int i = 1; i < 3; ++i)
+    if (M[4 * i] > M[4 * k]) k = i;
+  const double ak = std::sqrt(M[4 * k]);
+  double a[3];
+  for (int j = 0; j < 3; ++j) a[j] = M[3 * k + j] / ak;
+  const double dot = a[0] * v[0] + a[1] * v[1] + a[2] * v[2];
+  const double sg = dot < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < 3; ++i) w[i] = sg * th * a[i];
+}
+
+void pose_angles_f64(const mnr_pose* pose, double* omega) {
+  const int n = pose->n_joints;
+  for (int j = 0; j < n; ++j) {
+    double w[3] = {pose->axis_angle[3 * j], pose->axis_angle[3 * j + 1], pose->axis_angle[3 * j + 2]};
+    if (!pose->delta) {
+      for (int i = 0; i < 3; ++i) omega[3 * j + i] = w[i];
+      continue;
+    }
+    const double d[3] = {pose->delta[3 * j], pose->delta[3 * j + 1], pose->delta[3 * j + 2]};
+    double Rw[9], Rd[9], R[9];
+    rodrigues<double>(w, Rw);
+    rodrigues<double>(d, Rd);
+    matmul3<double>(Rd, Rw, R);
+    rotation_log(R, omega + 3 * j);
+  }
+}
+
 // Refiner layers in double precision; hidden activations kept for the adjoint.
 static constexpr int MAX_REFINER_WIDTH = 1024;
 

@@ -1,0 +1,331 @@
+// Adjoint of the paper's own canonical field (Sec. 4.4, Eq. 13, Fig. 9):
+// c, sigma = MLP_nerf(gamma(x_final)) with the 10-band positional encoding
+// gamma and the skip of gamma into layer 4 (training, Sec. 5.2).
+//
+// The forward weights (42 KiB BF16), their transposes (44 KiB) and FP32
+// block sums of the weight gradients (81 KiB) do not fit one kernel's LDS,
+// so the adjoint is split like the residual network's, handing per-sample
+// values through the split scratch (SplitArgs):
+//   freq_save_kernel  per ray, chunks last to first: the sample's query
+//                     point (inverse LBS here, or x_final from the residual
+//                     network's forward kernel), gamma, the skip MLP on
+//                     MFMA with its four hidden activations saved (BF16, the
+//                     values the next layer consumed), and the compositing
+//                     adjoint, storing dL/d(outputs) and dL/dL;
+//   freq_bwd_kernel   per 16-sample tile, the MLP's adjoint from the saved
+//                     activations: dL/dW1..W5 (block sums in LDS) and
+//                     dL/dx_final = (d gamma / dx)^T dL/dgamma, where
+//                     dL/dgamma collects the first layer's and the skip's
+//                     terms;
+// then the residual network's adjoint (if it is on) and the skinning
+// adjoint (res_bwd.hip).
+#include "adjoint_device.h"
+#include "kernels.h"
+
+namespace mnr {
+
+constexpr int FREQ_SAVE_WAVES = 4;
+constexpr int FREQ_BWD_WAVES = 4;
+
+// Transposed weights as A operands of dX = W^T dY (BF16 fragments):
+// W1^T, W2^T, W3^T (64 x 64), W4^T (128 x 64: h3's rows, then gamma's),
+// W5^T (64 x 4, padded to 32 columns).
+struct FreqTShape {
+  static constexpr int FRAG = 64 * 16;
+  static constexpr int T1 = 4 * 2 * FRAG, T2 = 4 * 2 * FRAG, T3 = 4 * 2 * FRAG, T4 = 8 * 2 * FRAG, T5 = 4 * 1 * FRAG;
+  static constexpr int o2 = T1, o3 = o2 + T2, o4 = o3 + T3, o5 = o4 + T4;
+  static constexpr int bytes() { return o5 + T5; }
+};
+
+// Block sums of the weight gradients (FP32, row-major with rows padded by
+// 4 floats for conflict-free LDS atomics): W1, W2, W3 [64][64],
+// W4 [64][128], W5 [4][64].
+struct FreqGrad {
+  static constexpr int L1 = 68, L2 = 68, L3 = 68, L4 = 132, L5 = 68;  // row strides
+  static constexpr int o2 = 64 * L1, o3 = o2 + 64 * L2, o4 = o3 + 64 * L3, o5 = o4 + 64 * L4;
+  static constexpr int floats() { return o5 + 4 * L5; }
+};
+
+constexpr int FREQ_SAVE_WAVE_BYTES = FreqShape::feat_bytes_per_wave() + 64 * 16;  // gamma + output buffer
+constexpr int FREQ_SAVE_LDS = FreqShape::bytes() + FREQ_SAVE_WAVES * FREQ_SAVE_WAVE_BYTES;
+constexpr int FREQ_BWD_LDS = FreqTShape::bytes() + FreqGrad::floats() * 4 + FREQ_BWD_WAVES * RES_TB_BYTES;
+static_assert(FREQ_SAVE_LDS <= 80 * 1024, "two forward blocks per compute unit");
+static_assert(FREQ_BWD_LDS <= 160 * 1024, "LDS of the frequency field's adjoint");
+
+// ---- 1. forward with saved activations, compositing adjoint -----------------
+
+template <bool RES>
+__global__ void __launch_bounds__(64 * FREQ_SAVE_WAVES) freq_save_kernel(const RenderArgs a, int n_slots) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* wl = lds;
+  char* feat = lds + FreqShape::bytes() + wave * FREQ_SAVE_WAVE_BYTES;
+  f4* obuf = (f4*)(feat + FreqShape::feat_bytes_per_wave());
+  stage_freq(wl, a.f);
+  __syncthreads();
+  const int nchunks = (a.r.spp + 63) >> 6;
+  float* sb = a.split.buf;
+  const int64_t ss = a.split.stride;
+  for (int slot = blockIdx.x * FREQ_SAVE_WAVES + wave; slot < n_slots; slot += gridDim.x * FREQ_SAVE_WAVES) {
+    int orow, n_done;
+    RaySetup rs;
+    if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
+    const f4 gout = *(const f4*)(a.grad_rgba + (size_t)orow * 4);
+    float Sc[4] = {a.r.bg[0], a.r.bg[1], a.r.bg[2], 0.f};  // S after the last processed sample
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    for (int ch = nchunks - 1; ch >= 0; --ch) {
+      const float T0 = tc[ch];
+      if (T0 < 0.f || ch * 64 >= n_done) continue;  // not reached by the forward pass
+      const int i = ch * 64 + lane;
+      const bool valid = i < n_done;
+      const int64_t cj = (int64_t)orow * nchunks + ch;
+      const int64_t sj = cj * 64 + lane;
+      SampleState st;
+      if constexpr (RES) {  // x_final and L from the residual network's forward kernel
+        st.xs[0] = sb[SPLIT_XF * ss + sj];
+        st.xs[1] = sb[(SPLIT_XF + 1) * ss + sj];
+        st.xs[2] = sb[(SPLIT_XF + 2) * ss + sj];
+        st.L = valid ? sb[SPLIT_L * ss + sj] : 0.f;
+      } else {
+        const float s = ((float)i + sample_jitter(a.r, orow, i)) * rs.delta;
+        st.x[0] = fmaf(s, rs.d[0], rs.p0[0]);
+        st.x[1] = fmaf(s, rs.d[1], rs.p0[1]);
+        st.x[2] = fmaf(s, rs.d[2], rs.p0[2]);
+        st.L = 0.f;
+        st.xs[0] = st.xs[1] = st.xs[2] = 0.f;
+        if (valid) {
+          warp_sample(a.m, a.G, st.x, st.xs, st.L);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            sb[(SPLIT_X + q) * ss + sj] = st.x[q];
+            sb[(SPLIT_XS + q) * ss + sj] = st.xs[q];
+            sb[(SPLIT_XF + q) * ss + sj] = st.xs[q];
+          }
+          sb[SPLIT_L * ss + sj] = st.L > 0.f ? st.L : 0.f;
+        }
+      }
+      st.live = valid && st.L > 0.f;
+      const uint64_t live_mask = __ballot(st.live);
+      if (live_mask == 0) continue;  // alpha' = 0 everywhere: S passes through unchanged
+      store_posenc10(feat, lane, st.xs, st.live);
+      wave_sync_lds();
+      bf16x8* act = (bf16x8*)a.split.act + cj * FREQ_ACT_VECS;
+#pragma unroll 1
+      for (int nt = 0; nt < 4; ++nt) {
+        f4 o = {0.f, 0.f, 0.f, 0.f};
+        if ((live_mask >> (16 * nt)) & 0xFFFFull) o = freq_tile<true>(wl, feat, nt, lane, act);
+        if (lane < 16) obuf[nt * 16 + lane] = o;
+      }
+      wave_sync_lds();
+      const f4 out = obuf[lane];
+      float g_o[4], g_L;
+      composite_adjoint(T0, rs.delta, out, st.L, st.live, gout, Sc, g_o, g_L);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sb[(SPLIT_GO + q) * ss + sj] = g_o[q];
+        sb[SPLIT_GL * ss + sj] = st.live ? g_L : 0.f;
+      }
+      wave_sync_lds();
+    }
+  }
+}
+
+// ---- 2. the skip MLP's adjoint ----------------------------------------------
+
+// gamma of sample x at the 16 inputs k = 16 t + 4 g + e (t, e = 0..3) that
+// lane group g holds in the D layout, with d gamma_k / d x_q(k): value, the
+// derivative and its axis.  The arguments of sincospi are formed as the
+// forward pass forms them, so the values round to the same BF16 operands.
+__device__ __forceinline__ void posenc10_lane(const float x[3], int g, f4 (&val)[4], float (&der)[16],
+                                              int (&axis)[16]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 16 * t + 4 * g + e, n = 4 * t + e;
+      float v = 0.f, d = 0.f;
+      int q = 0;
+      if (k < 3) {
+        q = k;
+        v = x[0];
+        if (k == 1) v = x[1];
+        if (k == 2) v = x[2];
+        d = 1.f;
+      } else if (k < 63) {
+        const int band = (k - 3) / 6, r = (k - 3) - 6 * ((k - 3) / 6);
+        q = r < 3 ? r : r - 3;
+        const float xq = q == 0 ? x[0] : (q == 1 ? x[1] : x[2]);
+        const float f = (float)(1 << band);
+        float sv, cv;
+        sincospif(f * xq, &sv, &cv);
+        v = r < 3 ? sv : cv;
+        d = (r < 3 ? cv : -sv) * (f * 3.14159265358979f);
+      }
+      val[t][e] = v;
+      der[n] = d;
+      axis[n] = q;
+    }
+}
+
+__device__ __forceinline__ void load_act(const bf16x8* act, int layer, int nt, int lane, f4 (&h)[4]) {
+  const bf16x8 p = act[(layer * 4 + nt) * 128 + lane], q = act[(layer * 4 + nt) * 128 + 64 + lane];
+  h[0] = f4{(float)p[0], (float)p[1], (float)p[2], (float)p[3]};
+  h[1] = f4{(float)p[4], (float)p[5], (float)p[6], (float)p[7]};
+  h[2] = f4{(float)q[0], (float)q[1], (float)q[2], (float)q[3]};
+  h[3] = f4{(float)q[4], (float)q[5], (float)q[6], (float)q[7]};
+}
+
+// Four waves per block share the transposed weights and the gradient sums;
+// each wave takes rays in turn and, per 64-sample chunk, its live 16-sample
+// tiles.  Lane c + 16 g works on sample 16 nt + c.
+__global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const RenderArgs a, int n_slots) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  char* rt = lds;
+  float* dw = (float*)(rt + FreqTShape::bytes());
+  __bf16* tb = (__bf16*)((char*)(dw + FreqGrad::floats()) + wave * RES_TB_BYTES);
+  stage_t(rt, (const __bf16*)a.f.w[0], HIDDEN, 64, HIDDEN);
+  stage_t(rt + FreqTShape::o2, (const __bf16*)a.f.w[1], HIDDEN, HIDDEN, HIDDEN);
+  stage_t(rt + FreqTShape::o3, (const __bf16*)a.f.w[2], HIDDEN, HIDDEN, HIDDEN);
+  stage_t(rt + FreqTShape::o4, (const __bf16*)a.f.w[3], HIDDEN, 2 * HIDDEN, HIDDEN);
+  stage_t(rt + FreqTShape::o5, (const __bf16*)a.f.w[4], 4, HIDDEN, 32);
+  for (int i = threadIdx.x; i < FreqGrad::floats(); i += blockDim.x) dw[i] = 0.f;
+  __syncthreads();
+  const int nchunks = (a.r.spp + 63) >> 6;
+  float* sb = a.split.buf;
+  const int64_t ss = a.split.stride;
+  const int c = lane & 15, g = lane >> 4;
+  const f4 z4 = {0.f, 0.f, 0.f, 0.f};
+  for (int slot = blockIdx.x * FREQ_BWD_WAVES + wave; slot < n_slots; slot += gridDim.x * FREQ_BWD_WAVES) {
+    int orow, n_done;
+    RaySetup rs;
+    if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
+    const float* tc = a.t_chunks + (size_t)orow * (nchunks + 1);
+    for (int ch = 0; ch < nchunks && ch * 64 < n_done; ++ch) {
+      if (tc[ch] < 0.f) continue;
+      const int i = ch * 64 + lane;
+      const int64_t cj = (int64_t)orow * nchunks + ch;
+      const int64_t sj = cj * 64 + lane;
+      const bool live = i < n_done && sb[SPLIT_L * ss + sj] > 0.f;
+      const uint64_t live_mask = __ballot(live);
+      if (live_mask == 0) continue;
+      float xf[3] = {0.f, 0.f, 0.f}, go[4] = {0.f, 0.f, 0.f, 0.f};
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) xf[q] = sb[(SPLIT_XF + q) * ss + sj];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) go[q] = sb[(SPLIT_GO + q) * ss + sj];
+      }
+      const bf16x8* act = (const bf16x8*)a.split.act + cj * FREQ_ACT_VECS;
+#pragma unroll 1
+      for (int nt = 0; nt < 4; ++nt) {
+        if (!((live_mask >> (16 * nt)) & 0xFFFFull)) continue;
+        const int sl = 16 * nt + c;  // the lane's sample
+        const bool slive = (live_mask >> sl) & 1ull;
+        float x[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) x[q] = __shfl(xf[q], sl, WAVE);
+        f4 gam[4];
+        float der[16];
+        int axis[16];
+        posenc10_lane(x, g, gam, der, axis);
+        if (!slive)  // the forward pass fed zeros for samples that are not live
+#pragma unroll
+          for (int t = 0; t < 4; ++t) gam[t] = z4;
+        f4 h1[4], h2[4], h3[4], h4[4];
+        load_act(act, 0, nt, lane, h1);
+        load_act(act, 1, nt, lane, h2);
+        load_act(act, 2, nt, lane, h3);
+        load_act(act, 3, nt, lane, h4);
+        // output layer: rows 0..3 of sample sl are dL/do
+        f4 d5[2] = {z4, z4};
+        {
+          const float q0 = __shfl(go[0], sl, WAVE), q1 = __shfl(go[1], sl, WAVE);
+          const float q2 = __shfl(go[2], sl, WAVE), q3 = __shfl(go[3], sl, WAVE);
+          if (g == 0) d5[0] = f4{q0, q1, q2, q3};
+        }
+        f4 tmp[8], d[4], dgam[4];
+        dw_tile<1, 4>(tb, d5, h4, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
+        mm_t<4, 1>(rt + FreqTShape::o5, d5, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
+        // layer 4: input [h3; gamma]
+        dw_tile<4, 4>(tb, d, h3, dw + FreqGrad::o4, HIDDEN, FreqGrad::L4, lane);
+        dw_tile<4, 4>(tb, d, gam, dw + FreqGrad::o4 + HIDDEN, HIDDEN, FreqGrad::L4, lane);
+        mm_t<8, 2>(rt + FreqTShape::o4, d, tmp, lane);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dgam[t] = tmp[4 + t];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
+        // layer 3
+        dw_tile<4, 4>(tb, d, h2, dw + FreqGrad::o3, HIDDEN, FreqGrad::L3, lane);
+        mm_t<4, 2>(rt + FreqTShape::o3, d, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
+        // layer 2
+        dw_tile<4, 4>(tb, d, h1, dw + FreqGrad::o2, HIDDEN, FreqGrad::L2, lane);
+        mm_t<4, 2>(rt + FreqTShape::o2, d, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
+        // layer 1: input gamma
+        dw_tile<4, 4>(tb, d, gam, dw, HIDDEN, FreqGrad::L1, lane);
+        mm_t<4, 2>(rt, d, tmp, lane);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dgam[t] += tmp[t];
+        // dL/dx_final of sample sl: the lane's 16 inputs, then the 4 lane groups
+        float gx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int n = 0; n < 16; ++n) {
+          const float v = dgam[n >> 2][n & 3] * der[n];
+          gx[0] += axis[n] == 0 ? v : 0.f;
+          gx[1] += axis[n] == 1 ? v : 0.f;
+          gx[2] += axis[n] == 2 ? v : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          gx[q] += __shfl_xor(gx[q], 16, WAVE);
+          gx[q] += __shfl_xor(gx[q], 32, WAVE);
+        }
+        if (g == 0 && slive)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) sb[(SPLIT_G + q) * ss + cj * 64 + sl] = gx[q];
+      }
+    }
+  }
+  __syncthreads();
+  // flush: element k of layer l (row-major, K columns) sits at row k / K of
+  // the padded block
+  const int cols[5] = {64, 64, 64, 128, 64}, rows[5] = {64, 64, 64, 64, 4};
+  const int ld[5] = {FreqGrad::L1, FreqGrad::L2, FreqGrad::L3, FreqGrad::L4, FreqGrad::L5};
+  const int off[5] = {0, FreqGrad::o2, FreqGrad::o3, FreqGrad::o4, FreqGrad::o5};
+#pragma unroll
+  for (int l = 0; l < 5; ++l)
+    for (int k = threadIdx.x; k < rows[l] * cols[l]; k += blockDim.x) {
+      const int r = k / cols[l];
+      const float v = dw[off[l] + r * ld[l] + (k - r * cols[l])];
+      if (v != 0.f) unsafeAtomicAdd(a.grad_w[l] + k, v);
+    }
+}
+
+template <bool RES>
+static void launch_save(const RenderArgs& a, int n_slots, hipStream_t st) {
+  static PersistentGrid pg;
+  auto kern = freq_save_kernel<RES>;
+  const int mb = persistent_blocks(kern, 64 * FREQ_SAVE_WAVES, FREQ_SAVE_LDS, pg);
+  const int need = (n_slots + FREQ_SAVE_WAVES - 1) / FREQ_SAVE_WAVES;
+  hipLaunchKernelGGL(kern, dim3(need < mb ? (need > 0 ? need : 1) : mb), dim3(64 * FREQ_SAVE_WAVES), FREQ_SAVE_LDS,
+                     st, a, n_slots);
+}
+
+hipError_t launch_freq_backward(const RenderArgs& a, int n_slots, hipStream_t st) {
+  if (a.res.w[0]) launch_save<true>(a, n_slots, st);
+  else launch_save<false>(a, n_slots, st);
+  static PersistentGrid pg;
+  const int mb = persistent_blocks(freq_bwd_kernel, 64 * FREQ_BWD_WAVES, FREQ_BWD_LDS, pg);
+  const int need = (n_slots + FREQ_BWD_WAVES - 1) / FREQ_BWD_WAVES;
+  hipLaunchKernelGGL(freq_bwd_kernel, dim3(need < mb ? (need > 0 ? need : 1) : mb), dim3(64 * FREQ_BWD_WAVES),
+                     FREQ_BWD_LDS, st, a, n_slots);
+  return hipGetLastError();
+}
+
+}  // namespace mnr

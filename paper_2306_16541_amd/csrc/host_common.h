@@ -11,6 +11,9 @@ void clear_error();
 mnr_status fail(mnr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 mnr_status validate_pose(const mnr_pose* pose);
 void fk_bones_f64(const mnr_pose* pose, double* G);
+// Joint angles of the observed pose [3n]: axis_angle, or with the refiner's
+// adjustment the axis-angle of R(delta_j) R(axis_angle_j) (angle <= pi).
+void pose_angles_f64(const mnr_pose* pose, double* omega);
 
 struct RenderArgs;
 struct FieldArgs;

@@ -47,6 +47,8 @@ hipError_t launch_render_bwd(const RenderArgs& a, int n_slots, mnr_dtype table_d
 // and after it the residual network's and the skinning adjoints.
 hipError_t launch_res_forward(const RenderArgs& a, int n_slots, hipStream_t st);
 hipError_t launch_res_backward(const RenderArgs& a, int n_slots, hipStream_t st);
+hipError_t launch_skin_backward(const RenderArgs& a, int n_slots, hipStream_t st);
+hipError_t launch_freq_backward(const RenderArgs& a, int n_slots, hipStream_t st);
 
 // Server tick: render the (slot, tile) items of wt with the requests' descriptors.
 hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,

@@ -3,16 +3,14 @@
 // One wavefront per ray, walking the chunks the forward pass processed from
 // last to first.  Nothing per-sample is stored by the forward pass: each
 // chunk is recomputed (sample, inverse LBS, encoding, MLP) and then
-//   1. compositing adjoint (Eq. 3 with alpha' = alpha * min(L, 1)): with
-//      S_i = alpha'_i c_i + (1 - alpha'_i) S_{i+1} (S after the last
-//      processed sample = background colour; the opacity channel uses
-//      c = 1, background 0), dC/dc_i = T_i alpha'_i and
-//      dC/dalpha'_i = T_i (c_i - S_{i+1}).  S_{i+1} comes from a reverse
-//      affine scan across the wave (division-free), T_i from the saved
-//      chunk-start transmittance and a forward prefix product;
+//   1. compositing adjoint (Eq. 3 with alpha' = alpha * min(L, 1),
+//      composite_adjoint): dL/d(outputs) and dL/dL from the saved
+//      chunk-start transmittance, S after the last processed sample being
+//      the background colour (opacity 0);
 //   2. MLP adjoint on MFMA, 16 samples at a time: activations recomputed
 //      with the forward weights, dX = W^T dY with transposed weight
-//      fragments, dW = dY X^T accumulated per block in LDS float atomics;
+//      fragments, dW = dY X^T accumulated on the MFMAs in the wave's
+//      registers and added to the block's LDS sums at the end;
 //   3. encoding adjoint: scatter-add into the table gradient and the
 //      encoding's spatial derivative back to the skinned point x_skel;
 //      consecutive samples in the same cell are summed in the wave first;
@@ -37,7 +35,12 @@ struct BwdShape {
   static constexpr int bytes_hidden_t() { return 4 * KG64 * S::FRAG; }
   static constexpr int bytes_out_t() { return 4 * 1 * S::FRAG; }
   static constexpr int bytes_t(int nhh) { return bytes_first_t() + nhh * bytes_hidden_t() + bytes_out_t(); }
-  static constexpr int dw_floats(int nhh) { return HIDDEN * IN_FEAT + nhh * HIDDEN * HIDDEN + 4 * HIDDEN; }
+  // Block sums of dW in LDS, rows padded by 4 floats: the lanes of one
+  // atomic (rows 4g + j, columns c of a 16 x 16 tile) then hit distinct
+  // banks instead of four lanes per bank.
+  static constexpr int LD_FIRST = IN_FEAT + 4, LD_HID = HIDDEN + 4;
+  static constexpr int off_hidden(int l) { return HIDDEN * LD_FIRST + l * HIDDEN * LD_HID; }
+  static constexpr int dw_floats(int nhh) { return off_hidden(nhh) + 4 * LD_HID; }
   static constexpr int tbuf_bytes() { return 2 * 64 * 16 * (int)sizeof(TB); }
   static constexpr int wave_bytes() { return S::feat_bytes_per_wave() + 64 * IN_FEAT * 4 + tbuf_bytes(); }
   static constexpr int dg_floats() { return MNR_MAX_BONES * 12; }  // block sums of dL/dG
@@ -76,11 +79,23 @@ __device__ __forceinline__ f4 relu_mask(f4 d, f4 h) {
   return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
 }
 
-// dW[M_out x K_in] += dY (MT tiles, D layout) x X^T (NT tiles, D layout), over
-// the 16 samples of one tile, accumulated into LDS with float atomics.
+// A wave's running sums of dW in registers, D layout: tile (mt, kt),
+// element j of lane c + 16 g is dW[16 mt + 4 g + j][16 kt + c].  They
+// accumulate on the MFMAs across every tile the wave processes and reach
+// the block's LDS sums once, at the end: float atomics on LDS cost more
+// than the products themselves.
+template <int P, int NHH>
+struct DwAcc {
+  f4 out[1][4];        // output layer, 4 x 64
+  f4 hid[NHH][4][4];   // hidden layers, 64 x 64
+  f4 first[4][2];      // first layer, 64 x 32
+};
+
+// acc += dY (MT tiles, D layout) x X^T (NT tiles, D layout) over the 16
+// samples of one tile, both operands transposed through the wave's buffer.
 template <int P, int MT, int NT>
 __device__ __forceinline__ void accumulate_dw(typename BwdShape<P>::TB* tb, const f4 (&d)[4], const f4 (&h)[4],
-                                              float* dw, int M_out, int K_in, int lane) {
+                                              f4 (&acc)[MT][NT], int lane) {
   using TB = typename BwdShape<P>::TB;
   TB* td = tb;            // [64 neurons][16 samples]
   TB* th = tb + 64 * 16;  // [64 neurons][16 samples]
@@ -98,12 +113,12 @@ __device__ __forceinline__ void accumulate_dw(typename BwdShape<P>::TB* tb, cons
   for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
     for (int kt = 0; kt < NT; ++kt) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      f4 a = acc[mt][kt];
       if constexpr (P == MNR_F32) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(td[(16 * mt + c) * 16 + 4 * s + g],
-                                                     th[(16 * kt + c) * 16 + 4 * s + g], acc, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x4f32(td[(16 * mt + c) * 16 + 4 * s + g],
+                                                   th[(16 * kt + c) * 16 + 4 * s + g], a, 0, 0, 0);
       } else {
         bf16x8 av, bv;
         if (g < 2) {
@@ -113,24 +128,38 @@ __device__ __forceinline__ void accumulate_dw(typename BwdShape<P>::TB* tb, cons
 #pragma unroll
           for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, a, 0, 0, 0);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 16 * mt + 4 * g + j;
-        if (row < M_out) atomicAdd(dw + row * K_in + 16 * kt + c, acc[j]);
-      }
+      acc[mt][kt] = a;
     }
   }
   wave_sync_lds();
 }
 
+// Add a wave's register sums (MT x NT tiles, rows < M_out) into the
+// block's LDS sums (row stride ld).
+template <int MT, int NT>
+__device__ __forceinline__ void flush_dw(const f4 (&acc)[MT][NT], float* dw, int M_out, int ld, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * mt + 4 * g + j;
+        if (row < M_out) atomicAdd(dw + row * ld + 16 * kt + c, acc[mt][kt][j]);
+      }
+}
+
 // MLP adjoint for sample tile nt.  dout: output-layer gradient in D layout
-// (lanes 0..15 hold d/do of sample 16nt + lane).  Writes d/dfeature of the
-// 16 samples into dfeat[sample][32].
+// (lanes 0..15 hold d/do of sample 16nt + lane).  Adds the tile's dW to the
+// wave's register sums and writes d/dfeature of the 16 samples into
+// dfeat[sample][32].
 template <int P, int NHH>
 __device__ __forceinline__ void mlp_tile_backward(const char* wl, const char* wt, const char* feat, int nt, int lane,
-                                                  f4 dout, typename BwdShape<P>::TB* tb, float* dw, float* dfeat) {
+                                                  f4 dout, typename BwdShape<P>::TB* tb, DwAcc<P, NHH>& acc,
+                                                  float* dfeat) {
   using S = MlpShape<P>;
   using B = BwdShape<P>;
   f4 x[4], hid[NHH + 1][4], tmp[4];
@@ -144,26 +173,23 @@ __device__ __forceinline__ void mlp_tile_backward(const char* wl, const char* wt
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) hid[l + 1][mt] = relu4(tmp[mt]);
   }
-  float* dw_first = dw;
-  float* dw_hidden = dw + HIDDEN * IN_FEAT;
-  float* dw_out = dw_hidden + NHH * HIDDEN * HIDDEN;
   const f4 z = {0.f, 0.f, 0.f, 0.f};
   f4 d[4] = {dout, z, z, z};
   // output layer
-  accumulate_dw<P, 1, 4>(tb, d, hid[NHH], dw_out, 4, HIDDEN, lane);
+  accumulate_dw<P, 1, 4>(tb, d, hid[NHH], acc.out, lane);
   mma_layer<P, 4, B::KT_OUTT>(wt + B::bytes_first_t() + NHH * B::bytes_hidden_t(), d, tmp, lane);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask(tmp[mt], hid[NHH][mt]);
   // hidden layers, last to first
 #pragma unroll
   for (int l = NHH - 1; l >= 0; --l) {
-    accumulate_dw<P, 4, 4>(tb, d, hid[l], dw_hidden + l * HIDDEN * HIDDEN, HIDDEN, HIDDEN, lane);
+    accumulate_dw<P, 4, 4>(tb, d, hid[l], acc.hid[l], lane);
     mma_layer<P, 4, 4>(wt + B::bytes_first_t() + l * B::bytes_hidden_t(), d, tmp, lane);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask(tmp[mt], hid[l][mt]);
   }
   // first layer
-  accumulate_dw<P, 4, 2>(tb, d, x, dw_first, HIDDEN, IN_FEAT, lane);
+  accumulate_dw<P, 4, 2>(tb, d, x, acc.first, lane);
   mma_layer<P, 2, 4>(wt, d, tmp, lane);
   const int c = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -217,6 +243,22 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   const int nb_min = (gridDim.x >> 3) > 0 ? (gridDim.x >> 3) : 1;
   const int iters = (((tiles + 7) >> 3) * 256 + nb_min * NW - 1) / (nb_min * NW);
 
+  DwAcc<P, NHH> acc;
+  {
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) acc.out[0][kt] = z;
+#pragma unroll
+    for (int l = 0; l < NHH; ++l)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) acc.hid[l][mt][kt] = z;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) acc.first[mt][kt] = z;
+  }
   int q = blockIdx.x & 7, tried = 0;
   for (int it = 0;; ++it) {
     int slot;
@@ -263,53 +305,8 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       if (live_mask == 0) continue;  // alpha' = 0 everywhere: S passes through unchanged
 
       // ---- 1. compositing adjoint -------------------------------------------------
-      const float sigma = fmaxf(out[3], 0.f);
-      const float alpha = -expm1f(-sigma * rs.delta);
-      const float mL = fminf(st.L, 1.f);
-      const float ap = st.live ? alpha * mL : 0.f;
-      float c[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) c[k] = 1.f / (1.f + expf(-out[k]));
-      const float incl = wave_prefix_prod(1.f - ap);
-      float excl = shfl_up(incl, 1);
-      if (lane == 0) excl = 1.f;
-      const float Ti = T0 * excl;
-      // reverse affine scan: S_i = b_i + a_i S_{i+1}
-      float A_ = 1.f - ap;
-      float Bv[4] = {ap * c[0], ap * c[1], ap * c[2], ap};
-#pragma unroll
-      for (int k = 1; k < WAVE; k <<= 1) {
-        const float Ak = shfl_down(A_, k);
-        float Bk[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Bk[q] = shfl_down(Bv[q], k);
-        if (lane + k < WAVE) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) Bv[q] = fmaf(A_, Bk[q], Bv[q]);
-          A_ *= Ak;
-        }
-      }
-      float Si[4], Snext[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Si[q] = fmaf(A_, Sc[q], Bv[q]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        Snext[q] = shfl_down(Si[q], 1);
-        if (lane == WAVE - 1) Snext[q] = Sc[q];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Sc[q] = __shfl(Si[q], 0, WAVE);
-      float g_ap = gout[3] * Ti * (1.f - Snext[3]);
-      float g_o[4];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        g_ap += gout[k] * Ti * (c[k] - Snext[k]);
-        g_o[k] = gout[k] * Ti * ap * c[k] * (1.f - c[k]);
-      }
-      const float g_sigma = g_ap * mL * rs.delta * (1.f - alpha);
-      g_o[3] = out[3] > 0.f ? g_sigma : 0.f;
-      const float g_L = (st.L < 1.f) ? g_ap * alpha : 0.f;
-      if (!st.live) g_o[0] = g_o[1] = g_o[2] = g_o[3] = 0.f;
+      float g_o[4], g_L;
+      composite_adjoint(T0, rs.delta, out, st.L, st.live, gout, Sc, g_o, g_L);
 
       // ---- 2. MLP adjoint -----------------------------------------------------------
       f4* gobuf = (f4*)dfeat;
@@ -320,7 +317,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       for (int nt = 0; nt < 4; ++nt) dout[nt] = (lane < 16) ? gobuf[nt * 16 + lane] : f4{0.f, 0.f, 0.f, 0.f};
       wave_sync_lds();
 #pragma unroll 1
-      for (int nt = 0; nt < 4; ++nt) mlp_tile_backward<P, NHH>(wl, wt, feat, nt, lane, dout[nt], tb, dw, dfeat);
+      for (int nt = 0; nt < 4; ++nt) mlp_tile_backward<P, NHH>(wl, wt, feat, nt, lane, dout[nt], tb, acc, dfeat);
       wave_sync_lds();
 
       // ---- 3. encoding adjoint ------------------------------------------------------
@@ -441,6 +438,10 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       wave_sync_lds();
     }
   }
+  flush_dw(acc.out, dw + B::off_hidden(NHH), 4, B::LD_HID, lane);
+#pragma unroll
+  for (int l = 0; l < NHH; ++l) flush_dw(acc.hid[l], dw + B::off_hidden(l), HIDDEN, B::LD_HID, lane);
+  flush_dw(acc.first, dw, HIDDEN, B::LD_FIRST, lane);
   __syncthreads();
   // flush the block's bone-transform gradients: every wave of every block
   // adds into the same few cache lines, so the sums stay in LDS until here
@@ -449,19 +450,24 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       if (dg[i] != 0.f) unsafeAtomicAdd(a.grad_G + i, dg[i]);
   // flush the block's MLP weight gradients
   const int n_first = HIDDEN * IN_FEAT, n_hid = HIDDEN * HIDDEN;
-  for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) {
-    const float v = dw[i];
-    if (v == 0.f) continue;
+  for (int i = threadIdx.x; i < n_first + NHH * n_hid + 4 * HIDDEN; i += blockDim.x) {
+    float v;
+    float* dst;
     if (i < n_first) {
-      unsafeAtomicAdd(a.grad_w[0] + i, v);
-    } else if (i < n_first + NHH * n_hid) {
-      const int l = (i - n_first) / n_hid;
-      unsafeAtomicAdd(a.grad_w[1 + l] + (i - n_first - l * n_hid), v);
+      const int r = i / IN_FEAT;
+      v = dw[r * B::LD_FIRST + (i - r * IN_FEAT)];
+      dst = a.grad_w[0] + i;
     } else {
-      unsafeAtomicAdd(a.grad_w[1 + NHH] + (i - n_first - NHH * n_hid), v);
+      const int e = i - n_first, l = e / n_hid, k = e - l * n_hid, r = k / HIDDEN;  // l == NHH: output layer
+      v = dw[B::off_hidden(l) + r * B::LD_HID + (k - r * HIDDEN)];
+      dst = a.grad_w[1 + l] + k;
     }
+    if (v != 0.f) unsafeAtomicAdd(dst, v);
   }
 }
+
+static_assert(BwdShape<MNR_BF16>::lds_bytes(2, 4) <= 160 * 1024, "LDS of the BF16 adjoint");
+static_assert(BwdShape<MNR_F32>::lds_bytes(2, 1) <= 160 * 1024, "LDS of the FP32 adjoint");
 
 template <typename TableT, int P, int NHH, bool SPLIT>
 static hipError_t launch_bwd_s(const RenderArgs& a, int n_slots, hipStream_t st) {

@@ -27,17 +27,6 @@ namespace mnr {
 constexpr int RES_FWD_WAVES = 8;
 constexpr int SKIN_WAVES = 8;
 
-// Ray slot r of a split-adjoint kernel: waves take slots in turn.
-__device__ __forceinline__ bool split_ray(const RenderArgs& a, int slot, int& orow, RaySetup& rs, int& n_done,
-                                          int nchunks) {
-  const int pix = ray_pixel(a.r, slot);
-  if (!a.r.pixel_ids && pix < 0) return false;
-  orow = a.r.pixel_ids ? slot : pix;
-  if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) return false;
-  n_done = (int)a.t_chunks[(size_t)orow * (nchunks + 1) + nchunks];
-  return true;
-}
-
 // ---- 1. forward of the warp and the residual network ------------------------
 
 __global__ void __launch_bounds__(64 * RES_FWD_WAVES) res_fwd_kernel(const RenderArgs a, int n_slots) {
@@ -101,85 +90,16 @@ struct ResTShape {
   static constexpr int bytes() { return o5 + T5; }
 };
 
-// Block sums of the weight gradients (FP32): W1 [64][32] (column 27, an
-// input that gamma never uses, carries the bias gradient: see below), W2,
-// W3 [64][64], W4 [64][96], W5 [3][64].
+// Block sums of the weight gradients (FP32, rows padded by 4 floats for
+// conflict-free LDS atomics): W1 [64][32] (column 27, an input that gamma
+// never uses, carries the bias gradient: see below), W2, W3 [64][64],
+// W4 [64][96], W5 [3][64].
 struct ResGrad {
-  static constexpr int n1 = 64 * 32, n2 = 64 * 64, n3 = 64 * 64, n4 = 64 * 96, n5 = 3 * 64;
-  static constexpr int o2 = n1, o3 = o2 + n2, o4 = o3 + n3, o5 = o4 + n4;
-  static constexpr int floats() { return o5 + n5; }
+  static constexpr int L1 = 36, L2 = 68, L3 = 68, L4 = 100, L5 = 68;  // row strides
+  static constexpr int o2 = 64 * L1, o3 = o2 + 64 * L2, o4 = o3 + 64 * L3, o5 = o4 + 64 * L4;
+  static constexpr int floats() { return o5 + 3 * L5; }
 };
 constexpr int BIAS_COL = 27;  // gamma has 27 values; inputs 27..31 are zero padding
-
-template <typename WT>
-__device__ void stage_t(char* lds, const WT* __restrict__ w, int M, int K, int Kpad) {
-  for (int e = threadIdx.x; e < K * Kpad; e += blockDim.x) {
-    const int m = e / Kpad, k = e - m * Kpad;  // element (m, k) of W^T = W[k][m]
-    const float v = (k < M) ? (float)w[(size_t)k * K + m] : 0.0f;
-    *(__bf16*)(lds + frag_offset<MNR_BF16>(m, k, Kpad / 32)) = (__bf16)v;
-  }
-}
-
-__device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
-  return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
-}
-
-// dW[M_out x K_in] (row stride K_in) += d (MT tiles) x h^T (NT tiles) over
-// the 16 samples of one tile, through the wave's transpose buffer tb
-// (2 x 64 x 16 bf16) and LDS float atomics.
-template <int MT, int NT>
-__device__ __forceinline__ void res_dw(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int K_in,
-                                       int lane) {
-  __bf16* td = tb;            // [64 rows][16 samples]
-  __bf16* th = tb + 64 * 16;  // [64 columns][16 samples]
-  const int c = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) td[(16 * t + 4 * g + j) * 16 + c] = (__bf16)d[t][j];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
-  wave_sync_lds();
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-      bf16x8 av, bv;
-      if (g < 2) {
-        av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
-        bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
-      }
-      const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 16 * mt + 4 * g + j;
-        if (row < M_out) atomicAdd(dw + row * K_in + 16 * kt + c, acc[j]);
-      }
-    }
-  }
-  wave_sync_lds();
-}
-
-// out[mt] = W^T-fragments (MT m-tiles, KS 32-wide k steps) x x (2 KS tiles).
-template <int MT, int KS>
-__device__ __forceinline__ void res_mm(const char* wl, const f4* x, f4* out, int lane) {
-  const bf16x8* W = (const bf16x8*)wl;
-  bf16x8 b[KS];
-#pragma unroll
-  for (int s = 0; s < KS; ++s) b[s] = pack_bf16(x[2 * s], x[2 * s + 1]);
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[(mt * KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
-    out[mt] = acc;
-  }
-}
 
 constexpr int RES_BWD_LDS = ResShape::bytes() + ResTShape::bytes() + ResGrad::floats() * 4 +
                             MlpShape<MNR_BF16>::feat_bytes_per_wave() + 2 * 64 * 16 * 2 + 64 * 32 * 4;
@@ -274,27 +194,27 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
           const float q0 = __shfl(gf[0], 16 * nt + c, WAVE), q1 = __shfl(gf[1], 16 * nt + c, WAVE),
                       q2 = __shfl(gf[2], 16 * nt + c, WAVE);
           f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : f4{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-          res_dw<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, 64, lane);
+          dw_tile<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, ResGrad::L5, lane);
           f4 d[4];
-          res_mm<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
+          mm_t<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
           // layer 4: input [h3; gamma]
-          res_dw<4, 4>(tb, d, h3, dw + ResGrad::o4, 64, 96, lane);
-          res_dw<4, 2>(tb, d, x, dw + ResGrad::o4 + 64, 64, 96, lane);
-          res_mm<6, 2>(rt + ResTShape::o4, d, tmp, lane);
+          dw_tile<4, 4>(tb, d, h3, dw + ResGrad::o4, 64, ResGrad::L4, lane);
+          dw_tile<4, 2>(tb, d, x, dw + ResGrad::o4 + 64, 64, ResGrad::L4, lane);
+          mm_t<6, 2>(rt + ResTShape::o4, d, tmp, lane);
           dg2[0] = tmp[4];
           dg2[1] = tmp[5];
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
           // layer 3
-          res_dw<4, 4>(tb, d, h2, dw + ResGrad::o3, 64, 64, lane);
-          res_mm<4, 2>(rt + ResTShape::o3, d, tmp, lane);
+          dw_tile<4, 4>(tb, d, h2, dw + ResGrad::o3, 64, ResGrad::L3, lane);
+          mm_t<4, 2>(rt + ResTShape::o3, d, tmp, lane);
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
           // layer 2
-          res_dw<4, 4>(tb, d, h1, dw + ResGrad::o2, 64, 64, lane);
-          res_mm<4, 2>(rt + ResTShape::o2, d, tmp, lane);
+          dw_tile<4, 4>(tb, d, h1, dw + ResGrad::o2, 64, ResGrad::L2, lane);
+          mm_t<4, 2>(rt + ResTShape::o2, d, tmp, lane);
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
           // layer 1: the pose term enters as a bias, so the bias gradient is
@@ -303,8 +223,8 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
           // collects exactly that sum
           f4 xb[2] = {x[0], x[1]};
           if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
-          res_dw<4, 2>(tb, d, xb, dw, 64, 32, lane);
-          res_mm<2, 2>(rt, d, tmp, lane);
+          dw_tile<4, 2>(tb, d, xb, dw, 64, ResGrad::L1, lane);
+          mm_t<2, 2>(rt, d, tmp, lane);
           dg2[0] += tmp[0];
           dg2[1] += tmp[1];
         }
@@ -336,23 +256,20 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
     }
   }
   __syncthreads();
-  // flush the block's sums; column 27 of dW1 is the bias gradient
-  for (int i = lane; i < ResGrad::floats(); i += 64) {
-    const float v = dw[i];
-    if (v == 0.f) continue;
-    if (i < ResGrad::o2) {
-      if ((i & 31) == BIAS_COL) unsafeAtomicAdd(a.split.dbias + (i >> 5), v);
-      else unsafeAtomicAdd(a.grad_res[0] + i, v);
-    } else if (i < ResGrad::o3) {
-      unsafeAtomicAdd(a.grad_res[1] + (i - ResGrad::o2), v);
-    } else if (i < ResGrad::o4) {
-      unsafeAtomicAdd(a.grad_res[2] + (i - ResGrad::o3), v);
-    } else if (i < ResGrad::o5) {
-      unsafeAtomicAdd(a.grad_res[3] + (i - ResGrad::o4), v);
-    } else {
-      unsafeAtomicAdd(a.grad_res[4] + (i - ResGrad::o5), v);
+  // flush the block's sums (element k of layer l sits at row k / K of the
+  // padded block); column 27 of dW1 is the bias gradient
+  const int cols[5] = {32, 64, 64, 96, 64}, rows[5] = {64, 64, 64, 64, 3};
+  const int ld[5] = {ResGrad::L1, ResGrad::L2, ResGrad::L3, ResGrad::L4, ResGrad::L5};
+  const int off[5] = {0, ResGrad::o2, ResGrad::o3, ResGrad::o4, ResGrad::o5};
+#pragma unroll
+  for (int l = 0; l < 5; ++l)
+    for (int k = lane; k < rows[l] * cols[l]; k += 64) {
+      const int r = k / cols[l], c = k - r * cols[l];
+      const float v = dw[off[l] + r * ld[l] + c];
+      if (v == 0.f) continue;
+      if (l == 0 && c == BIAS_COL) unsafeAtomicAdd(a.split.dbias + r, v);
+      else unsafeAtomicAdd(a.grad_res[l] + k, v);
     }
-  }
 }
 
 // ---- 3. the skinning adjoint with dL/dx_skel ----------------------------------
@@ -418,12 +335,16 @@ hipError_t launch_res_backward(const RenderArgs& a, int n_slots, hipStream_t st)
   const int mb = persistent_blocks(res_bwd_kernel, 64, RES_BWD_LDS, pg);
   hipLaunchKernelGGL(res_bwd_kernel, dim3(n_slots < mb ? (n_slots > 0 ? n_slots : 1) : mb), dim3(64), RES_BWD_LDS,
                      st, a, n_slots);
-  static PersistentGrid pg2;
-  const int mb2 = persistent_blocks(skin_bwd_kernel, 64 * SKIN_WAVES, 0, pg2);
-  const int need = (n_slots + SKIN_WAVES - 1) / SKIN_WAVES;
-  hipLaunchKernelGGL(skin_bwd_kernel, dim3(need < mb2 ? (need > 0 ? need : 1) : mb2), dim3(64 * SKIN_WAVES), 0, st, a,
-                     n_slots);
   hipLaunchKernelGGL(omega_grad_kernel, dim3(16), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_skin_backward(const RenderArgs& a, int n_slots, hipStream_t st) {
+  static PersistentGrid pg;
+  const int mb = persistent_blocks(skin_bwd_kernel, 64 * SKIN_WAVES, 0, pg);
+  const int need = (n_slots + SKIN_WAVES - 1) / SKIN_WAVES;
+  hipLaunchKernelGGL(skin_bwd_kernel, dim3(need < mb ? (need > 0 ? need : 1) : mb), dim3(64 * SKIN_WAVES), 0, st, a,
+                     n_slots);
   return hipGetLastError();
 }
 

@@ -60,10 +60,17 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_histogram_kernel(const uint32
   __syncthreads();
   const uint32_t t0 = (uint32_t)tile * BIN_TILE;
   uint32_t k[BIN_PER_THREAD];
+  // loads from clamped places, then the range test: all of a thread's
+  // loads are in flight together instead of one branch and wait per load
 #pragma unroll
   for (int j = 0; j < BIN_PER_THREAD; ++j) {
     const uint32_t i = t0 + j * BIN_THREADS + threadIdx.x;
-    k[j] = i < count ? keys[i] >> shift : 0xFFFFFFFFu;
+    k[j] = keys[i < count ? i : count - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const uint32_t i = t0 + j * BIN_THREADS + threadIdx.x;
+    k[j] = i < count ? k[j] >> shift : 0xFFFFFFFFu;
   }
 #pragma unroll
   for (int j = 0; j < BIN_PER_THREAD; ++j)
@@ -222,7 +229,7 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
                                                                      const uint32_t* __restrict__ base,
                                                                      const HashedLevels levels,
                                                                      float* __restrict__ grad) {
-  extern __shared__ float acc[];  // [2^shift][2]
+  extern __shared__ float acc[];  // [2][2^shift]: the two features in separate planes (row r: bank r mod 64)
   const int b = blockIdx.x;
   const uint32_t n = total[b];
   if (n == 0) return;
@@ -230,21 +237,55 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0.f;
   __syncthreads();
   const uint32_t s0 = base[b], mask = (uint32_t)rows - 1u;
-  constexpr int U = 4;  // records in flight per thread
+  const int lane = threadIdx.x & 63;
+  constexpr int U = 8;  // records in flight per thread
   for (uint32_t i0 = 0; i0 < n; i0 += U * ACC_THREADS) {
     uint32_t r[U];
     f2 v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < U; ++u) {  // clamped places: the U loads are in flight together
       const uint32_t i = i0 + u * ACC_THREADS + threadIdx.x;
-      r[u] = i < n ? skeys[s0 + i] & mask : 0xFFFFFFFFu;
-      v[u] = i < n ? svals[s0 + i] : f2{0.f, 0.f};
+      const uint32_t ic = s0 + (i < n ? i : n - 1);
+      r[u] = skeys[ic];
+      v[u] = svals[ic];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (r[u] != 0xFFFFFFFFu) {
-        atomicAdd(&acc[2 * r[u]], v[u][0]);
-        atomicAdd(&acc[2 * r[u] + 1], v[u][1]);
+      const uint32_t i = i0 + u * ACC_THREADS + threadIdx.x;
+      r[u] = i < n ? r[u] & mask : 0xFFFFFFFFu;
+      v[u] = i < n ? v[u] : f2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // Neighbouring records often carry the same row (consecutive samples
+      // of a ray in one cell): sum such runs across the wave first, so that
+      // one lane per run adds, instead of lanes queueing on one LDS address.
+      const uint32_t prev = __shfl_up(r[u], 1, WAVE);
+      const bool head = lane == 0 || prev != r[u];
+      const uint64_t heads = __ballot(head);
+      uint64_t z0 = ~heads;
+      int steps = 0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        if (z0 == 0) break;
+        ++steps;
+        z0 &= z0 >> (1 << j);
+      }
+      if (steps) {
+        const int seg = (int)__popcll(heads & (~0ull >> (63 - lane)));
+        for (int j = 0; j < steps; ++j) {
+          const int d = 1 << j;
+          const int seg_d = __shfl_down(seg, d, WAVE);
+          const float o0 = __shfl_down(v[u][0], d, WAVE), o1 = __shfl_down(v[u][1], d, WAVE);
+          if (lane + d < WAVE && seg_d == seg) {
+            v[u][0] += o0;
+            v[u][1] += o1;
+          }
+        }
+      }
+      if (head && r[u] != 0xFFFFFFFFu) {
+        atomicAdd(&acc[r[u]], v[u][0]);
+        atomicAdd(&acc[rows + r[u]], v[u][1]);
       }
     }
   }
@@ -252,7 +293,7 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   const int64_t k0 = (int64_t)b << shift;
   const uint32_t tmask = (1u << levels.log2_T) - 1u;
   for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
-    const f2 v = f2{acc[2 * r], acc[2 * r + 1]};
+    const f2 v = f2{acc[r], acc[rows + r]};
     const int64_t key = k0 + r;
     if ((v[0] != 0.f || v[1] != 0.f) && key < n_keys) {
       const int h = (int)(key >> levels.log2_T);

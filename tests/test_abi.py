@@ -214,8 +214,9 @@ def test_build_script_loads_without_the_package():
 def test_adjoint_workspace_size_and_checks():
     # Adjoint workspace: binned-scatter records for every sample, hashed
     # level and corner, twice, plus per-tile bin histograms; with a residual
-    # network, 14 floats per sample slot and 64 floats of bias gradient
-    # (include/metanerf.h).
+    # network or the frequency-encoded field, 18 floats per sample slot and
+    # 64 floats of bias gradient, and for the frequency-encoded field 512
+    # bytes of saved activations per slot (include/metanerf.h).
     m = _lib()
     sc = scenes.scene_body(H=8, W=8, spp=8, res=8, log2_T=19)
     _, f, mo, pose, cam = _args(sc)
@@ -231,10 +232,20 @@ def test_adjoint_workspace_size_and_checks():
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
         for k in range(6):
             mo.res_w[k] = 0x7000 + 0x100 * k
-        split = a256(14 * n_rays * -(-spp // 64) * 64 * 4) + 256
+        split = a256(18 * n_rays * -(-spp // 64) * 64 * 4) + 256
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split
         for k in range(6):
             mo.res_w[k] = None
+    ff = m.Field()      # the frequency-encoded field: no records, split scratch and saved activations
+    ff.encoding, ff.mlp_dtype, ff.n_layers = 1, m.BF16, 5
+    ff.width[:6] = [64, 64, 64, 64, 64, 4]
+    ff.box_min[:], ff.box_max[:] = [-0.5] * 3, [0.5] * 3
+    for k in range(5):
+        ff.w[k] = 0x9000 + 0x100 * k
+    for n_rays, spp in ((8192, 128), (100, 7)):
+        chunks = n_rays * -(-spp // 64)
+        want = a256(18 * chunks * 64 * 4) + 256 + chunks * 4 * 4 * 2 * 64 * 16
+        assert m.lib.mnr_adjoint_ws_bytes(C.byref(ff), C.byref(mo), n_rays, spp) == want
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
     f.log2_T = 24       # the largest table: 4 hashed levels of 2^24 rows, 4096 slices of 2^14 rows
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 64, 8) > 0

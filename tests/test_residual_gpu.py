@@ -67,6 +67,39 @@ def test_zero_output_layer_is_bitwise_plain():
     assert np.array_equal(a, b)
 
 
+def test_residual_on_a_refined_pose_matches_oracle():
+    # Eq. 11 conditions the residual network on the observed pose theta^o:
+    # with a refiner adjustment its joint angles are those of
+    # R(Delta_j) R(omega_j), the rotations the bone transforms use.  The
+    # oracle conditioned on the unrefined angles instead must differ
+    # visibly, so the test sees which angles the GPU used.
+    import paper_2306_16541_amd as m
+    from oracle import pose as OP
+    from oracle import render as O
+    sc = scenes.scene_body(H=40, W=48, spp=96)
+    res = scenes.residual_weights(25)
+    delta = np.random.default_rng(11).normal(0.0, 0.3, (24, 3)).astype(np.float32)
+    fld, _ = m.upload_scene(sc, "cuda", 1, 2)
+    fld.set_residual(res[0], res[1], 4.0)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle, delta)
+    got = m.render(fld, pose, m.make_camera(sc.cam), sc.H, sc.W, sc.spp, m.make_opts()).cpu().numpy()
+    G = OP.refined_bone_transforms(sc.parents, sc.rest_joints, sc.axis_angle, delta)
+    o, d = O.camera_rays(sc.cam, sc.H, sc.W, np.arange(sc.H * sc.W))
+    field = O.Field.from_scene(sc)
+
+    def orc(omega):
+        r = {"weights": res[0], "w_omega": res[1], "alpha": 4.0, "omega": omega}
+        return O.render_rays(field, G, o, d, sc.spp, residual=r).numpy()
+    want = orc(OP.observed_angles(sc.axis_angle, delta))
+    stale = orc(sc.axis_angle)
+    p, p_stale = psnr(got[:, :3], want[:, :3]), psnr(got[:, :3], stale[:, :3])
+    moved = float(np.abs(want - stale).max())
+    print(f"[residual, refined pose] PSNR {p:.2f} dB vs oracle; {p_stale:.2f} dB vs the oracle on the unrefined "
+          f"angles (which moves pixels by {moved:.3e})", flush=True)
+    assert moved > 1e-2
+    assert p >= 45.0 and p > p_stale + 10.0
+
+
 def test_residual_needs_the_bf16_path():
     import paper_2306_16541_amd as m
     sc = scenes.scene_body(H=16, W=16, spp=32)
@@ -84,11 +117,11 @@ def test_residual_needs_the_bf16_path():
 # group's largest (8-bit mantissas in every product of two MLPs, forward and
 # back).
 
-def _res_grads_gpu(sc, res, pid, tgt, alpha, seed=77):
+def _res_grads_gpu(sc, res, pid, tgt, alpha, seed=77, delta=None):
     import paper_2306_16541_amd as m
     fld, _ = m.upload_scene(sc, "cuda", m.F32, m.BF16)
     fld.set_residual(res[0], res[1], alpha)
-    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle, delta)
     cam = m.make_camera(sc.cam)
     opts = m.make_opts(ert_tau=0.0, stratified=True, seed=seed)
     n = len(pid)
@@ -113,16 +146,22 @@ def _res_grads_gpu(sc, res, pid, tgt, alpha, seed=77):
             [w.cpu().numpy() for w in g_res], gG.cpu().numpy())
 
 
-def _res_grads_oracle(sc, res, pid, tgt, alpha, seed=77):
+def _res_grads_oracle(sc, res, pid, tgt, alpha, seed=77, delta=None):
+    from oracle import pose as OP
     from oracle import render as O
     from oracle.rng import stratified_xi
     field = O.Field.from_scene(sc, requires_grad=True)
     rw = [torch.tensor(np.asarray(w, np.float64), requires_grad=True) for w in res[0]]
     wo = torch.tensor(np.asarray(res[1], np.float64), requires_grad=True)
-    G = O.bone_transforms(sc.parents, sc.rest_joints, sc.axis_angle).requires_grad_(True)
+    if delta is None:
+        G, omega = O.bone_transforms(sc.parents, sc.rest_joints, sc.axis_angle), sc.axis_angle
+    else:
+        G = OP.refined_bone_transforms(sc.parents, sc.rest_joints, sc.axis_angle, delta)
+        omega = OP.observed_angles(sc.axis_angle, delta)
+    G = G.detach().requires_grad_(True)
     o, d = O.camera_rays(sc.cam, sc.H, sc.W, pid)
     rgba = O.render_rays(field, G, o, d, sc.spp, xi=stratified_xi(seed, len(pid), sc.spp),
-                         residual={"weights": rw, "w_omega": wo, "alpha": alpha, "omega": sc.axis_angle})
+                         residual={"weights": rw, "w_omega": wo, "alpha": alpha, "omega": omega})
     loss = O.mse_loss(rgba, tgt)
     loss.backward()
     return (float(loss.detach()), [field.table.grad.numpy(), field.logits.grad.numpy()] +
@@ -200,8 +239,8 @@ def _bf16(a):
     return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).float().numpy()
 
 
-@pytest.mark.parametrize("alpha", [4.0, 1.5])
-def test_residual_adjoint_matches_oracle_gradient(alpha):
+@pytest.mark.parametrize("alpha,refined", [(4.0, False), (1.5, False), (4.0, True)])
+def test_residual_adjoint_matches_oracle_gradient(alpha, refined):
     # On the fine hashed levels (cells of 1/512) the gradients with respect
     # to the residual network are ill-conditioned: a BF16-sized change of the
     # offset x_res (~1e-4) moves samples across cell faces, where the
@@ -223,12 +262,17 @@ def test_residual_adjoint_matches_oracle_gradient(alpha):
     pid = np.array([(12 + g.integers(0, 8)) * sc.W + 12 + g.integers(0, 8) for _ in range(12)] +
                    list(g.integers(0, sc.H * sc.W, 4)), dtype=np.int32)
     tgt = g.random((16, 3)).astype(np.float32)
-    lg, got, gG = _res_grads_gpu(sc, res, pid, tgt, alpha)
-    lo, want, oG = _res_grads_oracle(sc, res, pid, tgt, alpha)
+    # refined: a pose-refiner adjustment; the residual network then sees the
+    # observed pose's joint angles (R(Delta_j) R(omega_j)), so dL/dW_omega
+    # is taken against those
+    delta = np.random.default_rng(12).normal(0.0, 0.3, (24, 3)).astype(np.float32) if refined else None
+    lg, got, gG = _res_grads_gpu(sc, res, pid, tgt, alpha, delta=delta)
+    lo, want, oG = _res_grads_oracle(sc, res, pid, tgt, alpha, delta=delta)
     sc_r = copy.copy(sc)
     sc_r.mlp = [_bf16(w) for w in sc.mlp]
-    _, shifted, _ = _res_grads_oracle(sc_r, ([_bf16(w) for w in res[0]], _bf16(res[1])), pid, tgt, alpha)
-    print(f"[residual adjoint alpha={alpha}] loss gpu {lg:.7f} oracle {lo:.7f}", flush=True)
+    _, shifted, _ = _res_grads_oracle(sc_r, ([_bf16(w) for w in res[0]], _bf16(res[1])), pid, tgt, alpha,
+                                      delta=delta)
+    print(f"[residual adjoint alpha={alpha} refined={refined}] loss gpu {lg:.7f} oracle {lo:.7f}", flush=True)
     names = ["table", "logits"] + [f"w{k}" for k in range(len(sc.mlp))] + [f"res W{k + 1}" for k in range(5)] + \
         ["res W_omega"]
     bad = []
