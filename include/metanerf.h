@@ -338,7 +338,7 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
  * the 9 hashed levels of a 2^19-row, 16-level table, none when the batch
  * (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14 rows)
  * is too large for the binned path -- plus, with a residual network or the
- * frequency-encoded field, 72 bytes per sample slot (n_rays * ceil(spp / 64)
+ * frequency-encoded field, 84 bytes per sample slot (n_rays * ceil(spp / 64)
  * * 64 slots, rounded up to 256 bytes) and 256 bytes, and for the
  * frequency-encoded field 512 bytes more per sample slot (its saved hidden
  * activations).  0: nothing to use it for. */

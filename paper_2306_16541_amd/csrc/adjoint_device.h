@@ -219,14 +219,22 @@ __device__ void stage_t(char* lds, const WT* __restrict__ w, int M, int K, int K
   }
 }
 
+// Tile w (0..3) of d, without indexing a register array by a runtime value.
+__device__ __forceinline__ f4 pick4(const f4 (&d)[4], int w) {
+  return w == 0 ? d[0] : (w == 1 ? d[1] : (w == 2 ? d[2] : d[3]));
+}
+
 __device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
   return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
 }
 
 // dW[M_out x K] (row stride ld) += d (MT tiles) x h^T (NT tiles) over the
 // 16 samples of one tile, through the wave's transpose buffer tb
-// (2 x 64 x 16 bf16) and LDS float atomics.  With ld = 4 (mod 16) the 64
-// lanes of one atomic (rows 4g + j, columns c) fall in distinct banks.
+// (2 x 64 x 16 bf16).  The sums are added with plain LDS read-add-write:
+// the caller guarantees that no other wave adds to the same rows (LDS float
+// atomics on this GPU cost far more than the products).  With ld = 4
+// (mod 16) the 64 lanes of one access (rows 4g + j, columns c) fall in
+// distinct banks.
 template <int MT, int NT>
 __device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int ld,
                                         int lane) {
@@ -258,7 +266,7 @@ __device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, fl
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = 16 * mt + 4 * g + j;
-        if (row < M_out) atomicAdd(dw + row * ld + 16 * kt + c, acc[j]);
+        if (row < M_out) dw[row * ld + 16 * kt + c] += acc[j];
       }
     }
   }

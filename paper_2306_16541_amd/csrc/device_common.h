@@ -97,10 +97,11 @@ enum SplitField {
   SPLIT_XS = 3,   // skinned point x_skel (3)
   SPLIT_XF = 6,   // x_final = x_skel + x_res (3)
   SPLIT_L = 9,    // weight sum L; 0 for samples that are not live
-  SPLIT_G = 10,   // dL/dx_final (3), then dL/dx_skel
+  SPLIT_G = 10,   // dL/dx_final (3); without the residual network also dL/dx_skel
   SPLIT_GL = 13,  // dL/dL
   SPLIT_GO = 14,  // dL/d(raw field outputs) (4), frequency-encoded field
-  SPLIT_N = 18
+  SPLIT_GS = 18,  // dL/dx_skel (3), written by the residual network's adjoint
+  SPLIT_N = 21
 };
 // Saved hidden activations of the frequency-encoded field's MLP per
 // 64-sample chunk: 4 layers x 4 tiles x 2 halves x 64 lanes of 8 BF16.

@@ -13,7 +13,8 @@
 //                     values the next layer consumed), and the compositing
 //                     adjoint, storing dL/d(outputs) and dL/dL;
 //   freq_bwd_kernel   per 16-sample tile, the MLP's adjoint from the saved
-//                     activations: dL/dW1..W5 (block sums in LDS) and
+//                     activations: dL/dW1..W5 (block sums in LDS, each
+//                     wave adding its own rows) and
 //                     dL/dx_final = (d gamma / dx)^T dL/dgamma, where
 //                     dL/dgamma collects the first layer's and the skip's
 //                     terms;
@@ -175,9 +176,12 @@ __device__ __forceinline__ void load_act(const bf16x8* act, int layer, int nt, i
   h[3] = f4{(float)q[4], (float)q[5], (float)q[6], (float)q[7]};
 }
 
-// Four waves per block share the transposed weights and the gradient sums;
-// each wave takes rays in turn and, per 64-sample chunk, its live 16-sample
-// tiles.  Lane c + 16 g works on sample 16 nt + c.
+// The four waves of a block work on the same rays, chunks and tiles: each
+// runs the whole backward chain of the tile (the dX products, cheap on the
+// MFMAs) but adds only its own 16 rows of every weight gradient (wave w:
+// rows 16 w .. 16 w + 15; W5's four rows: wave 0), so no two waves add to
+// one LDS entry and the sums need no atomics.  Wave 0 writes dL/dx_final.
+// Lane c + 16 g works on sample 16 nt + c.
 __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const RenderArgs a, int n_slots) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -196,7 +200,12 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
   const int64_t ss = a.split.stride;
   const int c = lane & 15, g = lane >> 4;
   const f4 z4 = {0.f, 0.f, 0.f, 0.f};
-  for (int slot = blockIdx.x * FREQ_BWD_WAVES + wave; slot < n_slots; slot += gridDim.x * FREQ_BWD_WAVES) {
+  // this wave's rows of each gradient block
+  float* dw1 = dw + 16 * wave * FreqGrad::L1;
+  float* dw2 = dw + FreqGrad::o2 + 16 * wave * FreqGrad::L2;
+  float* dw3 = dw + FreqGrad::o3 + 16 * wave * FreqGrad::L3;
+  float* dw4 = dw + FreqGrad::o4 + 16 * wave * FreqGrad::L4;
+  for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
     if (!split_ray(a, slot, orow, rs, n_done, nchunks)) continue;
@@ -244,31 +253,36 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
           const float q2 = __shfl(go[2], sl, WAVE), q3 = __shfl(go[3], sl, WAVE);
           if (g == 0) d5[0] = f4{q0, q1, q2, q3};
         }
-        f4 tmp[8], d[4], dgam[4];
-        dw_tile<1, 4>(tb, d5, h4, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
+        f4 tmp[8], d[4], dgam[4], dw_rows[1];
+        if (wave == 0) dw_tile<1, 4>(tb, d5, h4, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
         mm_t<4, 1>(rt + FreqTShape::o5, d5, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
         // layer 4: input [h3; gamma]
-        dw_tile<4, 4>(tb, d, h3, dw + FreqGrad::o4, HIDDEN, FreqGrad::L4, lane);
-        dw_tile<4, 4>(tb, d, gam, dw + FreqGrad::o4 + HIDDEN, HIDDEN, FreqGrad::L4, lane);
+        dw_rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, dw_rows, h3, dw4, 16, FreqGrad::L4, lane);
+        dw_tile<1, 4>(tb, dw_rows, gam, dw4 + HIDDEN, 16, FreqGrad::L4, lane);
         mm_t<8, 2>(rt + FreqTShape::o4, d, tmp, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) dgam[t] = tmp[4 + t];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
         // layer 3
-        dw_tile<4, 4>(tb, d, h2, dw + FreqGrad::o3, HIDDEN, FreqGrad::L3, lane);
+        dw_rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, dw_rows, h2, dw3, 16, FreqGrad::L3, lane);
         mm_t<4, 2>(rt + FreqTShape::o3, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
         // layer 2
-        dw_tile<4, 4>(tb, d, h1, dw + FreqGrad::o2, HIDDEN, FreqGrad::L2, lane);
+        dw_rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, dw_rows, h1, dw2, 16, FreqGrad::L2, lane);
         mm_t<4, 2>(rt + FreqTShape::o2, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
         // layer 1: input gamma
-        dw_tile<4, 4>(tb, d, gam, dw, HIDDEN, FreqGrad::L1, lane);
+        dw_rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, dw_rows, gam, dw1, 16, FreqGrad::L1, lane);
+        if (wave != 0) continue;
         mm_t<4, 2>(rt, d, tmp, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) dgam[t] += tmp[t];
@@ -322,9 +336,8 @@ hipError_t launch_freq_backward(const RenderArgs& a, int n_slots, hipStream_t st
   else launch_save<false>(a, n_slots, st);
   static PersistentGrid pg;
   const int mb = persistent_blocks(freq_bwd_kernel, 64 * FREQ_BWD_WAVES, FREQ_BWD_LDS, pg);
-  const int need = (n_slots + FREQ_BWD_WAVES - 1) / FREQ_BWD_WAVES;
-  hipLaunchKernelGGL(freq_bwd_kernel, dim3(need < mb ? (need > 0 ? need : 1) : mb), dim3(64 * FREQ_BWD_WAVES),
-                     FREQ_BWD_LDS, st, a, n_slots);
+  hipLaunchKernelGGL(freq_bwd_kernel, dim3(n_slots < mb ? (n_slots > 0 ? n_slots : 1) : mb),
+                     dim3(64 * FREQ_BWD_WAVES), FREQ_BWD_LDS, st, a, n_slots);
   return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@
 //                    differentiated: dL/dW1..W5 (block sums in LDS), the
 //                    sum of the first layer's pre-activation gradients (for
 //                    dL/dW_omega), and dL/dx_skel = dL/dx_final +
-//                    (d x_res / d x_skel)^T dL/dx_final;
+//                    (d x_res / d x_skel)^T dL/dx_final (stored apart from
+//                    dL/dx_final);
 //   skin_bwd_kernel  the skinning adjoint with dL/dx_skel (dL/dW^c, dL/dG);
 //   omega_grad_kernel  dL/dW_omega = (sum of layer-1 gradients) Omega^T.
 #include "adjoint_device.h"
@@ -101,37 +102,82 @@ struct ResGrad {
 };
 constexpr int BIAS_COL = 27;  // gamma has 27 values; inputs 27..31 are zero padding
 
-constexpr int RES_BWD_LDS = ResShape::bytes() + ResTShape::bytes() + ResGrad::floats() * 4 +
-                            MlpShape<MNR_BF16>::feat_bytes_per_wave() + 2 * 64 * 16 * 2 + 64 * 32 * 4;
+constexpr int RES_BWD_WAVES = 4;
+constexpr int RES_BWD_LDS = ResShape::bytes() + ResTShape::bytes() + ResGrad::floats() * 4 + RES_BWD_WAVES * RES_TB_BYTES;
 static_assert(RES_BWD_LDS <= 160 * 1024, "LDS of the residual adjoint");
 
-// One wave per block (the weights, their transposes and the gradient sums
-// fill the LDS).  Per 64-sample chunk: gamma(x_skel) into the feature
-// buffer; per 16-sample tile the forward pass again (activations kept in
-// registers), then the backward pass layer by layer; dL/dgamma to LDS and
-// from there, per lane, through gamma's derivative to dL/dx_skel.
-__global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_slots) {
+// gamma(x_skel) of the residual network (Hann-windowed, 27 values, zero
+// padded to 32) at the 8 inputs k = 16 t + 4 g + e (t = 0, 1; e = 0..3)
+// that lane group g holds in the D layout, with d gamma_k / d x_q(k):
+// value, derivative, axis.  Values are formed as the forward pass forms
+// them, so they round to the same BF16 operands.
+__device__ __forceinline__ void res_posenc_lane(const float x[3], const float (&win)[4], int g, f4 (&val)[2],
+                                                float (&der)[8], int (&axis)[8]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 16 * t + 4 * g + e, n = 4 * t + e;
+      float v = 0.f, d = 0.f;
+      int q = 0;
+      if (k < 3) {
+        q = k;
+        v = x[0];
+        if (k == 1) v = x[1];
+        if (k == 2) v = x[2];
+        d = 1.f;
+      } else if (k < 27) {
+        const int band = (k - 3) / 6, r = (k - 3) - 6 * ((k - 3) / 6);
+        q = r < 3 ? r : r - 3;
+        const float xq = q == 0 ? x[0] : (q == 1 ? x[1] : x[2]);
+        const float w = band == 0 ? win[0] : (band == 1 ? win[1] : (band == 2 ? win[2] : win[3]));
+        float sv, cv;
+        sincospif((float)(1 << band) * xq, &sv, &cv);
+        v = w * (r < 3 ? sv : cv);
+        d = w * (float)(1 << band) * 3.14159265358979f * (r < 3 ? cv : -sv);
+      }
+      val[t][e] = v;
+      der[n] = d;
+      axis[n] = q;
+    }
+}
+
+// Four waves per block share the weights, their transposes and the
+// gradient sums, and work on the same rays, chunks and tiles: each recomputes
+// the tile's forward pass and runs the whole backward chain (the products
+// are cheap on the MFMAs) but adds only its own 16 rows of every weight
+// gradient (wave w: rows 16 w .. 16 w + 15; W5's three rows: wave 0), so no
+// two waves add to one LDS entry and the sums need no atomics.  gamma and
+// its derivative are formed in registers, in the D layout; wave 0 writes
+// dL/dx_skel = dL/dx_final + (d gamma / d x_skel)^T dL/dgamma, to a field
+// of its own (the other waves may still be reading dL/dx_final).
+__global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const RenderArgs a, int n_slots) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   char* rl = lds;
   char* rt = rl + ResShape::bytes();
   float* dw = (float*)(rt + ResTShape::bytes());
-  char* feat = (char*)(dw + ResGrad::floats());
-  __bf16* tb = (__bf16*)(feat + MlpShape<MNR_BF16>::feat_bytes_per_wave());
-  float* dgam = (float*)(tb + 2 * 64 * 16);  // [64 samples][32]
+  __bf16* tb = (__bf16*)((char*)(dw + ResGrad::floats()) + wave * RES_TB_BYTES);
   stage_residual(rl, a.res);
   stage_t(rt, a.res.w[0], HIDDEN, 32, HIDDEN);
   stage_t(rt + ResTShape::o2, a.res.w[1], HIDDEN, HIDDEN, HIDDEN);
   stage_t(rt + ResTShape::o3, a.res.w[2], HIDDEN, HIDDEN, HIDDEN);
   stage_t(rt + ResTShape::o4, a.res.w[3], HIDDEN, HIDDEN + 32, HIDDEN);
   stage_t(rt + ResTShape::o5, a.res.w[4], 3, HIDDEN, 32);
-  for (int i = lane; i < ResGrad::floats(); i += 64) dw[i] = 0.f;
+  for (int i = threadIdx.x; i < ResGrad::floats(); i += blockDim.x) dw[i] = 0.f;
   __syncthreads();
   const float* bias = (const float*)(rl + ResShape::obias);
+  const float win[4] = {a.res.win[0], a.res.win[1], a.res.win[2], a.res.win[3]};
   const int nchunks = (a.r.spp + 63) >> 6;
   float* sb = a.split.buf;
   const int64_t ss = a.split.stride;
   const int c = lane & 15, g = lane >> 4;
+  const f4 z4 = {0.f, 0.f, 0.f, 0.f};
+  // this wave's rows of each gradient block
+  float* dw1 = dw + 16 * wave * ResGrad::L1;
+  float* dw2 = dw + ResGrad::o2 + 16 * wave * ResGrad::L2;
+  float* dw3 = dw + ResGrad::o3 + 16 * wave * ResGrad::L3;
+  float* dw4 = dw + ResGrad::o4 + 16 * wave * ResGrad::L4;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
@@ -140,7 +186,8 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
     for (int ch = 0; ch < nchunks && ch * 64 < n_done; ++ch) {
       if (tc[ch] < 0.f) continue;
       const int i = ch * 64 + lane;
-      const int64_t sj = ((int64_t)orow * nchunks + ch) * 64 + lane;
+      const int64_t cj = (int64_t)orow * nchunks + ch;
+      const int64_t sj = cj * 64 + lane;
       const bool live = i < n_done && sb[SPLIT_L * ss + sj] > 0.f;
       const uint64_t live_mask = __ballot(live);
       if (live_mask == 0) continue;
@@ -152,107 +199,99 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
           gf[q] = sb[(SPLIT_G + q) * ss + sj];
         }
       }
-      // gamma(x_skel), as the forward pass builds it
-      float gm[32], sn[4][3], cs[4][3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) gm[q] = xs[q];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          sincospif((float)(1 << k) * xs[q], &sn[k][q], &cs[k][q]);
-          gm[3 + 6 * k + q] = a.res.win[k] * sn[k][q];
-          gm[6 + 6 * k + q] = a.res.win[k] * cs[k][q];
-        }
-#pragma unroll
-      for (int q = 27; q < 32; ++q) gm[q] = 0.f;
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        store_feat2<MNR_BF16>(feat, lane, 2 * q, live ? f2{gm[2 * q], gm[2 * q + 1]} : f2{0.f, 0.f});
-      wave_sync_lds();
 #pragma unroll 1
       for (int nt = 0; nt < 4; ++nt) {
-        f4 dg2[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        if ((live_mask >> (16 * nt)) & 0xFFFFull) {
-          // forward, as residual_step
-          f4 x[4], h1[4], h2[4], h3[4], h4[4], tmp[6];
-          load_input<MNR_BF16>(feat, nt, lane, x);
-          mma_layer<MNR_BF16, 4, 2>(rl, x, h1, lane, bias);
+        if (!((live_mask >> (16 * nt)) & 0xFFFFull)) continue;
+        const int sl = 16 * nt + c;  // the lane's sample
+        const bool slive = (live_mask >> sl) & 1ull;
+        float x3[3];
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt) h1[mt] = relu4(h1[mt]);
-          mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o2, h1, h2, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
-          mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o3, h2, h3, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) h3[mt] = relu4(h3[mt]);
-          const f4 cat[6] = {h3[0], h3[1], h3[2], h3[3], x[0], x[1]};
-          mma_layer<MNR_BF16, 4, 6>(rl + ResShape::o4, cat, h4, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) h4[mt] = relu4(h4[mt]);
-          // output gradient: rows 0..2 of sample 16 nt + c are dL/dx_res = dL/dx_final
-          const float q0 = __shfl(gf[0], 16 * nt + c, WAVE), q1 = __shfl(gf[1], 16 * nt + c, WAVE),
-                      q2 = __shfl(gf[2], 16 * nt + c, WAVE);
-          f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : f4{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-          dw_tile<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, ResGrad::L5, lane);
-          f4 d[4];
-          mm_t<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
-          // layer 4: input [h3; gamma]
-          dw_tile<4, 4>(tb, d, h3, dw + ResGrad::o4, 64, ResGrad::L4, lane);
-          dw_tile<4, 2>(tb, d, x, dw + ResGrad::o4 + 64, 64, ResGrad::L4, lane);
-          mm_t<6, 2>(rt + ResTShape::o4, d, tmp, lane);
-          dg2[0] = tmp[4];
-          dg2[1] = tmp[5];
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
-          // layer 3
-          dw_tile<4, 4>(tb, d, h2, dw + ResGrad::o3, 64, ResGrad::L3, lane);
-          mm_t<4, 2>(rt + ResTShape::o3, d, tmp, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
-          // layer 2
-          dw_tile<4, 4>(tb, d, h1, dw + ResGrad::o2, 64, ResGrad::L2, lane);
-          mm_t<4, 2>(rt + ResTShape::o2, d, tmp, lane);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
-          // layer 1: the pose term enters as a bias, so the bias gradient is
-          // the sum of d over the samples: gamma's unused input 27 is set to
-          // 1 here (it is 0 in the forward pass) and its column of dW1
-          // collects exactly that sum
-          f4 xb[2] = {x[0], x[1]};
-          if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
-          dw_tile<4, 2>(tb, d, xb, dw, 64, ResGrad::L1, lane);
-          mm_t<2, 2>(rt, d, tmp, lane);
-          dg2[0] += tmp[0];
-          dg2[1] += tmp[1];
+        for (int q = 0; q < 3; ++q) x3[q] = __shfl(xs[q], sl, WAVE);
+        f4 x[4];
+        float der[8];
+        int axis[8];
+        {
+          f4 v2[2];
+          res_posenc_lane(x3, win, g, v2, der, axis);
+          x[0] = slive ? v2[0] : z4;  // the forward pass fed zeros for samples that are not live
+          x[1] = slive ? v2[1] : z4;
+          x[2] = x[3] = z4;
         }
-        // dL/dgamma of the tile's samples: lane c + 16 g holds inputs 16 t + 4 g + e of sample c
+        // forward, as residual_step
+        f4 h1[4], h2[4], h3[4], h4[4], tmp[6];
+        mma_layer<MNR_BF16, 4, 2>(rl, x, h1, lane, bias);
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int mt = 0; mt < 4; ++mt) h1[mt] = relu4(h1[mt]);
+        mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o2, h1, h2, lane);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) dgam[(16 * nt + c) * 32 + 16 * t + 4 * g + e] = dg2[t][e];
-      }
-      wave_sync_lds();
-      if (live) {  // dL/dx_skel = dL/dx_final + (d gamma / d x_skel)^T dL/dgamma
-        const float* dgm = dgam + lane * 32;
-        float gs[3];
+        for (int mt = 0; mt < 4; ++mt) h2[mt] = relu4(h2[mt]);
+        mma_layer<MNR_BF16, 4, 4>(rl + ResShape::o3, h2, h3, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h3[mt] = relu4(h3[mt]);
+        const f4 cat[6] = {h3[0], h3[1], h3[2], h3[3], x[0], x[1]};
+        mma_layer<MNR_BF16, 4, 6>(rl + ResShape::o4, cat, h4, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h4[mt] = relu4(h4[mt]);
+        // output gradient: rows 0..2 of sample sl are dL/dx_res = dL/dx_final
+        const float q0 = __shfl(gf[0], sl, WAVE), q1 = __shfl(gf[1], sl, WAVE), q2 = __shfl(gf[2], sl, WAVE);
+        f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : z4, z4};
+        if (wave == 0) dw_tile<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, ResGrad::L5, lane);
+        f4 d[4], rows[1], dg2[2];
+        mm_t<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
+        // layer 4: input [h3; gamma]
+        rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, rows, h3, dw4, 16, ResGrad::L4, lane);
+        dw_tile<1, 2>(tb, rows, x, dw4 + 64, 16, ResGrad::L4, lane);
+        mm_t<6, 2>(rt + ResTShape::o4, d, tmp, lane);
+        dg2[0] = tmp[4];
+        dg2[1] = tmp[5];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
+        // layer 3
+        rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, rows, h2, dw3, 16, ResGrad::L3, lane);
+        mm_t<4, 2>(rt + ResTShape::o3, d, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
+        // layer 2
+        rows[0] = pick4(d, wave);
+        dw_tile<1, 4>(tb, rows, h1, dw2, 16, ResGrad::L2, lane);
+        mm_t<4, 2>(rt + ResTShape::o2, d, tmp, lane);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
+        // layer 1: the pose term enters as a bias, so the bias gradient is
+        // the sum of d over the samples: gamma's unused input 27 is set to
+        // 1 here (it is 0 in the forward pass) and its column of dW1
+        // collects exactly that sum
+        f4 xb[2] = {x[0], x[1]};
+        if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
+        rows[0] = pick4(d, wave);
+        dw_tile<1, 2>(tb, rows, xb, dw1, 16, ResGrad::L1, lane);
+        if (wave != 0) continue;
+        mm_t<2, 2>(rt, d, tmp, lane);
+        dg2[0] += tmp[0];
+        dg2[1] += tmp[1];
+        // dL/dx_skel of sample sl: the lane's 8 inputs, then the 4 lane groups
+        float gx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+          const float v = dg2[n >> 2][n & 3] * der[n];
+          gx[0] += axis[n] == 0 ? v : 0.f;
+          gx[1] += axis[n] == 1 ? v : 0.f;
+          gx[2] += axis[n] == 2 ? v : 0.f;
+        }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          float acc = gf[q] + dgm[q];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const float f = a.res.win[k] * (float)(1 << k) * 3.14159265358979f;
-            acc = fmaf(f * cs[k][q], dgm[3 + 6 * k + q], acc);
-            acc = fmaf(-f * sn[k][q], dgm[6 + 6 * k + q], acc);
-          }
-          gs[q] = acc;
+          gx[q] += __shfl_xor(gx[q], 16, WAVE);
+          gx[q] += __shfl_xor(gx[q], 32, WAVE);
         }
+        const float gq[3] = {q0, q1, q2};
+        if (g == 0 && slive)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) sb[(SPLIT_G + q) * ss + sj] = gs[q];
+          for (int q = 0; q < 3; ++q) sb[(SPLIT_GS + q) * ss + cj * 64 + sl] = gq[q] + gx[q];
       }
-      wave_sync_lds();
     }
   }
   __syncthreads();
@@ -263,7 +302,7 @@ __global__ void __launch_bounds__(64) res_bwd_kernel(const RenderArgs a, int n_s
   const int off[5] = {0, ResGrad::o2, ResGrad::o3, ResGrad::o4, ResGrad::o5};
 #pragma unroll
   for (int l = 0; l < 5; ++l)
-    for (int k = lane; k < rows[l] * cols[l]; k += 64) {
+    for (int k = threadIdx.x; k < rows[l] * cols[l]; k += blockDim.x) {
       const int r = k / cols[l], c = k - r * cols[l];
       const float v = dw[off[l] + r * ld[l] + c];
       if (v == 0.f) continue;
@@ -282,6 +321,7 @@ __global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderA
   const int nchunks = (a.r.spp + 63) >> 6;
   const float* sb = a.split.buf;
   const int64_t ss = a.split.stride;
+  const int gfield = a.res.w[0] ? SPLIT_GS : SPLIT_G;  // dL/dx_skel
   for (int slot = blockIdx.x * SKIN_WAVES + wave; slot < n_slots; slot += gridDim.x * SKIN_WAVES) {
     int orow, n_done;
     RaySetup rs;
@@ -300,7 +340,7 @@ __global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderA
         for (int q = 0; q < 3; ++q) {
           x[q] = sb[(SPLIT_X + q) * ss + sj];
           xs[q] = sb[(SPLIT_XS + q) * ss + sj];
-          gs[q] = sb[(SPLIT_G + q) * ss + sj];
+          gs[q] = sb[(gfield + q) * ss + sj];
         }
         gL = sb[SPLIT_GL * ss + sj];
       }
@@ -332,9 +372,9 @@ hipError_t launch_res_forward(const RenderArgs& a, int n_slots, hipStream_t st) 
 
 hipError_t launch_res_backward(const RenderArgs& a, int n_slots, hipStream_t st) {
   static PersistentGrid pg;
-  const int mb = persistent_blocks(res_bwd_kernel, 64, RES_BWD_LDS, pg);
-  hipLaunchKernelGGL(res_bwd_kernel, dim3(n_slots < mb ? (n_slots > 0 ? n_slots : 1) : mb), dim3(64), RES_BWD_LDS,
-                     st, a, n_slots);
+  const int mb = persistent_blocks(res_bwd_kernel, 64 * RES_BWD_WAVES, RES_BWD_LDS, pg);
+  hipLaunchKernelGGL(res_bwd_kernel, dim3(n_slots < mb ? (n_slots > 0 ? n_slots : 1) : mb),
+                     dim3(64 * RES_BWD_WAVES), RES_BWD_LDS, st, a, n_slots);
   hipLaunchKernelGGL(omega_grad_kernel, dim3(16), dim3(256), 0, st, a);
   return hipGetLastError();
 }

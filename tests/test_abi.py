@@ -214,7 +214,7 @@ def test_build_script_loads_without_the_package():
 def test_adjoint_workspace_size_and_checks():
     # Adjoint workspace: binned-scatter records for every sample, hashed
     # level and corner, twice, plus per-tile bin histograms; with a residual
-    # network or the frequency-encoded field, 18 floats per sample slot and
+    # network or the frequency-encoded field, 21 floats per sample slot and
     # 64 floats of bias gradient, and for the frequency-encoded field 512
     # bytes of saved activations per slot (include/metanerf.h).
     m = _lib()
@@ -232,7 +232,7 @@ def test_adjoint_workspace_size_and_checks():
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
         for k in range(6):
             mo.res_w[k] = 0x7000 + 0x100 * k
-        split = a256(18 * n_rays * -(-spp // 64) * 64 * 4) + 256
+        split = a256(21 * n_rays * -(-spp // 64) * 64 * 4) + 256
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split
         for k in range(6):
             mo.res_w[k] = None
@@ -244,7 +244,7 @@ def test_adjoint_workspace_size_and_checks():
         ff.w[k] = 0x9000 + 0x100 * k
     for n_rays, spp in ((8192, 128), (100, 7)):
         chunks = n_rays * -(-spp // 64)
-        want = a256(18 * chunks * 64 * 4) + 256 + chunks * 4 * 4 * 2 * 64 * 16
+        want = a256(21 * chunks * 64 * 4) + 256 + chunks * 4 * 4 * 2 * 64 * 16
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(ff), C.byref(mo), n_rays, spp) == want
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
     f.log2_T = 24       # the largest table: 4 hashed levels of 2^24 rows, 4096 slices of 2^14 rows
