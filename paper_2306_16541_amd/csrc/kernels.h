@@ -56,7 +56,7 @@ hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_
 
 // Binned scatter-add of the adjoint's hashed-level records (scatter.hip).
 constexpr int MAX_BINS = 4096;
-constexpr int MAX_BIN_SHIFT = 14;       // a bin's LDS slice: 2^14 rows x 2 floats = 128 KiB
+constexpr int MAX_BIN_SHIFT = 14;       // largest bin: 2^14 rows (summed in 2^12-row parts)
 constexpr int BIN_TILE_RECORDS = 8192;  // records per histogram / scatter block
 struct HashedLevels {  // the table level of each hashed level h (keys h * T + row)
   int32_t level[MNR_MAX_LEVELS];

@@ -137,7 +137,8 @@ __device__ __forceinline__ void accumulate_dw(typename BwdShape<P>::TB* tb, cons
 }
 
 // Add a wave's register sums (MT x NT tiles, rows < M_out) into the
-// block's LDS sums (row stride ld).
+// block's LDS sums (row stride ld), with plain read-add-write: the caller
+// lets one wave at a time do it.
 template <int MT, int NT>
 __device__ __forceinline__ void flush_dw(const f4 (&acc)[MT][NT], float* dw, int M_out, int ld, int lane) {
   const int c = lane & 15, g = lane >> 4;
@@ -148,7 +149,7 @@ __device__ __forceinline__ void flush_dw(const f4 (&acc)[MT][NT], float* dw, int
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = 16 * mt + 4 * g + j;
-        if (row < M_out) atomicAdd(dw + row * ld + 16 * kt + c, acc[mt][kt][j]);
+        if (row < M_out) dw[row * ld + 16 * kt + c] += acc[mt][kt][j];
       }
 }
 
@@ -438,11 +439,16 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       wave_sync_lds();
     }
   }
-  flush_dw(acc.out, dw + B::off_hidden(NHH), 4, B::LD_HID, lane);
+  // the waves' register sums into the block's LDS sums, one wave at a time
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+      flush_dw(acc.out, dw + B::off_hidden(NHH), 4, B::LD_HID, lane);
 #pragma unroll
-  for (int l = 0; l < NHH; ++l) flush_dw(acc.hid[l], dw + B::off_hidden(l), HIDDEN, B::LD_HID, lane);
-  flush_dw(acc.first, dw, HIDDEN, B::LD_FIRST, lane);
-  __syncthreads();
+      for (int l = 0; l < NHH; ++l) flush_dw(acc.hid[l], dw + B::off_hidden(l), HIDDEN, B::LD_HID, lane);
+      flush_dw(acc.first, dw, HIDDEN, B::LD_FIRST, lane);
+    }
+    __syncthreads();
+  }
   // flush the block's bone-transform gradients: every wave of every block
   // adds into the same few cache lines, so the sums stay in LDS until here
   if (a.grad_G)

@@ -17,12 +17,15 @@
 //   3. bin_scatter: each tile sorts its records by bin in LDS and writes
 //      them to their places, bin run by bin run;
 //   4. bin_accumulate: one block per bin sums its records into an LDS copy
-//      of the bin's slice with LDS atomics, then adds the slice to the
-//      table gradient (each slice has one owner: plain read-add-write).
+//      of the bin's slice (64-bit fixed point, integer LDS atomics), then
+//      adds the slice to the table gradient (each slice has one owner:
+//      plain read-add-write).
 // Keys count hashed levels only: key = h * T + row for the h-th hashed
 // level, so no bin is spent on the dense levels (which keep atomics).
 // Traffic is a few passes over the records (12 bytes each) instead of two
 // memory-side atomics per record.
+#include <cfloat>
+
 #include "kernels.h"
 
 namespace mnr {
@@ -32,11 +35,13 @@ constexpr int BIN_TILE = BIN_TILE_RECORDS;  // records per tile
 constexpr int BIN_PER_THREAD = BIN_TILE / BIN_THREADS;
 constexpr int SCAN_THREADS = 256;           // the per-bin scans
 constexpr int ACC_THREADS = 1024;           // the per-bin sums
+constexpr int ACC_SHIFT = 12;               // rows per summing block: 2^12 x 2 features x 8 bytes = 64 KiB of LDS
 
 int scatter_bin_shift(int64_t n_keys) {
-  // slices of 2^13 keys (64 KiB of gradient in LDS: two summing blocks per
-  // CU), larger only when that would make more than MAX_BINS of them
-  int shift = 13;
+  // bins of 2^12 keys (one summing block each, 64 KiB of fixed-point sums
+  // in LDS: two blocks per CU), larger only when that would make more than
+  // MAX_BINS of them (their blocks then sum 2^12-row parts)
+  int shift = ACC_SHIFT;
   while ((n_keys + ((int64_t)1 << shift) - 1) >> shift > MAX_BINS) ++shift;
   return shift;
 }
@@ -220,24 +225,54 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
   }
 }
 
-// One block per bin: LDS copy of the bin's gradient slice.  Key
-// h * T + row is row `row` of hashed level h, i.e. of table level
-// levels.level[h].
+// One block per bin (per 2^ACC_SHIFT-row part of a bin when bins are
+// larger): the slice's sums in LDS as 64-bit fixed point.  LDS float
+// atomics on this GPU are ~40x slower than integer ones, so every value is
+// scaled by a power of two chosen from the bin's largest magnitude and its
+// record count (n max 2^S < 2^62: no sum can overflow), rounded to an
+// integer and added with integer atomics.  The integer sums are exact, so
+// the result does not depend on the order of the records; each value is
+// rounded once, by at most 2^-(S+1).  A bin holding a non-finite value is
+// summed in floats instead.  Key h * T + row is row `row` of hashed level
+// h, i.e. of table level levels.level[h].
 __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint32_t* __restrict__ skeys,
                                                                      const f2* __restrict__ svals, int shift,
                                                                      int64_t n_keys, const uint32_t* __restrict__ total,
                                                                      const uint32_t* __restrict__ base,
                                                                      const HashedLevels levels,
                                                                      float* __restrict__ grad) {
-  extern __shared__ float acc[];  // [2][2^shift]: the two features in separate planes (row r: bank r mod 64)
-  const int b = blockIdx.x;
+  extern __shared__ unsigned long long acc[];  // [2][rows]: the two features in separate planes
+  __shared__ uint32_t max_bits;
+  const int parts_log2 = shift > ACC_SHIFT ? shift - ACC_SHIFT : 0;
+  const int b = blockIdx.x >> parts_log2, part = blockIdx.x & ((1 << parts_log2) - 1);
   const uint32_t n = total[b];
   if (n == 0) return;
-  const int rows = 1 << shift;
-  for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0.f;
+  const int rows = 1 << (shift - parts_log2);
+  const uint32_t lo = (uint32_t)part * rows, kmask = (1u << shift) - 1u;
+  const uint32_t s0 = base[b];
+  if (threadIdx.x == 0) max_bits = 0u;
+  for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0ull;
   __syncthreads();
-  const uint32_t s0 = base[b], mask = (uint32_t)rows - 1u;
-  const int lane = threadIdx.x & 63;
+  // pass 1: the largest magnitude among the part's values (non-negative
+  // floats order as their bit patterns; NaN sorts above infinity)
+  float mx = 0.f;
+  for (uint32_t i = threadIdx.x; i < n; i += ACC_THREADS) {
+    const uint32_t r = (skeys[s0 + i] & kmask) - lo;
+    const f2 v = svals[s0 + i];
+    if (r < (uint32_t)rows) mx = fmaxf(mx, fmaxf(fabsf(v[0]), fabsf(v[1])));
+    if (r < (uint32_t)rows && !(fabsf(v[0]) <= FLT_MAX && fabsf(v[1]) <= FLT_MAX)) mx = __uint_as_float(0x7F800000u);
+  }
+#pragma unroll
+  for (int k = WAVE / 2; k > 0; k >>= 1) mx = fmaxf(mx, __shfl_xor(mx, k, WAVE));
+  if ((threadIdx.x & 63) == 0) atomicMax(&max_bits, __float_as_uint(mx));
+  __syncthreads();
+  const float M = __uint_as_float(max_bits);
+  if (M == 0.f) return;  // every value of the part is zero
+  const bool fixed = M <= FLT_MAX;
+  int e = 0;
+  frexp((double)M * (double)n, &e);  // M n < 2^e
+  const double scale = ldexp(1.0, 62 - e);
+  float* accf = (float*)acc;  // float sums (a non-finite value in the part)
   constexpr int U = 8;  // records in flight per thread
   for (uint32_t i0 = 0; i0 < n; i0 += U * ACC_THREADS) {
     uint32_t r[U];
@@ -252,48 +287,23 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t i = i0 + u * ACC_THREADS + threadIdx.x;
-      r[u] = i < n ? r[u] & mask : 0xFFFFFFFFu;
-      v[u] = i < n ? v[u] : f2{0.f, 0.f};
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // Neighbouring records often carry the same row (consecutive samples
-      // of a ray in one cell): sum such runs across the wave first, so that
-      // one lane per run adds, instead of lanes queueing on one LDS address.
-      const uint32_t prev = __shfl_up(r[u], 1, WAVE);
-      const bool head = lane == 0 || prev != r[u];
-      const uint64_t heads = __ballot(head);
-      uint64_t z0 = ~heads;
-      int steps = 0;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        if (z0 == 0) break;
-        ++steps;
-        z0 &= z0 >> (1 << j);
-      }
-      if (steps) {
-        const int seg = (int)__popcll(heads & (~0ull >> (63 - lane)));
-        for (int j = 0; j < steps; ++j) {
-          const int d = 1 << j;
-          const int seg_d = __shfl_down(seg, d, WAVE);
-          const float o0 = __shfl_down(v[u][0], d, WAVE), o1 = __shfl_down(v[u][1], d, WAVE);
-          if (lane + d < WAVE && seg_d == seg) {
-            v[u][0] += o0;
-            v[u][1] += o1;
-          }
-        }
-      }
-      if (head && r[u] != 0xFFFFFFFFu) {
-        atomicAdd(&acc[r[u]], v[u][0]);
-        atomicAdd(&acc[rows + r[u]], v[u][1]);
+      const uint32_t row = (r[u] & kmask) - lo;
+      if (i >= n || row >= (uint32_t)rows) continue;
+      if (fixed) {
+        atomicAdd(&acc[row], (unsigned long long)(long long)rint((double)v[u][0] * scale));
+        atomicAdd(&acc[rows + row], (unsigned long long)(long long)rint((double)v[u][1] * scale));
+      } else {
+        atomicAdd(&accf[row], v[u][0]);
+        atomicAdd(&accf[rows + row], v[u][1]);
       }
     }
   }
   __syncthreads();
-  const int64_t k0 = (int64_t)b << shift;
+  const int64_t k0 = ((int64_t)b << shift) + lo;
   const uint32_t tmask = (1u << levels.log2_T) - 1u;
   for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
-    const f2 v = f2{acc[r], acc[rows + r]};
+    const f2 v = fixed ? f2{(float)((double)(long long)acc[r] / scale), (float)((double)(long long)acc[rows + r] / scale)}
+                       : f2{accf[r], accf[rows + r]};
     const int64_t key = k0 + r;
     if ((v[0] != 0.f || v[1] != 0.f) && key < n_keys) {
       const int h = (int)(key >> levels.log2_T);
@@ -305,9 +315,10 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
 }
 
 hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st) {
-  const int lds = (2 << p.shift) * (int)sizeof(float);
-  static PersistentGrid once_acc, once_sc;  // raise the LDS limits once (to the largest slice)
-  persistent_blocks(bin_accumulate_kernel, ACC_THREADS, (2 << MAX_BIN_SHIFT) * (int)sizeof(float), once_acc);
+  const int parts_log2 = p.shift > ACC_SHIFT ? p.shift - ACC_SHIFT : 0;
+  const int lds = (2 << (p.shift - parts_log2)) * (int)sizeof(unsigned long long);
+  static PersistentGrid once_acc, once_sc;  // raise the LDS limits once
+  persistent_blocks(bin_accumulate_kernel, ACC_THREADS, (2 << ACC_SHIFT) * (int)sizeof(unsigned long long), once_acc);
   persistent_blocks(bin_scatter_kernel, BIN_THREADS, SCATTER_LDS, once_sc);
   hipLaunchKernelGGL(bin_histogram_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), 0, st, p.cursor, p.cap, p.keys,
                      p.shift, p.n_bins, p.n_tiles_cap, p.hist);
@@ -317,8 +328,8 @@ hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStr
                      p.n_tiles_cap, p.total, p.base);
   hipLaunchKernelGGL(bin_scatter_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
                      p.keys, p.vals, p.shift, p.n_bins, p.n_tiles_cap, p.hist, p.skeys, p.svals);
-  hipLaunchKernelGGL(bin_accumulate_kernel, dim3(p.n_bins), dim3(ACC_THREADS), lds, st, p.skeys, p.svals, p.shift,
-                     p.n_keys, p.total, p.base, p.levels, grad_table);
+  hipLaunchKernelGGL(bin_accumulate_kernel, dim3(p.n_bins << parts_log2), dim3(ACC_THREADS), lds, st, p.skeys,
+                     p.svals, p.shift, p.n_keys, p.total, p.base, p.levels, grad_table);
   return hipGetLastError();
 }
 

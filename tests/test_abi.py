@@ -226,7 +226,7 @@ def test_adjoint_workspace_size_and_checks():
     for n_rays, spp in ((8192, 128), (100, 7)):
         cap = n_rays * spp * nh * 8
         n_keys = nh << 19                   # keys number the hashed levels only
-        n_bins = -(-n_keys // (1 << 13))      # slices of 2^13 rows
+        n_bins = -(-n_keys // (1 << 12))      # slices of 2^12 rows
         tiles = -(-cap // 8192)
         want = (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + 2 * a256(n_bins * 4))
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
