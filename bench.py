@@ -210,6 +210,18 @@ def ceilings(reps=5):
         ms = timed_launches.last_median
         out[f"float_atomics_64MiB_run{run}"] = {"G_atomics_per_s": (1 << 20) * 128 / (ms * 1e-3) / 1e9}
     del acc
+    # LDS operations (the adjoint's block sums): cycles per wave instruction per CU at 2.4 GHz
+    lb, li = 512, 2000
+    lbuf = torch.empty(lb * 1024, dtype=torch.float32, device="cuda")
+    lds = {}
+    for op, name in enumerate(m.PROBE_LDS_OPS):
+        timed_launches(lambda: m.probe_lds(op, li, lb, out=lbuf), reps, 1)
+        ms = timed_launches.last_median
+        lane_ops = lb * 1024 * li
+        lds[name] = {"G_lane_ops_per_s": lane_ops / (ms * 1e-3) / 1e9,
+                     "cycles_per_wave_op_per_CU": ms * 1e-3 * 2.4e9 / (lane_ops / 64 / 256)}
+    out["lds_ops"] = lds
+    del lbuf
     n_blocks, iters = 2048, 4000
     buf = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda")
     for dt, name, flop in ((m.F32, "mfma_f32_16x16x4", 2048), (m.BF16, "mfma_bf16_16x16x32", 16384)):
@@ -419,6 +431,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--quick", action="store_true", help="headline FP32 frame only (for profiling)")
+    ap.add_argument("--ceilings-only", action="store_true", help="the machine-ceiling probes only")
     ap.add_argument("--mixed-only", action="store_true", help="the mixed-precision 512x512 frame only (profiling)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--train-only", action="store_true", help="the 8192-ray training step only (profiling)")
@@ -445,6 +458,9 @@ def main():
         return
     if args.train_only:
         print(json.dumps({"train_step_8192x128": train_bench(args.steps, args.warmup)}))
+        return
+    if args.ceilings_only:
+        print(json.dumps({"ceilings": ceilings()}))
         return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench()}))

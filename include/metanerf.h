@@ -93,8 +93,7 @@ typedef enum { MNR_ENC_GRID = 0, MNR_ENC_FREQ = 1 } mnr_encoding;
  * h3 and gamma), mlp_dtype = MNR_BF16 (BF16 MFMA, FP32 accumulation); the
  * grid fields (n_levels .. table, dense_packed) are ignored.  It trains:
  * mnr_render_backward and mnr_train_step run its adjoint (split, through
- * the adjoint workspace, which it requires); the server returns
- * MNR_E_UNSUPPORTED for it. */
+ * the adjoint workspace, which it requires); the server serves it. */
 typedef struct {
   int32_t n_levels, n_feat, log2_T;
   int32_t level_res[MNR_MAX_LEVELS];
@@ -150,7 +149,7 @@ typedef struct {
    * Runs on BF16 MFMA with FP32 accumulation, so it needs mlp_dtype ==
    * MNR_BF16.  It trains (mnr_render_backward's grad_res, mnr_train_step's
    * res_* state; gradients reach W1..W5 and W_omega, not Omega); the server
-   * returns MNR_E_UNSUPPORTED when it is on. */
+   * serves it, conditioned on each request's pose. */
   const void* res_w[6];
   float res_alpha;
 } mnr_motion;

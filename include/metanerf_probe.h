@@ -8,7 +8,8 @@
  *   - small random gathers from a table of the grid encoding's size
  *     (the warp and encoding steps, Sec. 4.2 Eq. 9 and Sec. 4.4 Eq. 13);
  *   - a dense MFMA loop in the MLP's arithmetic types (the MLP of Eq. 13);
- *   - scattered float atomics (the adjoint's gradient scatter, Sec. 5.2);
+ *   - scattered float atomics (the adjoint's gradient scatter, Sec. 5.2),
+ *     in memory and in LDS (the adjoint's block sums);
  *   - the renderer's MLP run unfused, over features read from memory.
  * All run on the caller's stream; time them with events around the call.
  */
@@ -42,6 +43,17 @@ mnr_status mnr_probe_gather(const void* table, uint64_t table_bytes, int32_t row
  * atomics_per_lane; the buffer's sum grows by exactly that. */
 mnr_status mnr_probe_atomic(float* acc, uint32_t n_words, int32_t atomics_per_lane, int32_t n_lanes, int32_t run,
                             uint32_t seed, void* stream);
+
+/* LDS operations, the block sums of the adjoint: n_blocks blocks of 1024
+ * threads (4..4096) each zero an LDS array of 8192 words (32 KiB per
+ * type), then every thread performs `iters` (1..100000) operations on word
+ * (thread + 97 k) mod 8192 (consecutive lanes on consecutive words, no two
+ * lanes of a wave on one bank), op: 0 float atomic add, 1 32-bit integer
+ * atomic add, 2 64-bit integer atomic add (4096 words), 3 plain float
+ * read-add-write, 4 plain 32-bit store.  Lane operations issued =
+ * n_blocks * 1024 * iters.  out: dev float [n_blocks * 1024] (each thread's
+ * first word afterwards, so that nothing is optimised away). */
+mnr_status mnr_probe_lds(int32_t op, int32_t iters, int32_t n_blocks, float* out, void* stream);
 
 /* n_blocks blocks of 4 waves each run `iters` iterations of 4 independent
  * MFMA chains: F32 -> v_mfma_f32_16x16x4f32 (2048 FLOP each), BF16 ->

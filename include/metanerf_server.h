@@ -68,7 +68,13 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
 
 /* Register user `user` (0..1023) with a resident field and blend-weight
  * volume (dev pointers, caller-owned).  Every user of a server must share
- * the field format (dtypes, layer count).  MNR_E_OOM when the resident
+ * the field format: dtypes, layer count, encoding (grid or the
+ * frequency-encoded field) and whether the residual motion network is on
+ * (MNR_E_DTYPE otherwise; the residual network needs the BF16 MLP path,
+ * MNR_E_UNSUPPORTED).  The first user fixes the format, and this call then
+ * captures the server's two tick graphs on its streams (stream capture on
+ * the calling thread: no thread may synchronise the whole device while it
+ * runs).  MNR_E_OOM when the resident
  * bytes plus the outputs of queued and admitted requests would exceed the
  * budget (so that every queued request still fits once the ones ahead of
  * it finish); MNR_E_INVALID if the id is taken. */

@@ -119,6 +119,7 @@ _sig("mnr_probe_gather", C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint32
                                    C.c_void_p, C.c_void_p])
 _sig("mnr_probe_mfma", C.c_int, [C.c_int, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p])
 _sig("mnr_probe_atomic", C.c_int, [C.c_void_p, C.c_uint32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_void_p])
+_sig("mnr_probe_lds", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p])
 _sig("mnr_probe_mlp", C.c_int, [C.POINTER(Field), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p])
 _sig("mnr_train_step", C.c_int, _RENDER_COMMON + [C.c_void_p, C.POINTER(TrainState), C.c_void_p])
 
@@ -126,7 +127,7 @@ EXPORTED = ["mnr_status_str", "mnr_last_error", "mnr_version", "mnr_fk_bones", "
             "mnr_render_backward", "mnr_adjoint_ws_bytes",
             "mnr_mse_loss", "mnr_softmax_fwd", "mnr_softmax_bwd", "mnr_adam_step", "mnr_convert", "mnr_zero",
             "mnr_train_step", "mnr_motion_packed_bytes", "mnr_motion_pack", "mnr_field_packed_bytes", "mnr_field_pack",
-            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_probe_mlp", "mnr_fk_backward", "mnr_refiner_apply",
+            "mnr_probe_gather", "mnr_probe_mfma", "mnr_probe_atomic", "mnr_probe_lds", "mnr_probe_mlp", "mnr_fk_backward", "mnr_refiner_apply",
             "mnr_refiner_backward", "mnr_skel_cnn_act_floats", "mnr_skel_cnn_scratch_floats", "mnr_skel_cnn_forward",
             "mnr_skel_cnn_backward", "mnr_patch_rays"]
 
@@ -319,6 +320,16 @@ def probe_atomic(acc: torch.Tensor, atomics_per_lane: int, n_lanes: int, run: in
     """Scattered float-atomic ceiling probe (include/metanerf_probe.h)."""
     check(lib.mnr_probe_atomic(_ptr(acc), acc.numel(), atomics_per_lane, n_lanes, run, seed, _stream()),
           "probe_atomic")
+
+
+PROBE_LDS_OPS = ("float_atomic_add", "u32_atomic_add", "u64_atomic_add", "float_read_add_write", "store_b32")
+
+
+def probe_lds(op: int, iters: int, n_blocks: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """LDS operation throughput probe (include/metanerf_probe.h); op indexes PROBE_LDS_OPS."""
+    out = torch.empty(n_blocks * 1024, dtype=torch.float32, device="cuda") if out is None else out
+    check(lib.mnr_probe_lds(op, iters, n_blocks, _ptr(out), _stream()), "probe_lds")
+    return out
 
 
 def probe_mfma(dtype: int, iters: int, n_blocks: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -681,6 +681,24 @@ __device__ __forceinline__ f4 freq_tile(const char* wl, const char* feat, int nt
   return o[0];
 }
 
+// LDS bytes in front of the per-wave feature buffers: the field's MLP
+// weights, then (RES) the residual motion network's.
+template <int P, int NHH, bool RES, bool FREQ = false>
+constexpr int weight_lds_bytes() {
+  return (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)) + (RES ? ResShape::bytes() : 0);
+}
+
+// Per-wave feature buffer: the grid's 32 features, or gamma's 64 (FREQ).
+template <int P, bool FREQ>
+constexpr int feat_bytes() { return FREQ ? FreqShape::feat_bytes_per_wave() : MlpShape<P>::feat_bytes_per_wave(); }
+
+template <int P, int NHH, bool RES, bool FREQ = false>
+__device__ __forceinline__ void stage_all(char* wl, const RenderArgs& a) {
+  if constexpr (FREQ) stage_freq(wl, a.f);
+  else stage_weights<P, NHH>(wl, a.f);
+  if constexpr (RES) stage_residual(wl + (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)), a.res);
+}
+
 // PRE: the caller has already set st.xs (the point the field is queried at)
 // and st.L (0 for samples that are not live); the warp is skipped.
 template <typename TableT, int P, int NHH, bool RES = false, bool FREQ = false, bool PRE = false>

@@ -51,8 +51,8 @@ hipError_t launch_skin_backward(const RenderArgs& a, int n_slots, hipStream_t st
 hipError_t launch_freq_backward(const RenderArgs& a, int n_slots, hipStream_t st);
 
 // Server tick: render the (slot, tile) items of wt with the requests' descriptors.
-hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh,
-                        hipStream_t st);
+hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh, bool res,
+                        bool freq, hipStream_t st);
 
 // Binned scatter-add of the adjoint's hashed-level records (scatter.hip).
 constexpr int MAX_BINS = 4096;

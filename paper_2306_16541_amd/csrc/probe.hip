@@ -204,6 +204,49 @@ extern "C" mnr_status mnr_probe_atomic(float* acc, uint32_t n_words, int32_t ato
   return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_atomic launch: %s", hipGetErrorString(e));
 }
 
+// LDS operation throughput (the adjoint's block sums): one op per thread
+// per iteration on word (thread + 97 k) mod 8192.
+template <int OP>
+__global__ void __launch_bounds__(1024) probe_lds_kernel(int iters, float* __restrict__ out) {
+  __shared__ float sf[8192];
+  __shared__ uint32_t su[8192];
+  __shared__ unsigned long long s64[4096];
+  for (int i = threadIdx.x; i < 8192; i += blockDim.x) {
+    sf[i] = 0.f;
+    su[i] = 0u;
+  }
+  for (int i = threadIdx.x; i < 4096; i += blockDim.x) s64[i] = 0ull;
+  __syncthreads();
+  const float v = 1.0f + (float)threadIdx.x * 1e-7f;
+  for (int k = 0; k < iters; ++k) {
+    const uint32_t w = (threadIdx.x + 97u * (uint32_t)k) & 8191u;
+    if constexpr (OP == 0) atomicAdd(&sf[w], v);
+    if constexpr (OP == 1) atomicAdd(&su[w], 1u);
+    if constexpr (OP == 2) atomicAdd(&s64[w & 4095u], 1ull);
+    if constexpr (OP == 3) sf[w] += v;
+    if constexpr (OP == 4) sf[w] = v;
+  }
+  __syncthreads();
+  out[(size_t)blockIdx.x * 1024 + threadIdx.x] = sf[threadIdx.x] + (float)su[threadIdx.x] + (float)s64[threadIdx.x];
+}
+
+extern "C" mnr_status mnr_probe_lds(int32_t op, int32_t iters, int32_t n_blocks, float* out, void* stream) {
+  clear_error();
+  if (!out) return fail(MNR_E_INVALID, "probe_lds: null pointer");
+  if (op < 0 || op > 4) return fail(MNR_E_INVALID, "probe_lds: op must be 0..4");
+  if (iters < 1 || iters > 100000 || n_blocks < 4 || n_blocks > 4096) return fail(MNR_E_SHAPE, "probe_lds: bad sizes");
+  hipStream_t st = (hipStream_t)stream;
+  switch (op) {
+    case 0: hipLaunchKernelGGL(probe_lds_kernel<0>, dim3(n_blocks), dim3(1024), 0, st, iters, out); break;
+    case 1: hipLaunchKernelGGL(probe_lds_kernel<1>, dim3(n_blocks), dim3(1024), 0, st, iters, out); break;
+    case 2: hipLaunchKernelGGL(probe_lds_kernel<2>, dim3(n_blocks), dim3(1024), 0, st, iters, out); break;
+    case 3: hipLaunchKernelGGL(probe_lds_kernel<3>, dim3(n_blocks), dim3(1024), 0, st, iters, out); break;
+    default: hipLaunchKernelGGL(probe_lds_kernel<4>, dim3(n_blocks), dim3(1024), 0, st, iters, out); break;
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNR_OK : fail(MNR_E_HIP, "probe_lds launch: %s", hipGetErrorString(e));
+}
+
 extern "C" mnr_status mnr_probe_mfma(mnr_dtype dtype, int32_t iters, int32_t n_blocks, float* out, void* stream) {
   clear_error();
   if (!out) return fail(MNR_E_INVALID, "probe_mfma: null pointer");

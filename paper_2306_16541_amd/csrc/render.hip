@@ -62,23 +62,6 @@ __device__ __forceinline__ int n_iters(int nblk, int n_slots) {
   return (tiles_per_xcd * 256 + nb_min * NW - 1) / (nb_min * NW);
 }
 
-// LDS bytes in front of the per-wave feature buffers: the field's MLP
-// weights, then (RES) the residual motion network's.
-template <int P, int NHH, bool RES, bool FREQ = false>
-constexpr int weight_lds_bytes() {
-  return (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)) + (RES ? ResShape::bytes() : 0);
-}
-
-// Per-wave feature buffer: the grid's 32 features, or gamma's 64 (FREQ).
-template <int P, bool FREQ>
-constexpr int feat_bytes() { return FREQ ? FreqShape::feat_bytes_per_wave() : MlpShape<P>::feat_bytes_per_wave(); }
-
-template <int P, int NHH, bool RES, bool FREQ = false>
-__device__ __forceinline__ void stage_all(char* wl, const RenderArgs& a) {
-  if constexpr (FREQ) stage_freq(wl, a.f);
-  else stage_weights<P, NHH>(wl, a.f);
-  if constexpr (RES) stage_residual(wl + (FREQ ? FreqShape::bytes() : MlpShape<P>::bytes_total(NHH)), a.res);
-}
 
 template <typename TableT, int P, int NHH, int NW, bool RES, bool FREQ = false>
 __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a, int n_slots) {

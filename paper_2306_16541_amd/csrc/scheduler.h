@@ -49,6 +49,7 @@ class Scheduler {
     resident_ += bytes;
     return true;
   }
+  void release_resident(uint64_t bytes) { resident_ = bytes < resident_ ? resident_ - bytes : 0; }
 
   Submit submit(const Payload& p, int n_tiles, uint64_t out_bytes, int64_t t_arrive, uint64_t* ticket) {
     if (resident_ + out_bytes > budget_) {

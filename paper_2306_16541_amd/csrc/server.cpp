@@ -52,8 +52,12 @@ struct User {
 
 static uint64_t field_bytes(const mnr_field& f, const mnr_motion& m) {
   const uint64_t el = f.table_dtype == MNR_F32 ? 4 : 2, wl = f.mlp_dtype == MNR_F32 ? 4 : 2;
-  uint64_t b = (uint64_t)f.n_levels * ((uint64_t)1 << f.log2_T) * f.n_feat * el;
-  for (int k = 0; k < f.n_layers; ++k) b += (uint64_t)f.width[k] * f.width[k + 1] * wl;
+  const bool freq = f.encoding == MNR_ENC_FREQ;
+  uint64_t b = freq ? 0 : (uint64_t)f.n_levels * ((uint64_t)1 << f.log2_T) * f.n_feat * el;
+  for (int k = 0; k < f.n_layers; ++k)  // the frequency field's W4 takes [h3; gamma]: 64 x 128
+    b += (uint64_t)f.width[k] * f.width[k + 1] * (freq && k == 3 ? 2 : 1) * wl;
+  if (m.res_w[0])  // residual network, BF16: W1..W5 and W_omega
+    b += (uint64_t)(64 * 32 + 2 * 64 * 64 + 64 * 96 + 3 * 64 + 64 * 3 * m.n_bones) * 2;
   b += (uint64_t)(m.n_bones + 1) * m.res * m.res * m.res * 4;
   if (m.packed) b += mnr_motion_packed_bytes(m.res, m.n_bones);
   if (f.dense_packed) b += mnr_field_packed_bytes(&f);
@@ -75,6 +79,7 @@ struct mnr_server {
   bool have_format = false;
   mnr_dtype table_dt = MNR_F32, mlp_dt = MNR_F32;
   int nhh = 0;
+  bool res = false, freq = false;  // residual motion network; frequency-encoded field
   std::map<int, User> users;
   Sched* sched = nullptr;
   std::vector<TileRef> items;           // composition scratch of the next tick
@@ -94,6 +99,8 @@ struct mnr_server {
   int next_buf = 0;
 
   void loop();
+  hipError_t prepare_ticks();
+  void drop_ticks();
   bool retire_locked();
   bool admit_locked();
   bool launch_locked();
@@ -131,6 +138,42 @@ bool mnr_server::admit_locked() {
   return !adm.empty();
 }
 
+// The two tick graphs (tile-table upload + tick kernel, one per tick
+// buffer) for the field format, captured when the first user fixes it, on
+// the thread that registers that user: the scheduler thread then only
+// replays them, and a stream capture never runs while other threads of the
+// application synchronise their own work.
+hipError_t mnr_server::prepare_ticks() {
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e == hipSuccess) e = hipSetDevice(device);
+  for (int buf = 0; buf < 2 && e == hipSuccess; ++buf) {
+    hipStream_t sb = stream[buf];
+    hipGraph_t g = nullptr;
+    e = launch_serve(nullptr, nullptr, table_dt, mlp_dt, nhh, res, freq, sb);  // kernel set-up, no launch
+    if (e == hipSuccess) e = hipStreamBeginCapture(sb, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      e = hipMemcpyAsync(d_wt[buf], h_wt[buf], wt_bytes, hipMemcpyHostToDevice, sb);
+      if (e == hipSuccess) e = launch_serve(d_slots, d_wt[buf], table_dt, mlp_dt, nhh, res, freq, sb);
+      const hipError_t e2 = hipStreamEndCapture(sb, &g);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&graph[buf], g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+  }
+  if (e != hipSuccess) drop_ticks();
+  (void)hipSetDevice(prev);
+  return e;
+}
+
+void mnr_server::drop_ticks() {
+  for (int buf = 0; buf < 2; ++buf)
+    if (graph[buf]) {
+      (void)hipGraphExecDestroy(graph[buf]);
+      graph[buf] = nullptr;
+    }
+}
+
 // Tick composition is the scheduler's (Scheduler::compose); this uploads
 // the tile table and replays the buffer's captured graph.
 bool mnr_server::launch_locked() {
@@ -143,23 +186,8 @@ bool mnr_server::launch_locked() {
   w->counter = 0;
   w->n_items = n;
   hipStream_t sb = stream[buf];
-  if (!graph[buf]) {  // capture this buffer's tick once: table upload + tick kernel
-    hipGraph_t g = nullptr;
-    hipError_t e = launch_serve(nullptr, nullptr, table_dt, mlp_dt, nhh, sb);  // kernel set-up, no launch
-    if (e == hipSuccess) e = hipStreamBeginCapture(sb, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_wt[buf], h_wt[buf], wt_bytes, hipMemcpyHostToDevice, sb);
-    if (e == hipSuccess) e = launch_serve(d_slots, d_wt[buf], table_dt, mlp_dt, nhh, sb);
-    const hipError_t e2 = hipStreamEndCapture(sb, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&graph[buf], g, nullptr, nullptr, 0);
-    if (g) hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      set_error(e);
-      return true;  // the tick counts as in flight; the error path fails it
-    }
-  }
-  hipError_t e = hipSuccess;
-  if (copy_wait[buf]) {
+  hipError_t e = graph[buf] ? hipSuccess : hipErrorNotReady;  // captured by the first add_user
+  if (e == hipSuccess && copy_wait[buf]) {
     e = hipStreamWaitEvent(sb, copy_ev, 0);
     copy_wait[buf] = false;
   }
@@ -233,26 +261,35 @@ mnr_status mnr_server_create(uint64_t mem_budget, int32_t max_slots, int32_t til
 mnr_status mnr_server_add_user(mnr_server* s, int32_t user, const mnr_field* field, const mnr_motion* motion) {
   clear_error();
   if (!s || !field || !motion || !motion->weights) return fail(MNR_E_INVALID, "server: null argument");
-  if (motion->res_w[0]) return fail(MNR_E_UNSUPPORTED, "server: users with a residual motion network");
-  if (field->encoding != MNR_ENC_GRID) return fail(MNR_E_UNSUPPORTED, "server: users with a frequency-encoded field");
   if (user < 0 || user > 1023) return fail(MNR_E_INVALID, "server: user id out of range");
   if (mnr_status st = validate_field(field)) return st;
   const uint64_t bytes = field_bytes(*field, *motion);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->users.count(user)) return fail(MNR_E_INVALID, "server: user %d already registered", user);
+  const bool res = motion->res_w[0] != nullptr, freq = field->encoding == MNR_ENC_FREQ;
+  if (res && field->mlp_dtype != MNR_BF16)
+    return fail(MNR_E_UNSUPPORTED, "server: the residual motion network needs the BF16 MLP path");
   if (s->have_format && (field->table_dtype != s->table_dt || field->mlp_dtype != s->mlp_dt ||
-                         field->n_layers - 2 != s->nhh))
-    return fail(MNR_E_DTYPE, "server: every user must share the field format");
+                         field->n_layers - 2 != s->nhh || res != s->res || freq != s->freq))
+    return fail(MNR_E_DTYPE, "server: every user must share the field format (dtypes, layers, encoding, residual network)");
   if (!s->sched->reserve_resident(bytes))
     return fail(MNR_E_OOM, "server: user needs %llu bytes; %llu resident and %llu queued or in flight of %llu",
                 (unsigned long long)bytes, (unsigned long long)s->sched->resident_bytes(),
                 (unsigned long long)(s->sched->inflight_bytes() + s->sched->queued_bytes()),
                 (unsigned long long)s->sched->budget());
+  if (!s->have_format) {  // the first user fixes the format: capture the tick graphs for it
+    s->table_dt = field->table_dtype;
+    s->mlp_dt = field->mlp_dtype;
+    s->nhh = field->n_layers - 2;
+    s->res = res;
+    s->freq = freq;
+    if (const hipError_t e = s->prepare_ticks()) {
+      s->sched->release_resident(bytes);
+      return fail(MNR_E_HIP, "server: preparing the tick kernel: %s", hipGetErrorString(e));
+    }
+    s->have_format = true;
+  }
   s->users[user] = User{*field, *motion, bytes};
-  s->have_format = true;
-  s->table_dt = field->table_dtype;
-  s->mlp_dt = field->mlp_dtype;
-  s->nhh = field->n_layers - 2;
   return MNR_OK;
 }
 

@@ -157,6 +157,9 @@ static void test_new_user_cannot_strand_a_queued_request() {
   d.admit();                                        // a admitted, b queued (one slot)
   CHECK(!s.reserve_resident(200));                  // 400 + 500 + 200 > 1000
   CHECK(s.reserve_resident(100));
+  s.release_resident(100);                          // a registration that failed later gives it back
+  CHECK(s.resident_bytes() == 0);
+  CHECK(s.reserve_resident(100));
   d.run();
   CHECK(s.poll(a, nullptr, true) == S::POLL_DONE);
   CHECK(s.poll(b, nullptr, true) == S::POLL_DONE);

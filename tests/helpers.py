@@ -27,5 +27,16 @@ def gpu_render(sc, table_dtype=0, mlp_dtype=0, pixel_ids=None, ert_tau=1e-6, bg=
     return out.cpu().numpy()
 
 
-def oracle_render(sc, pixel_ids=None, bg=(0.0, 0.0, 0.0), xi=None, axis_angle=None, cam=None):
-    return oracle.render_image(sc, pixel_ids=pixel_ids, bg=bg, xi=xi, axis_angle=axis_angle, cam=cam).numpy()
+def oracle_render(sc, pixel_ids=None, bg=(0.0, 0.0, 0.0), xi=None, axis_angle=None, cam=None, freq=None,
+                  residual=None, alpha=4.0):
+    """freq: W1..W5 of the frequency-encoded field instead of the scene's
+    grid field; residual: (W1..W5, W_omega) of the residual motion network
+    at window position alpha."""
+    field = None
+    if freq is not None:
+        field = oracle.Field.from_scene(sc)
+        field.encoding = "freq"
+        field.mlp = [oracle.as64(w) for w in freq]
+    res = None if residual is None else {"weights": residual[0], "w_omega": residual[1], "alpha": alpha}
+    return oracle.render_image(sc, field=field, pixel_ids=pixel_ids, bg=bg, xi=xi, axis_angle=axis_angle, cam=cam,
+                               residual=res).numpy()

@@ -126,3 +126,78 @@ def test_memory_admission_and_rejections():
     st = srv.stats()
     assert st["rejected"] >= 3 and st["completed"] == 5
     srv.close()
+
+
+@pytest.mark.parametrize("kind", ["frequency", "residual"])
+def test_frequency_and_residual_users(kind):
+    # Users of the paper's own field (Sec. 4.4) or with the residual motion
+    # network (Sec. 4.3, conditioned on each request's pose): two users,
+    # requests interleaved over several ticks; each image equals the same
+    # request alone (bitwise) and mnr_render within 1e-6, and the first is
+    # within 45 dB of the FP64 oracle.
+    import dataclasses
+    import paper_2306_16541_amd as m
+    from helpers import oracle_render, psnr
+    users = []
+    for u in range(2):
+        sc = scenes.scene_body(H=64, W=64, spp=64, res=32, log2_T=16, seed=16541 + 70 + u)
+        if kind == "frequency":
+            ws = scenes.freq_field_weights(40 + u)
+            fld = m.DeviceField.frequency([m.convert(torch.as_tensor(w, device="cuda"), m.BF16) for w in ws],
+                                          m.softmax_fwd(torch.as_tensor(sc.logits, device="cuda")))
+            extra = {"freq": ws}
+        else:
+            fld, _ = m.upload_scene(sc, "cuda", 1, 2)
+            rw, w_omega = scenes.residual_weights(45 + u)
+            fld.set_residual(rw, w_omega, 4.0)
+            extra = {"residual": (rw, w_omega)}
+        users.append((sc, fld, extra))
+    srv = m.Server(mem_budget=4 << 30, max_slots=8, tiles_per_tick=64)
+    for u, (_, fld, _) in enumerate(users):
+        srv.add_user(u, fld)
+    spp = 64
+    reqs = []
+    for k, (h, w) in enumerate([(96, 80), (64, 64), (128, 96), (48, 112)]):
+        u = k % 2
+        p, c, hh, ww = _req(users[u][0], 20 + k, h, w)
+        o = torch.zeros(hh * ww, 4, device="cuda")
+        torch.cuda.synchronize()
+        reqs.append((u, k, p, c, hh, ww, o, srv.submit(u, p, c, hh, ww, spp, o)))
+    for r in reqs:
+        srv.wait(r[-1])
+    torch.cuda.synchronize()
+    for u, k, p, c, hh, ww, o, _ in reqs:
+        alone = torch.zeros(hh * ww, 4, device="cuda")
+        torch.cuda.synchronize()
+        srv.wait(srv.submit(u, p, c, hh, ww, spp, alone))
+        torch.cuda.synchronize()
+        assert torch.equal(alone, o), (kind, k)
+        ref = m.render(users[u][1], p, c, hh, ww, spp, m.make_opts())
+        torch.cuda.synchronize()
+        assert float((o - ref).abs().max()) <= 1e-6, (kind, k)
+    # the first request against the oracle
+    u, k, p, c, hh, ww, o, _ = reqs[0]
+    sc, _, extra = users[u]
+    sc_req = dataclasses.replace(sc, H=hh, W=ww, spp=spp)
+    pid = np.arange(0, hh * ww, 5)
+    want = oracle_render(sc_req, pixel_ids=pid, axis_angle=scenes.pose(20 + k, 0.3),
+                         cam=scenes.camera(hh, ww, yaw=0.3 * (20 + k)), **extra)
+    got = o.cpu().numpy()[pid]
+    q = psnr(got[:, :3], want[:, :3])
+    print(f"[server, {kind} users] request vs oracle: PSNR {q:.1f} dB", flush=True)
+    assert q >= 45.0
+    srv.close()
+
+
+def test_users_must_share_the_field_format():
+    import paper_2306_16541_amd as m
+    sc, fld = _user(16541 + 80)
+    sc2 = scenes.scene_body(H=64, W=64, spp=64, res=32, log2_T=16, seed=16541 + 81)
+    freq = m.DeviceField.frequency([m.convert(torch.as_tensor(w, device="cuda"), m.BF16)
+                                    for w in scenes.freq_field_weights(46)],
+                                   m.softmax_fwd(torch.as_tensor(sc2.logits, device="cuda")))
+    srv = m.Server(mem_budget=4 << 30, max_slots=8, tiles_per_tick=64)
+    srv.add_user(0, fld)
+    with pytest.raises(m.MnrError, match="format"):
+        srv.add_user(1, freq)
+    srv.close()
