@@ -66,6 +66,18 @@ def measured_traffic(key):
     return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024.0
 
 
+def add_traffic_rate(roof, kernel_ms):
+    """Beside the algorithmic rate (achieved / frac: every gather counted,
+    L1 and L2 hits included), the rate of the measured traffic beyond the
+    L2: traffic bytes per launch / kernel time, and its fraction of the HBM
+    peak (when the counters match the current sources)."""
+    if roof.get("traffic") and roof.get("bound") == "hbm":
+        rate = roof["traffic"] / (kernel_ms * 1e-3) / 1e9
+        roof["traffic_GB_per_s"] = rate
+        roof["traffic_frac"] = rate / HBM_PEAK_GBS
+    return roof
+
+
 def mlp_flops(widths):
     return 2 * sum(a * b for a, b in zip(widths[:-1], widths[1:]))
 
@@ -474,6 +486,7 @@ def main():
     widths = [32] + [w.shape[0] for w in sc.mlp]
     roof, roof2 = roofline(fp32, sc, "f32", "f32", widths)
     roof["traffic"] = measured_traffic("render_fwd_fp32_512x512x128")
+    add_traffic_rate(roof, fp32["kernel_ms"])
     nominal = sc.H * sc.W * sc.spp
     line = {
         "metric": METRIC,
@@ -500,8 +513,9 @@ def main():
         line["mixed_512"] = {
             "Msamples_per_s": nominal / (mixed["kernel_ms"] * 1e-3) / 1e6, "frames_per_s": 1e3 / mixed["kernel_ms"],
             "speedup_vs_fp32": fp32["kernel_ms"] / mixed["kernel_ms"], "dtype": "fp16 table, bf16 MLP (fp32 acc)",
-            "roofline": dict(roofline(mixed, sc, "f16", "bf16", widths)[0],
-                             traffic=measured_traffic("render_fwd_mixed_512x512x128"))}
+            "roofline": add_traffic_rate(dict(roofline(mixed, sc, "f16", "bf16", widths)[0],
+                                              traffic=measured_traffic("render_fwd_mixed_512x512x128")),
+                                         mixed["kernel_ms"])}
         # Residual non-rigid motion network on (all four bands open).
         rb = render_bench(sc, m.F16, m.BF16, args.steps, args.warmup, residual=(*scenes.residual_weights(21), 4.0))
         res_flop = 2 * (64 * 32 + 2 * 64 * 64 + 64 * 96 + 3 * 64)
