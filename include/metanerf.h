@@ -315,10 +315,14 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
  * adjoint at x_skel, passing per-sample values through the workspace.
  * adjoint_ws (dev, 256-byte aligned, adjoint_ws_bytes >=
  * mnr_adjoint_ws_bytes(field, motion, n_rays, spp); contents are scratch):
- *   - with hashed grid levels, their gradient leaves the adjoint as (row,
- *     value) records that are binned by table slice and summed in LDS,
- *     instead of one global float atomic per sample, corner and feature
- *     (the same sum in another order);
+ *   - with a grid-encoded field, the table gradient leaves the adjoint as
+ *     (row, value) records that are binned by table slice and summed in
+ *     LDS, instead of one global float atomic per sample, corner and
+ *     feature (the same sum in another order): every hashed level's, and
+ *     the dense levels' (one record per corner and run of consecutive
+ *     samples in one cell) when the hashed levels' T rows each plus the
+ *     dense levels' (N+1)^3 rows fit 4096 x 2^14 keys -- else the dense
+ *     levels keep run-summed atomics;
  *   - with a residual network or the frequency-encoded field, the split
  *     adjoint's per-sample values.
  * NULL: atomics for the table; with a residual network or the
@@ -332,11 +336,12 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                void* adjoint_ws, uint64_t adjoint_ws_bytes, void* stream);
 
 /* Bytes of the adjoint workspace for a batch of n_rays rays of spp samples:
- * binned-scatter records for every sample, hashed level and corner (12
- * bytes each, twice) plus bin histograms -- about 200 bytes per sample for
- * the 9 hashed levels of a 2^19-row, 16-level table, none when the batch
- * (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14 rows)
- * is too large for the binned path -- plus, with a residual network or the
+ * binned-scatter room for a record per sample, keyed level and corner (12
+ * bytes each, twice: 192 bytes per sample and keyed level) plus bin
+ * histograms and the summing items -- about 3.1 KB per sample for the 16
+ * levels of a 2^19-row table, none when the
+ * batch (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14
+ * rows) is too large for the binned path -- plus, with a residual network or the
  * frequency-encoded field, 84 bytes per sample slot (n_rays * ceil(spp / 64)
  * * 64 slots, rounded up to 256 bytes) and 256 bytes, and for the
  * frequency-encoded field 512 bytes more per sample slot (its saved hidden

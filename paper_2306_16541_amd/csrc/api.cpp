@@ -263,14 +263,7 @@ static mnr_status scratch_address(void** out) {
   return MNR_OK;
 }
 
-// ---- binned scatter of the hashed levels' table gradient (scatter.hip) ----
-
-static int hashed_levels(const mnr_field* f) {
-  if (f->encoding == MNR_ENC_FREQ) return 0;
-  int n = 0;
-  for (int l = 0; l < f->n_levels; ++l) n += level_is_dense(f, l) ? 0 : 1;
-  return n;
-}
+// ---- binned scatter of the table gradient (scatter.hip) ----
 
 static uint64_t align256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 
@@ -281,18 +274,59 @@ static int64_t layer_elems(const mnr_field* f, int k) {
   return (int64_t)f->width[k] * f->width[k + 1];
 }
 
-// Carves the caller's scatter workspace; returns its size (0: the field has
-// no hashed level, or the batch or table is too large for the binned path).
+// Rows of a dense level: (N+1)^3.
+static int64_t dense_rows(const mnr_field* f, int l) {
+  const int64_t n1 = (int64_t)f->level_res[l] + 1;
+  return n1 * n1 * n1;
+}
+
+// Key map of the binned scatter: the hashed levels (T keys each), then,
+// when the key space holds them too, the dense levels ((N+1)^3 keys each,
+// in level order); otherwise the dense levels keep run-summed atomics.
+// Returns the number of keys (0: no keyed level).
+static int64_t key_map(const mnr_field* f, KeyMap* map, bool* dense) {
+  KeyMap k{};
+  k.log2_T = f->log2_T;
+  if (f->encoding != MNR_ENC_GRID) return 0;
+  int64_t n_keys = 0;
+  for (int l = 0; l < f->n_levels; ++l)
+    if (!level_is_dense(f, l)) {
+      k.start[k.n] = (uint32_t)n_keys;
+      k.level[k.n++] = l;
+      n_keys += (int64_t)1 << f->log2_T;
+    }
+  int64_t all = n_keys;
+  for (int l = 0; l < f->n_levels; ++l)
+    if (level_is_dense(f, l)) all += dense_rows(f, l);
+  const bool with_dense = all <= ((int64_t)MAX_BINS << MAX_BIN_SHIFT);
+  if (with_dense)
+    for (int l = 0; l < f->n_levels; ++l)
+      if (level_is_dense(f, l)) {
+        k.start[k.n] = (uint32_t)n_keys;
+        k.level[k.n++] = l;
+        n_keys += dense_rows(f, l);
+      }
+  k.start[k.n] = (uint32_t)n_keys;
+  if (map) *map = k;
+  if (dense) *dense = with_dense;
+  return n_keys;
+}
+
+// Carves the caller's scatter workspace; returns its size (0: no keyed
+// level, or the batch or table is too large for the binned path).
 static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws, ScatterPlan* p) {
-  const int nh = hashed_levels(f);
-  if (nh == 0 || n_rays <= 0 || spp <= 0) return 0;
-  const uint64_t cap = (uint64_t)n_rays * spp * nh * 8;
+  KeyMap map;
+  bool dense = false;
+  const int64_t n_keys = key_map(f, &map, &dense);
+  if (n_keys == 0 || n_rays <= 0 || spp <= 0) return 0;
+  const uint64_t cap = (uint64_t)n_rays * spp * map.n * 8;
   if (cap >= ((uint64_t)1 << 31)) return 0;
-  const int64_t n_keys = (int64_t)nh << f->log2_T;
   const int shift = scatter_bin_shift(n_keys);
   if (shift > MAX_BIN_SHIFT) return 0;
   const int n_bins = (int)((n_keys + ((int64_t)1 << shift) - 1) >> shift);
   const int n_tiles = (int)((cap + BIN_TILE_RECORDS - 1) / BIN_TILE_RECORDS);
+  // a bin of t records is summed by ceil(t / ACC_PART_RECORDS) blocks
+  const int max_items = n_bins + (int)((cap + ACC_PART_RECORDS - 1) / ACC_PART_RECORDS);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t o = off;
@@ -307,6 +341,9 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
   char* hist = take((uint64_t)n_bins * n_tiles * 4);
   char* total = take((uint64_t)n_bins * 4);
   char* base = take((uint64_t)n_bins * 4);
+  char* item_base = take((uint64_t)n_bins * 4);
+  char* item_bin = take((uint64_t)max_items * 4);
+  char* n_items = take(4);
   if (p) {
     p->cursor = (uint32_t*)cursor;
     p->keys = (uint32_t*)keys;
@@ -316,15 +353,17 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
     p->hist = (uint32_t*)hist;
     p->total = (uint32_t*)total;
     p->base = (uint32_t*)base;
+    p->item_base = (uint32_t*)item_base;
+    p->item_bin = (uint32_t*)item_bin;
+    p->n_items = (uint32_t*)n_items;
     p->cap = (uint32_t)cap;
     p->shift = shift;
     p->n_bins = n_bins;
     p->n_tiles_cap = n_tiles;
+    p->max_items = max_items;
     p->n_keys = n_keys;
-    int h = 0;
-    for (int l = 0; l < f->n_levels; ++l)
-      if (!level_is_dense(f, l)) p->levels.level[h++] = l;
-    p->levels.log2_T = f->log2_T;
+    p->map = map;
+    p->dense = dense;
   }
   return off;
 }
@@ -364,7 +403,7 @@ static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_ra
 // Validates a caller's adjoint workspace and points the adjoint at it.
 static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
                                 uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp) {
-  rec = RecordSink{nullptr, nullptr, nullptr, 0};
+  rec = RecordSink{nullptr, nullptr, nullptr, 0, 0};
   sp = SplitArgs{nullptr, 0, nullptr, nullptr};
   if (!ws) {
     if (m->res_w[0]) return fail(MNR_E_INVALID, "the residual network's adjoint needs the adjoint workspace");
@@ -382,7 +421,7 @@ static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_r
                 (unsigned long long)need);
   if (scatter_layout(f, n_rays, spp, nullptr, nullptr)) {
     p = pp;
-    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap};
+    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0};
   }
   sp = ss;
   return MNR_OK;

@@ -86,6 +86,7 @@ struct RecordSink {
   uint32_t* keys;
   f2* vals;
   uint32_t cap;      // capacity in records
+  int32_t dense;     // 1: the dense levels leave as records too (keys after the hashed levels')
 };
 
 // Per-sample scratch of the split adjoint (used with the residual motion

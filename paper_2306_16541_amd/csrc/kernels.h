@@ -54,12 +54,15 @@ hipError_t launch_freq_backward(const RenderArgs& a, int n_slots, hipStream_t st
 hipError_t launch_serve(const RenderArgs* slots, WorkTable* wt, mnr_dtype table_dt, mnr_dtype mlp_dt, int nhh, bool res,
                         bool freq, hipStream_t st);
 
-// Binned scatter-add of the adjoint's hashed-level records (scatter.hip).
+// Binned scatter-add of the adjoint's table-gradient records (scatter.hip).
 constexpr int MAX_BINS = 4096;
 constexpr int MAX_BIN_SHIFT = 14;       // largest bin: 2^14 rows (summed in 2^12-row parts)
 constexpr int BIN_TILE_RECORDS = 8192;  // records per histogram / scatter block
-struct HashedLevels {  // the table level of each hashed level h (keys h * T + row)
+constexpr int ACC_PART_RECORDS = 65536; // records per summing block: larger bins are split
+struct KeyMap {  // keyed level j: keys [start[j], start[j + 1]) are rows 0, 1, ... of table level level[j]
   int32_t level[MNR_MAX_LEVELS];
+  uint32_t start[MNR_MAX_LEVELS + 1];
+  int32_t n;                 // keyed levels: the hashed ones (T keys each), then the dense ones ((N+1)^3 each)
   int32_t log2_T;
 };
 struct ScatterPlan {
@@ -71,10 +74,14 @@ struct ScatterPlan {
   uint32_t* hist;            // [n_bins][n_tiles_cap]
   uint32_t* total;           // [n_bins]
   uint32_t* base;            // [n_bins]
+  uint32_t* item_base;       // [n_bins] first summing item of each bin
+  uint32_t* item_bin;        // [max_items] bin of each summing item
+  uint32_t* n_items;         // summing items of this launch
   uint32_t cap;
-  int shift, n_bins, n_tiles_cap;
-  int64_t n_keys;            // hashed levels * T
-  HashedLevels levels;
+  int shift, n_bins, n_tiles_cap, max_items;
+  int64_t n_keys;            // keys of all keyed levels
+  KeyMap map;
+  bool dense;                // the dense levels are keyed too
 };
 int scatter_bin_shift(int64_t n_keys);
 hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st);

@@ -330,18 +330,32 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 #pragma unroll
       for (int q = 0; q < 3; ++q) u[q] = live ? u[q] : 0.f;
       const float* df = dfeat + lane * IN_FEAT;
-      // With a record sink, the hashed levels' gradient leaves as records
-      // (binned and summed after this kernel) instead of global atomics:
-      // one reservation per chunk, then for hashed level h and corner k the
-      // live lanes write records base + (8 h + k) n_live + rank.
-      uint32_t rec_base = 0, n_live = 0, rank = 0;
+      // With a record sink, the table gradient leaves as records (binned
+      // and summed after this kernel) instead of global atomics: one
+      // reservation per chunk, then for hashed level h and corner k the live
+      // lanes write records base + (8 h + k) n_live + rank; a dense level
+      // (when keyed) writes one record per corner and run of consecutive
+      // samples in one cell, after the hashed levels' records.  Keys: h T +
+      // row for hashed level h, then the dense levels' rows one level after
+      // the other ((N+1)^3 keys each).
+      uint32_t rec_base = 0, n_live = 0, rank = 0, n_hashed = 0;
       bool rec_ok = false;
       if (a.rec.keys) {
         const uint64_t lm = __ballot(live);
         n_live = (uint32_t)__popcll(lm);
         rank = (uint32_t)__popcll(lm & ((1ull << lane) - 1ull));
-        const uint32_t n_hashed = (uint32_t)__popc(~a.f.dense_mask & ((1u << a.f.n_levels) - 1u));
-        const uint32_t cnt = n_live * n_hashed * 8u;
+        n_hashed = (uint32_t)__popc(~a.f.dense_mask & ((1u << a.f.n_levels) - 1u));
+        uint32_t n_runs = 0;  // runs over the dense levels
+        if (a.rec.dense) {
+#pragma unroll 1
+          for (int l = 0; l < a.f.n_levels; ++l) {
+            if (!((a.f.dense_mask >> l) & 1u)) continue;
+            const GridCell gc = grid_cell(u, a.f.level_res[l]);
+            const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
+            n_runs += (uint32_t)__popcll(__ballot(live && cr.head));
+          }
+        }
+        const uint32_t cnt = (n_live * n_hashed + n_runs) * 8u;
         uint32_t b = 0;
         if (lane == 0 && cnt) b = atomicAdd(a.rec.cursor, cnt);
         rec_base = __builtin_amdgcn_readfirstlane(b);
@@ -375,6 +389,8 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           for (int q = 0; q < 3; ++q) g_u[q] = fmaf(gp[q], (float)N, g_u[q]);
         }
       }
+      uint32_t dense_off = 0;                       // runs of the dense levels written so far
+      uint32_t dense_key = n_hashed << a.f.log2_T;  // first key of the next dense level
 #pragma unroll 1
       for (int l = 0; l < a.f.n_levels; ++l) {
         const int N = a.f.level_res[l];
@@ -389,7 +405,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         if (a.rec.keys && !dense) {  // hashed level: records
           if (live && rec_ok) {
             const uint32_t h = (uint32_t)__popc(~a.f.dense_mask & ((1u << l) - 1u));
-            const uint32_t key0 = h << a.f.log2_T;  // keys number the hashed levels only
+            const uint32_t key0 = h << a.f.log2_T;  // the hashed levels take the first keys
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               const uint32_t idx = rec_base + (h * 8u + (uint32_t)k) * n_live + rank;
@@ -406,6 +422,23 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         for (int k = 0; k < 8; ++k) { v[2 * k] = wk[k] * d0; v[2 * k + 1] = wk[k] * d1; }
         const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
         run_sums<16>(cr, v);
+        if (a.rec.keys && a.rec.dense) {  // dense level: one record per corner and run
+          const uint64_t hm = __ballot(live && cr.head);
+          const uint32_t n_runs = (uint32_t)__popcll(hm);
+          if (live && cr.head && rec_ok) {
+            const uint32_t r = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
+            const uint32_t first = rec_base + n_live * n_hashed * 8u + dense_off * 8u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint32_t idx = first + (uint32_t)k * n_runs + r;
+              a.rec.keys[idx] = dense_key + grid_row(gc, N, dense, tmask, k);
+              a.rec.vals[idx] = f2{v[2 * k], v[2 * k + 1]};
+            }
+          }
+          dense_off += n_runs;
+          dense_key += (uint32_t)(N + 1) * (uint32_t)(N + 1) * (uint32_t)(N + 1);
+          continue;
+        }
         if (live && cr.head) {
           float* gt = a.grad_table + (size_t)l * T * 2;
 #pragma unroll

@@ -1,29 +1,34 @@
 // Binned scatter-add of the grid-table gradient (training, Sec. 5.2).
 //
-// The adjoint's gradient with respect to the hashed grid levels is a
-// scatter-add: every evaluated sample adds to 8 rows of each hashed level,
-// and the rows are spread over the whole table by the spatial hash, so
-// consecutive samples of a ray almost never share one.  Done with global
-// float atomics, which this GPU executes at the memory side at ~20 G/s, the
-// scatter costs more than the rest of the adjoint.  Instead the adjoint
-// writes one record (key, two feature gradients) per sample, hashed level
-// and corner, and the records are summed here without global float
-// atomics:
+// The adjoint's gradient with respect to the grid table is a scatter-add:
+// every evaluated sample adds to 8 rows of each level.  On the hashed levels
+// the rows are spread over the whole table by the spatial hash, so
+// consecutive samples of a ray almost never share one; on the dense levels
+// the adjoint first sums runs of consecutive samples in one cell.  Done with
+// global float atomics, which this GPU executes at the memory side at
+// ~20 G/s, the scatter costs more than the rest of the adjoint.  Instead the
+// adjoint writes one record (key, two feature gradients) per sample (per run
+// on a dense level), level and corner, and the records are summed here
+// without global float atomics:
 //   1. bin_histogram: per tile of records, a histogram of the key bins
 //      (a bin = 2^shift consecutive keys, up to a 128 KiB slice of the table
 //      gradient), written bin-major to H[bin][tile];
 //   2. bin_totals / bin_offsets: exclusive scan of H in (bin, tile) order,
-//      giving every (bin, tile) pair its place in bin order;
+//      giving every (bin, tile) pair its place in bin order, and the list of
+//      summing items (a bin of t records is ceil(t / ACC_PART_RECORDS)
+//      items: the coarse dense levels pack millions of records into a few
+//      bins);
 //   3. bin_scatter: each tile sorts its records by bin in LDS and writes
 //      them to their places, bin run by bin run;
-//   4. bin_accumulate: one block per bin sums its records into an LDS copy
+//   4. bin_accumulate: one block per item sums its records into an LDS copy
 //      of the bin's slice (64-bit fixed point, integer LDS atomics), then
-//      adds the slice to the table gradient (each slice has one owner:
-//      plain read-add-write).
-// Keys count hashed levels only: key = h * T + row for the h-th hashed
-// level, so no bin is spent on the dense levels (which keep atomics).
-// Traffic is a few passes over the records (12 bytes each) instead of two
-// memory-side atomics per record.
+//      adds the slice to the table gradient (a bin of one item has one
+//      owner: plain read-add-write; the items of a split bin add with float
+//      atomics, a few thousand per item).
+// The key map (KeyMap) numbers the hashed levels' rows (T keys per level),
+// then the dense levels' ((N+1)^3 keys per level), so no bin is spent on
+// rows a dense level does not have.  Traffic is a few passes over the
+// records (12 bytes each) instead of two memory-side atomics per record.
 #include <cfloat>
 
 #include "kernels.h"
@@ -77,9 +82,21 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_histogram_kernel(const uint32
     const uint32_t i = t0 + j * BIN_THREADS + threadIdx.x;
     k[j] = i < count ? k[j] >> shift : 0xFFFFFFFFu;
   }
+  // The dense levels' records come in long stretches of one bin: the lanes
+  // that share the first lane's bin add once, through one lane.
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
 #pragma unroll
-  for (int j = 0; j < BIN_PER_THREAD; ++j)
-    if (k[j] < (uint32_t)n_bins) atomicAdd(&hist[k[j]], 1u);  // keys are < n_keys by construction
+  for (int j = 0; j < BIN_PER_THREAD; ++j) {
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(k[j]);
+    const bool same = k[j] == b0;
+    const uint64_t m = __ballot(same);
+    if (k[j] < (uint32_t)n_bins) {  // keys are < n_keys by construction
+      if (!same)
+        atomicAdd(&hist[k[j]], 1u);
+      else if (lane == __ffsll((unsigned long long)m) - 1)
+        atomicAdd(&hist[b0], (uint32_t)__popcll(m));
+    }
+  }
   __syncthreads();
   for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) H[(size_t)b * n_tiles_cap + tile] = hist[b];
 }
@@ -108,20 +125,40 @@ __global__ void __launch_bounds__(SCAN_THREADS) bin_totals_kernel(const uint32_t
   if (threadIdx.x == 0) total[blockIdx.x] = s;
 }
 
+// Summing items of a bin of n records.
+__device__ __forceinline__ uint32_t bin_items(uint32_t n) {
+  return (n + ACC_PART_RECORDS - 1) / ACC_PART_RECORDS;
+}
+
 // base[b] = records in bins before b; H[b][t] becomes the place of tile t's
-// first record of bin b (exclusive scan in (bin, tile) order).
+// first record of bin b (exclusive scan in (bin, tile) order).  Items:
+// item_base[b] = items of the bins before b, item_bin[item_base[b] + j] = b
+// for the bin's items j, and the last bin's block writes the item count.
 __global__ void __launch_bounds__(SCAN_THREADS) bin_offsets_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
                                                                   uint32_t* __restrict__ H, int n_tiles_cap,
                                                                   const uint32_t* __restrict__ total,
-                                                                  uint32_t* __restrict__ base) {
+                                                                  uint32_t* __restrict__ base,
+                                                                  uint32_t* __restrict__ item_base,
+                                                                  uint32_t* __restrict__ item_bin,
+                                                                  uint32_t* __restrict__ n_items) {
   __shared__ uint32_t red[SCAN_THREADS / WAVE];
   __shared__ uint32_t scan[SCAN_THREADS];
   const int b = blockIdx.x;
   const int n_tiles = (int)((record_count(cursor, cap) + BIN_TILE - 1) / BIN_TILE);
-  uint32_t s = 0;
-  for (int k = threadIdx.x; k < b; k += SCAN_THREADS) s += total[k];
+  uint32_t s = 0, q = 0;
+  for (int k = threadIdx.x; k < b; k += SCAN_THREADS) {
+    s += total[k];
+    q += bin_items(total[k]);
+  }
   uint32_t carry = block_sum_u32(s, red);
-  if (threadIdx.x == 0) base[b] = carry;
+  const uint32_t first_item = block_sum_u32(q, red);
+  const uint32_t my_items = bin_items(total[b]);
+  if (threadIdx.x == 0) {
+    base[b] = carry;
+    item_base[b] = first_item;
+    if (b == (int)gridDim.x - 1) *n_items = first_item + my_items;
+  }
+  for (uint32_t j = threadIdx.x; j < my_items; j += SCAN_THREADS) item_bin[first_item + j] = (uint32_t)b;
   uint32_t* row = H + (size_t)b * n_tiles_cap;
   for (int t0 = 0; t0 < n_tiles; t0 += SCAN_THREADS) {
     const int t = t0 + threadIdx.x;
@@ -173,10 +210,25 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
     k[j] = i < n_here ? keys[t0 + i] : 0xFFFFFFFFu;
     v[j] = i < n_here ? vals[t0 + i] : f2{0.f, 0.f};
   }
+  // ranks within the bin; the lanes that share the first lane's bin take
+  // one block of consecutive ranks through one lane (in lane order)
+  const int lane = (int)(threadIdx.x & (WAVE - 1));
 #pragma unroll
   for (int j = 0; j < BIN_PER_THREAD; ++j) {
     const uint32_t b = k[j] >> shift;
-    rank[j] = b < (uint32_t)n_bins ? atomicAdd(&cur[b], 1u) : 0u;
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+    const bool same = b == b0;
+    const uint64_t m = __ballot(same);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t got = 0;
+    if (b < (uint32_t)n_bins) {
+      if (!same)
+        got = atomicAdd(&cur[b], 1u);
+      else if (lane == leader)
+        got = atomicAdd(&cur[b], (uint32_t)__popcll(m));
+    }
+    const uint32_t first = __shfl(got, leader, WAVE);
+    rank[j] = same ? first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)) : got;
   }
   __syncthreads();
   // exclusive scan of the counts: start[b]
@@ -225,35 +277,43 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
   }
 }
 
-// One block per bin (per 2^ACC_SHIFT-row part of a bin when bins are
-// larger): the slice's sums in LDS as 64-bit fixed point.  LDS float
-// atomics on this GPU are ~40x slower than integer ones, so every value is
-// scaled by a power of two chosen from the bin's largest magnitude and its
-// record count (n max 2^S < 2^62: no sum can overflow), rounded to an
-// integer and added with integer atomics.  The integer sums are exact, so
-// the result does not depend on the order of the records; each value is
-// rounded once, by at most 2^-(S+1).  A bin holding a non-finite value is
-// summed in floats instead.  Key h * T + row is row `row` of hashed level
-// h, i.e. of table level levels.level[h].
+// One block per item of a bin (and per 2^ACC_SHIFT-row part of the bin when
+// bins are larger): the slice's sums in LDS as 64-bit fixed point.  LDS
+// float atomics on this GPU are ~40x slower than integer ones, so every
+// value is scaled by a power of two chosen from the item's largest magnitude
+// and its record count (n max 2^S < 2^62: no sum can overflow), rounded to
+// an integer and added with integer atomics.  The integer sums are exact, so
+// a bin summed by one item does not depend on the order of its records;
+// each value is rounded once, by at most 2^-(S+1).  The items of a split bin
+// add their (exact) sums to the table gradient with float atomics.  An item
+// holding a non-finite value is summed in floats instead.  Keys map to
+// table rows through the key map.
 __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint32_t* __restrict__ skeys,
                                                                      const f2* __restrict__ svals, int shift,
                                                                      int64_t n_keys, const uint32_t* __restrict__ total,
                                                                      const uint32_t* __restrict__ base,
-                                                                     const HashedLevels levels,
-                                                                     float* __restrict__ grad) {
+                                                                     const uint32_t* __restrict__ item_base,
+                                                                     const uint32_t* __restrict__ item_bin,
+                                                                     const uint32_t* __restrict__ n_items,
+                                                                     const KeyMap map, float* __restrict__ grad) {
   extern __shared__ unsigned long long acc[];  // [2][rows]: the two features in separate planes
   __shared__ uint32_t max_bits;
   const int parts_log2 = shift > ACC_SHIFT ? shift - ACC_SHIFT : 0;
-  const int b = blockIdx.x >> parts_log2, part = blockIdx.x & ((1 << parts_log2) - 1);
-  const uint32_t n = total[b];
-  if (n == 0) return;
+  const uint32_t item = blockIdx.x >> parts_log2;
+  const int part = blockIdx.x & ((1 << parts_log2) - 1);
+  if (item >= *n_items) return;
+  const uint32_t b = item_bin[item];
+  const uint32_t n_bin = total[b];
+  const uint32_t r0 = (item - item_base[b]) * (uint32_t)ACC_PART_RECORDS;  // the item's first record in the bin
+  const uint32_t n = min(n_bin - r0, (uint32_t)ACC_PART_RECORDS);
+  const bool shared = n_bin > (uint32_t)ACC_PART_RECORDS;  // other items add to the same rows
   const int rows = 1 << (shift - parts_log2);
   const uint32_t lo = (uint32_t)part * rows, kmask = (1u << shift) - 1u;
-  const uint32_t s0 = base[b];
+  const uint32_t s0 = base[b] + r0;
   if (threadIdx.x == 0) max_bits = 0u;
   for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0ull;
   __syncthreads();
-  // pass 1: the largest magnitude among the part's values (non-negative
+  // pass 1: the largest magnitude among the item's values (non-negative
   // floats order as their bit patterns; NaN sorts above infinity)
   float mx = 0.f;
   for (uint32_t i = threadIdx.x; i < n; i += ACC_THREADS) {
@@ -267,12 +327,12 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   if ((threadIdx.x & 63) == 0) atomicMax(&max_bits, __float_as_uint(mx));
   __syncthreads();
   const float M = __uint_as_float(max_bits);
-  if (M == 0.f) return;  // every value of the part is zero
+  if (M == 0.f) return;  // every value of the item is zero
   const bool fixed = M <= FLT_MAX;
   int e = 0;
   frexp((double)M * (double)n, &e);  // M n < 2^e
   const double scale = ldexp(1.0, 62 - e);
-  float* accf = (float*)acc;  // float sums (a non-finite value in the part)
+  float* accf = (float*)acc;  // float sums (a non-finite value in the item)
   constexpr int U = 8;  // records in flight per thread
   for (uint32_t i0 = 0; i0 < n; i0 += U * ACC_THREADS) {
     uint32_t r[U];
@@ -300,16 +360,21 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   }
   __syncthreads();
   const int64_t k0 = ((int64_t)b << shift) + lo;
-  const uint32_t tmask = (1u << levels.log2_T) - 1u;
   for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
     const f2 v = fixed ? f2{(float)((double)(long long)acc[r] / scale), (float)((double)(long long)acc[rows + r] / scale)}
                        : f2{accf[r], accf[rows + r]};
     const int64_t key = k0 + r;
     if ((v[0] != 0.f || v[1] != 0.f) && key < n_keys) {
-      const int h = (int)(key >> levels.log2_T);
-      const int64_t row = (int64_t)levels.level[h] * ((int64_t)tmask + 1) + (key & tmask);
-      f2* g = (f2*)grad + row;
-      *g = *g + v;
+      int j = 0;
+      while (j + 1 < map.n && (uint32_t)key >= map.start[j + 1]) ++j;
+      const int64_t row = ((int64_t)map.level[j] << map.log2_T) + ((uint32_t)key - map.start[j]);
+      float* g = grad + 2 * row;
+      if (shared) {
+        unsafeAtomicAdd(g, v[0]);
+        unsafeAtomicAdd(g + 1, v[1]);
+      } else {
+        *(f2*)g = *(f2*)g + v;
+      }
     }
   }
 }
@@ -325,11 +390,12 @@ hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStr
   hipLaunchKernelGGL(bin_totals_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
                      p.n_tiles_cap, p.total);
   hipLaunchKernelGGL(bin_offsets_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
-                     p.n_tiles_cap, p.total, p.base);
+                     p.n_tiles_cap, p.total, p.base, p.item_base, p.item_bin, p.n_items);
   hipLaunchKernelGGL(bin_scatter_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
                      p.keys, p.vals, p.shift, p.n_bins, p.n_tiles_cap, p.hist, p.skeys, p.svals);
-  hipLaunchKernelGGL(bin_accumulate_kernel, dim3(p.n_bins << parts_log2), dim3(ACC_THREADS), lds, st, p.skeys,
-                     p.svals, p.shift, p.n_keys, p.total, p.base, p.levels, grad_table);
+  hipLaunchKernelGGL(bin_accumulate_kernel, dim3((unsigned)p.max_items << parts_log2), dim3(ACC_THREADS), lds, st,
+                     p.skeys, p.svals, p.shift, p.n_keys, p.total, p.base, p.item_base, p.item_bin, p.n_items, p.map,
+                     grad_table);
   return hipGetLastError();
 }
 

@@ -212,8 +212,11 @@ def test_build_script_loads_without_the_package():
 
 
 def test_adjoint_workspace_size_and_checks():
-    # Adjoint workspace: binned-scatter records for every sample, hashed
-    # level and corner, twice, plus per-tile bin histograms; with a residual
+    # Adjoint workspace: binned-scatter records for every sample, level and
+    # corner (the dense levels are keyed too while hashed levels x T plus
+    # dense rows fit the key space), twice, plus per-tile bin histograms, the
+    # per-bin totals and places and the summing items (a bin of t records is
+    # ceil(t / 65536) items); with a residual
     # network or the frequency-encoded field, 21 floats per sample slot and
     # 64 floats of bias gradient, and for the frequency-encoded field 512
     # bytes of saved activations per slot (include/metanerf.h).
@@ -223,12 +226,17 @@ def test_adjoint_workspace_size_and_checks():
     nh = sum(1 for n in sc.level_res if (int(n) + 1) ** 3 > 1 << 19)
     assert nh == 9
     a256 = lambda b: (b + 255) // 256 * 256
+    nk = len(sc.level_res)                 # every level is keyed
+    dense_rows = sum((int(n) + 1) ** 3 for n in sc.level_res if (int(n) + 1) ** 3 <= 1 << 19)
+    assert dense_rows == 4913 + 9261 + 17576 + 35937 + 68921 + 132651 + 274625
     for n_rays, spp in ((8192, 128), (100, 7)):
-        cap = n_rays * spp * nh * 8
-        n_keys = nh << 19                   # keys number the hashed levels only
+        cap = n_rays * spp * nk * 8
+        n_keys = (nh << 19) + dense_rows       # hashed levels' keys, then the dense levels' rows
         n_bins = -(-n_keys // (1 << 12))      # slices of 2^12 rows
         tiles = -(-cap // 8192)
-        want = (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + 2 * a256(n_bins * 4))
+        items = n_bins + -(-cap // 65536)
+        want = (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + 3 * a256(n_bins * 4) +
+                a256(items * 4) + a256(4))
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
         for k in range(6):
             mo.res_w[k] = 0x7000 + 0x100 * k
@@ -247,7 +255,7 @@ def test_adjoint_workspace_size_and_checks():
         want = a256(21 * chunks * 64 * 4) + 256 + chunks * 4 * 4 * 2 * 64 * 16
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(ff), C.byref(mo), n_rays, spp) == want
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
-    f.log2_T = 24       # the largest table: 4 hashed levels of 2^24 rows, 4096 slices of 2^14 rows
+    f.log2_T = 24       # the largest table: its 4 hashed levels fill the key space (4096 slices of 2^14 rows), dense levels keep atomics
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 64, 8) > 0
     f.log2_T = 19
     gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)

@@ -46,8 +46,8 @@ def _rays(sc, n=16):
 
 
 def gpu_grads(sc, pid, tgt, mlp_dtype, ert_tau=1e-6, binned=False):
-    """binned: the hashed levels' table gradient goes through the binned
-    scatter (records summed in LDS) instead of global atomics."""
+    """binned: the table gradient goes through the binned scatter (records
+    summed in LDS) instead of global atomics."""
     import paper_2306_16541_amd as m
     fld, _ = m.upload_scene(sc, "cuda", m.F32, mlp_dtype)
     pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
@@ -244,9 +244,9 @@ def test_adjoint_on_the_full_size_field():
 
 
 def test_binned_scatter_equals_atomic_scatter():
-    # The same adjoint with the hashed levels' gradient summed through the
-    # binned scatter and through global atomics: the same sums in another
-    # order (float32 reassociation only), on a batch of 512 rays.
+    # The same adjoint with the table gradient summed through the binned
+    # scatter and through global atomics: the same sums in another order
+    # (float32 reassociation only), on a batch of 512 rays.
     sc = scenes.scene_body(H=64, W=64, spp=128, res=32, log2_T=16, seed=16541 + 4)
     g = np.random.default_rng(9)
     pid = g.integers(0, sc.H * sc.W, 512).astype(np.int32)
@@ -261,6 +261,28 @@ def test_binned_scatter_equals_atomic_scatter():
     assert err <= 1e-5
     for x, y in zip(a[2], b[2]):       # the other gradients are untouched by the switch
         assert float(np.abs(x - y).max()) <= 1e-5 * float(np.abs(x).max())
+
+
+def test_binned_scatter_splits_crowded_bins():
+    # The full-size field's coarse dense levels put hundreds of thousands of
+    # records into one 4096-row bin (level 0 has 17^3 rows), which the
+    # binned scatter sums with several blocks; against global atomics, level
+    # by level, on 4096 rays of the training batch.
+    sc = scenes.scene_body()
+    pid, tgt = scenes.train_batch(7, sc.H, sc.W, 8192)
+    pid, tgt = pid[:4096], tgt[:4096]
+    a = gpu_grads(sc, pid, tgt, 0, binned=False)
+    b = gpu_grads(sc, pid, tgt, 0, binned=True)
+    assert abs(a[0] - b[0]) <= 1e-6 * abs(a[0])
+    for l, n in enumerate(sc.level_res):
+        ta, tb = a[1][l], b[1][l]
+        mx = float(np.abs(ta).max())
+        err = float(np.abs(ta - tb).max()) / mx
+        if l in (0, 6, 7, 15):
+            print(f"  level {l} (N={int(n)}, {'dense' if (int(n) + 1) ** 3 <= 1 << 19 else 'hashed'}): "
+                  f"max diff {err:.2e} of max, {int((ta != 0).sum())} nonzero entries", flush=True)
+        assert mx > 0, l
+        assert err <= 1e-5, (l, err)
 
 
 @pytest.mark.parametrize("ert_tau", [0.0, 1e-6])
