@@ -62,22 +62,63 @@ __device__ __forceinline__ void run_sums(const CellRuns& r, float (&v)[NV]) {
   }
 }
 
+// Corner pair q of a weight-volume cell (corners 2q at x0 and 2q + 1 at
+// x0 + 1, both at y0 + (q & 1), z0 + (q >> 1)) has a corner inside the
+// volume.  Points far from a bone map far outside its volume, so most
+// cells of most bones have none.
+__device__ __forceinline__ bool wc_pair_inside(const Tri& t, int R, int q) {
+  return (unsigned)(t.i0[1] + (q & 1)) < (unsigned)R && (unsigned)(t.i0[2] + (q >> 1)) < (unsigned)R &&
+         t.i0[0] >= -1 && t.i0[0] < R;
+}
+
+// Blend-weight gradient records of one chunk: per bone and run of live
+// lanes in one cell of that bone's weight volume, one per corner pair with a
+// corner inside the volume.  Computes the cells exactly as skin_adjoint
+// does (the same explicit-FMA transform and cell rounding), so the count
+// matches what it writes; skin_adjoint still never writes past the count.
+__device__ __forceinline__ uint32_t wc_record_count(const RenderArgs& a, const float x[3], bool live) {
+  uint32_t n = 0;
+#pragma unroll 1
+  for (int b = 0; b < a.m.n_bones; ++b) {
+    float y[3];
+    bone_apply(a.G[b], x, y);
+    const Tri t = bone_cell(a.m, y);
+    const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      n += (uint32_t)__popcll(__ballot(live && cr.head && wc_pair_inside(t, a.m.res, q)));
+  }
+  return n;
+}
+
+// Where skin_adjoint writes the chunk's blend-weight records: [base, end)
+// (records == false: global atomics).
+struct WcRecords {
+  bool records;
+  uint32_t base, end;
+};
+
 // Skinning adjoint (Eq. 7, 9) of one sample per lane.  x: observed point,
 // xs: x_skel, L: the weight sum, g_xs: dL/dx_skel, g_L: dL/dL (the
 // likelihood factor alpha' = alpha min(L, 1)).  Per bone i:
 // dL/dw_i = dL/dx_skel . (y_i - x_skel) / L + dL/dL, scattered through the
-// trilinear weights into dL/dW^c (runs of lanes in one cell summed first);
-// optionally dL/dG_i into the block's LDS sums dg[n_bones][12].  Every lane
-// of the wave takes part (the run detection shuffles across it); lanes that
-// are not live contribute nothing.
+// trilinear weights into dL/dW^c (runs of lanes in one cell summed first;
+// global atomics, or records for the binned scatter laid out bone after
+// bone and corner pair after corner pair, one per run with a corner of the
+// pair inside the volume); optionally dL/dG_i into
+// the block's LDS sums dg[n_bones][12].  Every lane of the wave takes part
+// (the run detection shuffles across it); lanes that are not live
+// contribute nothing.
 __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[3], const float xs[3], float L,
-                                             const float g_xs[3], float g_L, bool live, float* dg) {
+                                             const float g_xs[3], float g_L, bool live, float* dg,
+                                             const WcRecords wr = WcRecords{false, 0u, 0u}) {
   const int lane = lane_id();
   const int R = a.m.res;
   const size_t plane = (size_t)R * R * R;
   const bool above = L > EPS_L;
   const float invL = 1.f / (above ? L : EPS_L);
   const float gL = live ? g_L : 0.f;
+  uint32_t wc_off = wr.base;  // next record of the chunk
 #pragma unroll 1
   for (int b = 0; b < a.m.n_bones; ++b) {
     float y[3];
@@ -120,7 +161,27 @@ __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[
     }
     const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
     run_sums<8>(cr, v);
-    if (live && cr.head) {
+    if (wr.records) {
+      const int x0 = t.i0[0];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // pair q: corners 2q (x0) and 2q + 1 (x0 + 1) at y0 + (q & 1), z0 + (q >> 1)
+        const bool in = live && cr.head && wc_pair_inside(t, R, q);
+        const uint64_t m = __ballot(in);
+        if (in) {
+          const uint32_t idx = wc_off + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          const uint32_t row =
+              a.rec.wc_key0 + (uint32_t)b * (uint32_t)plane + ((uint32_t)(t.i0[2] + (q >> 1)) * R + t.i0[1] + (q & 1)) * R;
+          // x0 = -1: only the x0 + 1 corner is inside; x0 = R - 1: only x0
+          const uint32_t key = x0 >= 0 ? row + (uint32_t)x0 : row;
+          const f2 val = x0 >= 0 ? f2{v[2 * q], x0 + 1 < R ? v[2 * q + 1] : 0.f} : f2{v[2 * q + 1], 0.f};
+          if (idx < wr.end) {
+            a.rec.keys[idx] = key;
+            a.rec.vals[idx] = val;
+          }
+        }
+        wc_off += (uint32_t)__popcll(m);
+      }
+    } else if (live && cr.head) {
       float* gplane = a.grad_weights + b * plane;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {

@@ -282,44 +282,63 @@ static int64_t dense_rows(const mnr_field* f, int l) {
 
 // Key map of the binned scatter: the hashed levels (T keys each), then,
 // when the key space holds them too, the dense levels ((N+1)^3 keys each,
-// in level order); otherwise the dense levels keep run-summed atomics.
-// Returns the number of keys (0: no keyed level).
-static int64_t key_map(const mnr_field* f, KeyMap* map, bool* dense) {
+// in level order; else they keep run-summed atomics), then, from a multiple
+// of 2^MAX_BIN_SHIFT, the blend-weight gradient's n_bones x res^3 elements
+// when they fit and res is a power of two up to 2^12 (else global atomics).
+// Returns the number of keys (0: nothing keyed).
+static int64_t key_map(const mnr_field* f, const mnr_motion* m, KeyMap* map, bool* dense, bool* wc) {
+  const int64_t limit = (int64_t)MAX_BINS << MAX_BIN_SHIFT;
   KeyMap k{};
   k.log2_T = f->log2_T;
-  if (f->encoding != MNR_ENC_GRID) return 0;
   int64_t n_keys = 0;
-  for (int l = 0; l < f->n_levels; ++l)
-    if (!level_is_dense(f, l)) {
-      k.start[k.n] = (uint32_t)n_keys;
-      k.level[k.n++] = l;
-      n_keys += (int64_t)1 << f->log2_T;
-    }
-  int64_t all = n_keys;
-  for (int l = 0; l < f->n_levels; ++l)
-    if (level_is_dense(f, l)) all += dense_rows(f, l);
-  const bool with_dense = all <= ((int64_t)MAX_BINS << MAX_BIN_SHIFT);
-  if (with_dense)
+  bool with_dense = false;
+  if (f->encoding == MNR_ENC_GRID) {
     for (int l = 0; l < f->n_levels; ++l)
-      if (level_is_dense(f, l)) {
+      if (!level_is_dense(f, l)) {
         k.start[k.n] = (uint32_t)n_keys;
         k.level[k.n++] = l;
-        n_keys += dense_rows(f, l);
+        n_keys += (int64_t)1 << f->log2_T;
       }
+    int64_t all = n_keys;
+    for (int l = 0; l < f->n_levels; ++l)
+      if (level_is_dense(f, l)) all += dense_rows(f, l);
+    with_dense = all <= limit;
+    if (with_dense)
+      for (int l = 0; l < f->n_levels; ++l)
+        if (level_is_dense(f, l)) {
+          k.start[k.n] = (uint32_t)n_keys;
+          k.level[k.n++] = l;
+          n_keys += dense_rows(f, l);
+        }
+  }
   k.start[k.n] = (uint32_t)n_keys;
+  const int64_t R = m ? m->res : 0;
+  const int64_t wc_keys = m ? (int64_t)m->n_bones * R * R * R : 0;
+  const int64_t wc0 = (n_keys + ((int64_t)1 << MAX_BIN_SHIFT) - 1) & ~(((int64_t)1 << MAX_BIN_SHIFT) - 1);
+  const bool with_wc = wc_keys > 0 && (R & (R - 1)) == 0 && R <= 4096 && wc0 + wc_keys <= limit;
+  k.wc_start = k.wc_end = (uint32_t)n_keys;
+  if (with_wc) {
+    k.wc_start = (uint32_t)wc0;
+    k.wc_end = (uint32_t)(wc0 + wc_keys);
+    n_keys = wc0 + wc_keys;
+  }
   if (map) *map = k;
   if (dense) *dense = with_dense;
+  if (wc) *wc = with_wc;
   return n_keys;
 }
 
-// Carves the caller's scatter workspace; returns its size (0: no keyed
-// level, or the batch or table is too large for the binned path).
-static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws, ScatterPlan* p) {
+// Carves the caller's scatter workspace; returns its size (0: nothing
+// keyed, or the batch or table is too large for the binned path).
+static uint64_t scatter_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
+                               ScatterPlan* p) {
   KeyMap map;
-  bool dense = false;
-  const int64_t n_keys = key_map(f, &map, &dense);
+  bool dense = false, wc = false;
+  const int64_t n_keys = key_map(f, m, &map, &dense, &wc);
   if (n_keys == 0 || n_rays <= 0 || spp <= 0) return 0;
-  const uint64_t cap = (uint64_t)n_rays * spp * map.n * 8;
+  // per sample: 8 records per keyed level, 4 per bone (corner pairs)
+  const uint64_t per_sample = (uint64_t)map.n * 8 + (wc ? (uint64_t)m->n_bones * 4 : 0);
+  const uint64_t cap = (uint64_t)n_rays * spp * per_sample;
   if (cap >= ((uint64_t)1 << 31)) return 0;
   const int shift = scatter_bin_shift(n_keys);
   if (shift > MAX_BIN_SHIFT) return 0;
@@ -339,6 +358,7 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
   char* skeys = take(cap * 4);
   char* svals = take(cap * 8);
   char* hist = take((uint64_t)n_bins * n_tiles * 4);
+  char* seg = take((uint64_t)BIN_SEGS * n_bins * 4);
   char* total = take((uint64_t)n_bins * 4);
   char* base = take((uint64_t)n_bins * 4);
   char* item_base = take((uint64_t)n_bins * 4);
@@ -351,6 +371,7 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
     p->skeys = (uint32_t*)skeys;
     p->svals = (f2*)svals;
     p->hist = (uint32_t*)hist;
+    p->seg = (uint32_t*)seg;
     p->total = (uint32_t*)total;
     p->base = (uint32_t*)base;
     p->item_base = (uint32_t*)item_base;
@@ -364,6 +385,7 @@ static uint64_t scatter_layout(const mnr_field* f, int n_rays, int spp, char* ws
     p->n_keys = n_keys;
     p->map = map;
     p->dense = dense;
+    p->wc = wc;
   }
   return off;
 }
@@ -390,12 +412,12 @@ static uint64_t split_layout(const mnr_field* f, const mnr_motion* m, int n_rays
   return arrays + 256 + act;
 }
 
-// The adjoint workspace: the binned scatter's part (when the field has
-// hashed levels), then the split adjoint's (when the motion has a residual
-// network).
+// The adjoint workspace: the binned scatter's part (table and blend-weight
+// gradient records), then the split adjoint's (with a residual network or
+// the frequency-encoded field).
 static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
                                ScatterPlan* p, SplitArgs* sp) {
-  const uint64_t a = scatter_layout(f, n_rays, spp, ws, p);
+  const uint64_t a = scatter_layout(f, m, n_rays, spp, ws, p);
   const uint64_t b = split_layout(f, m, n_rays, spp, ws ? ws + a : nullptr, sp);
   return a + b;
 }
@@ -403,7 +425,7 @@ static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_ra
 // Validates a caller's adjoint workspace and points the adjoint at it.
 static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
                                 uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp) {
-  rec = RecordSink{nullptr, nullptr, nullptr, 0, 0};
+  rec = RecordSink{nullptr, nullptr, nullptr, 0, 0, 0, 0u};
   sp = SplitArgs{nullptr, 0, nullptr, nullptr};
   if (!ws) {
     if (m->res_w[0]) return fail(MNR_E_INVALID, "the residual network's adjoint needs the adjoint workspace");
@@ -415,21 +437,22 @@ static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_r
   ScatterPlan pp{};
   SplitArgs ss{nullptr, 0, nullptr, nullptr};
   const uint64_t need = adjoint_layout(f, m, n_rays, spp, (char*)ws, &pp, &ss);
-  if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (no hashed level, no residual network, not the frequency-encoded field, or a batch or table too large)");
+  if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (nothing keyed, no residual network, not the frequency-encoded field, or a batch or table too large)");
   if (ws_bytes < need)
     return fail(MNR_E_SHAPE, "adjoint workspace has %llu bytes, needs %llu", (unsigned long long)ws_bytes,
                 (unsigned long long)need);
-  if (scatter_layout(f, n_rays, spp, nullptr, nullptr)) {
+  if (scatter_layout(f, m, n_rays, spp, nullptr, nullptr)) {
     p = pp;
-    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0};
+    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0, p.wc ? 1 : 0, p.map.wc_start};
   }
   sp = ss;
   return MNR_OK;
 }
 
-// The adjoint's launches: with the residual network, the split chain
-// (residual forward, field adjoint, residual and skinning adjoints), else
-// the fused kernel; the binned scatter after the field adjoint.
+// The adjoint's launches: with the residual network or the frequency-
+// encoded field, the split chain (residual forward, field adjoint, residual
+// and skinning adjoints), else the fused kernel; the binned scatter after
+// every kernel that writes records.
 static hipError_t adjoint_launches(const RenderArgs& a, const ScatterPlan& plan, int slots, const mnr_field* f,
                                    float* grad_table, hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -442,9 +465,9 @@ static hipError_t adjoint_launches(const RenderArgs& a, const ScatterPlan& plan,
   }
   if (a.f.freq) ok(launch_freq_backward(a, slots, st));
   else ok(launch_render_bwd(a, slots, f->table_dtype, f->mlp_dtype, f->n_layers - 2, st));
-  if (a.rec.keys) ok(launch_binned_scatter(plan, grad_table, st));
   if (res) ok(launch_res_backward(a, slots, st));
   if (a.split.buf) ok(launch_skin_backward(a, slots, st));
+  if (a.rec.keys) ok(launch_binned_scatter(plan, grad_table, a.grad_weights, st));
   return e;
 }
 

@@ -78,15 +78,21 @@ struct ResArgs {
   int32_t n_omega;
 };
 
-// Where the adjoint writes the gradient records of the hashed grid levels
-// (keys == NULL: it adds them with global atomics instead).  Record i:
-// keys[i] = level * T + row, vals[i] = the two features' gradients.
+// Where the adjoint writes its gradient records (keys == NULL: it adds the
+// gradients with global atomics instead).  Record i: key keys[i], values
+// vals[i].  Grid table: key = the row's place among the keyed levels' rows,
+// values = the two features' gradients.  Blend weights (when wc != 0):
+// key = wc_key0 + element of dL/dW^c ([bone][z][y][x]), values = the
+// gradients of that element and of the next one along x (zero when that is
+// outside the volume): one record per pair of x-adjacent cell corners.
 struct RecordSink {
   uint32_t* cursor;  // records written so far (zero before the adjoint)
   uint32_t* keys;
   f2* vals;
   uint32_t cap;      // capacity in records
   int32_t dense;     // 1: the dense levels leave as records too (keys after the hashed levels')
+  int32_t wc;        // 1: the blend-weight gradient leaves as records too (else global atomics)
+  uint32_t wc_key0;  // its first key
 };
 
 // Per-sample scratch of the split adjoint (used with the residual motion

@@ -59,11 +59,18 @@ constexpr int MAX_BINS = 4096;
 constexpr int MAX_BIN_SHIFT = 14;       // largest bin: 2^14 rows (summed in 2^12-row parts)
 constexpr int BIN_TILE_RECORDS = 8192;  // records per histogram / scatter block
 constexpr int ACC_PART_RECORDS = 65536; // records per summing block: larger bins are split
+constexpr int BIN_SEGS = 64;            // tile segments of the per-bin scans
+constexpr int BIN_SCAN_BINS = 256;      // bins per block of the segment scans
 struct KeyMap {  // keyed level j: keys [start[j], start[j + 1]) are rows 0, 1, ... of table level level[j]
   int32_t level[MNR_MAX_LEVELS];
   uint32_t start[MNR_MAX_LEVELS + 1];
   int32_t n;                 // keyed levels: the hashed ones (T keys each), then the dense ones ((N+1)^3 each)
   int32_t log2_T;
+  // keys [wc_start, wc_end): elements of dL/dW^c (x-pair records: value 0 at
+  // the key, value 1 at the next element); wc_start is a multiple of
+  // 2^MAX_BIN_SHIFT and the volume's x extent divides 2^12, so no pair
+  // crosses a bin or a summing part
+  uint32_t wc_start, wc_end;
 };
 struct ScatterPlan {
   uint32_t* cursor;          // records written by the adjoint
@@ -71,7 +78,8 @@ struct ScatterPlan {
   f2* vals;                  // [cap]
   uint32_t* skeys;           // [cap] records in bin order
   f2* svals;                 // [cap]
-  uint32_t* hist;            // [n_bins][n_tiles_cap]
+  uint32_t* hist;            // [n_tiles_cap][n_bins]
+  uint32_t* seg;             // [BIN_SEGS][n_bins]
   uint32_t* total;           // [n_bins]
   uint32_t* base;            // [n_bins]
   uint32_t* item_base;       // [n_bins] first summing item of each bin
@@ -82,9 +90,10 @@ struct ScatterPlan {
   int64_t n_keys;            // keys of all keyed levels
   KeyMap map;
   bool dense;                // the dense levels are keyed too
+  bool wc;                   // so is dL/dW^c
 };
 int scatter_bin_shift(int64_t n_keys);
-hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st);
+hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, float* grad_weights, hipStream_t st);
 
 hipError_t launch_mse(const float* rgba, const float* target, int n, float* grad, float* loss, hipStream_t st);
 hipError_t launch_softmax_fwd(const float* logits, float* w, int C, int64_t V, hipStream_t st);

@@ -337,9 +337,12 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       // (when keyed) writes one record per corner and run of consecutive
       // samples in one cell, after the hashed levels' records.  Keys: h T +
       // row for hashed level h, then the dense levels' rows one level after
-      // the other ((N+1)^3 keys each).
-      uint32_t rec_base = 0, n_live = 0, rank = 0, n_hashed = 0;
+      // the other ((N+1)^3 keys each).  The blend-weight records (when
+      // keyed) take the rest of the reservation.  A reservation past the
+      // capacity falls back to global atomics.
+      uint32_t rec_base = 0, rec_end = 0, n_live = 0, rank = 0, n_hashed = 0;
       bool rec_ok = false;
+      WcRecords wcr{false, 0u, 0u};
       if (a.rec.keys) {
         const uint64_t lm = __ballot(live);
         n_live = (uint32_t)__popcll(lm);
@@ -355,11 +358,18 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
             n_runs += (uint32_t)__popcll(__ballot(live && cr.head));
           }
         }
-        const uint32_t cnt = (n_live * n_hashed + n_runs) * 8u;
+        const uint32_t n_tab = (n_live * n_hashed + n_runs) * 8u;
+        uint32_t n_wc = 0;
+        if constexpr (!SPLIT) {
+          if (a.rec.wc) n_wc = wc_record_count(a, st.x, live);
+        }
+        const uint32_t cnt = n_tab + n_wc;
         uint32_t b = 0;
         if (lane == 0 && cnt) b = atomicAdd(a.rec.cursor, cnt);
         rec_base = __builtin_amdgcn_readfirstlane(b);
+        rec_end = rec_base + cnt;
         rec_ok = (uint64_t)rec_base + cnt <= (uint64_t)a.rec.cap;
+        wcr = WcRecords{rec_ok && n_wc > 0, rec_base + n_tab, rec_end};
       }
       // (a) spatial derivative of the encoding: table reads only.  (b) then
       // the gradient scatter, which reads nothing: on this GPU one counter
@@ -402,8 +412,8 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         for (int k = 0; k < 8; ++k)
           wk[k] = ((k & 1) ? gc.f[0] : 1.f - gc.f[0]) * ((k & 2) ? gc.f[1] : 1.f - gc.f[1]) *
                   ((k & 4) ? gc.f[2] : 1.f - gc.f[2]);
-        if (a.rec.keys && !dense) {  // hashed level: records
-          if (live && rec_ok) {
+        if (rec_ok && !dense) {  // hashed level: records
+          if (live) {
             const uint32_t h = (uint32_t)__popc(~a.f.dense_mask & ((1u << l) - 1u));
             const uint32_t key0 = h << a.f.log2_T;  // the hashed levels take the first keys
 #pragma unroll
@@ -422,17 +432,19 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         for (int k = 0; k < 8; ++k) { v[2 * k] = wk[k] * d0; v[2 * k + 1] = wk[k] * d1; }
         const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
         run_sums<16>(cr, v);
-        if (a.rec.keys && a.rec.dense) {  // dense level: one record per corner and run
+        if (rec_ok && a.rec.dense) {  // dense level: one record per corner and run
           const uint64_t hm = __ballot(live && cr.head);
           const uint32_t n_runs = (uint32_t)__popcll(hm);
-          if (live && cr.head && rec_ok) {
+          if (live && cr.head) {
             const uint32_t r = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
             const uint32_t first = rec_base + n_live * n_hashed * 8u + dense_off * 8u;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               const uint32_t idx = first + (uint32_t)k * n_runs + r;
-              a.rec.keys[idx] = dense_key + grid_row(gc, N, dense, tmask, k);
-              a.rec.vals[idx] = f2{v[2 * k], v[2 * k + 1]};
+              if (idx < rec_end) {  // (the counting pass found the same runs)
+                a.rec.keys[idx] = dense_key + grid_row(gc, N, dense, tmask, k);
+                a.rec.vals[idx] = f2{v[2 * k], v[2 * k + 1]};
+              }
             }
           }
           dense_off += n_runs;
@@ -467,7 +479,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           sb[SPLIT_GL * ss + sj] = live ? g_L : 0.f;
         }
       } else {
-        skin_adjoint(a, st.x, st.xs, st.L, g_xs, g_L, live, dg);
+        skin_adjoint(a, st.x, st.xs, st.L, g_xs, g_L, live, dg, wcr);
       }
       wave_sync_lds();
     }

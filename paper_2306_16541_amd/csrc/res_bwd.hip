@@ -344,7 +344,15 @@ __global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderA
         }
         gL = sb[SPLIT_GL * ss + sj];
       }
-      skin_adjoint(a, x, xs, L, gs, gL, live, dg);
+      WcRecords wcr{false, 0u, 0u};
+      if (a.rec.keys && a.rec.wc) {  // blend-weight records: one reservation per chunk
+        const uint32_t cnt = wc_record_count(a, x, live);
+        uint32_t b = 0;
+        if (lane == 0 && cnt) b = atomicAdd(a.rec.cursor, cnt);
+        const uint32_t base = __builtin_amdgcn_readfirstlane(b);
+        wcr = WcRecords{cnt > 0 && (uint64_t)base + cnt <= (uint64_t)a.rec.cap, base, base + cnt};
+      }
+      skin_adjoint(a, x, xs, L, gs, gL, live, dg, wcr);
     }
   }
   __syncthreads();

@@ -12,8 +12,11 @@
 // without global float atomics:
 //   1. bin_histogram: per tile of records, a histogram of the key bins
 //      (a bin = 2^shift consecutive keys, up to a 128 KiB slice of the table
-//      gradient), written bin-major to H[bin][tile];
-//   2. bin_totals / bin_offsets: exclusive scan of H in (bin, tile) order,
+//      gradient), written tile-major to H[tile][bin] (one contiguous row per
+//      tile: thousands of bins make a bin-major layout's column writes and
+//      reads the slowest part of the pipeline);
+//   2. bin_segsum / bin_scan / bin_offsets: exclusive scan of H in (bin,
+//      tile) order, per bin over BIN_SEGS segments of tiles in parallel,
 //      giving every (bin, tile) pair its place in bin order, and the list of
 //      summing items (a bin of t records is ceil(t / ACC_PART_RECORDS)
 //      items: the coarse dense levels pack millions of records into a few
@@ -27,7 +30,9 @@
 //      atomics, a few thousand per item).
 // The key map (KeyMap) numbers the hashed levels' rows (T keys per level),
 // then the dense levels' ((N+1)^3 keys per level), so no bin is spent on
-// rows a dense level does not have.  Traffic is a few passes over the
+// rows a dense level does not have; then, from a bin-aligned start, the
+// elements of the blend-weight gradient dL/dW^c (Eq. 7), whose records carry
+// two x-adjacent cell corners each.  Traffic is a few passes over the
 // records (12 bytes each) instead of two memory-side atomics per record.
 #include <cfloat>
 
@@ -38,7 +43,6 @@ namespace mnr {
 constexpr int BIN_THREADS = 512;
 constexpr int BIN_TILE = BIN_TILE_RECORDS;  // records per tile
 constexpr int BIN_PER_THREAD = BIN_TILE / BIN_THREADS;
-constexpr int SCAN_THREADS = 256;           // the per-bin scans
 constexpr int ACC_THREADS = 1024;           // the per-bin sums
 constexpr int ACC_SHIFT = 12;               // rows per summing block: 2^12 x 2 features x 8 bytes = 64 KiB of LDS
 
@@ -60,8 +64,7 @@ __device__ __forceinline__ uint32_t record_count(const uint32_t* cursor, uint32_
 
 __global__ void __launch_bounds__(BIN_THREADS) bin_histogram_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
                                                                     const uint32_t* __restrict__ keys, int shift,
-                                                                    int n_bins, int n_tiles_cap,
-                                                                    uint32_t* __restrict__ H) {
+                                                                    int n_bins, uint32_t* __restrict__ H) {
   __shared__ uint32_t hist[MAX_BINS];
   const uint32_t count = record_count(cursor, cap);
   const int tile = blockIdx.x;
@@ -98,31 +101,7 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_histogram_kernel(const uint32
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) H[(size_t)b * n_tiles_cap + tile] = hist[b];
-}
-
-__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
-#pragma unroll
-  for (int k = WAVE / 2; k > 0; k >>= 1) v += __shfl_xor(v, k, WAVE);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint32_t s = 0;
-  for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += red[w];
-  __syncthreads();
-  return s;
-}
-
-// total[b] = number of records in bin b.
-__global__ void __launch_bounds__(SCAN_THREADS) bin_totals_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
-                                                                 const uint32_t* __restrict__ H, int n_tiles_cap,
-                                                                 uint32_t* __restrict__ total) {
-  __shared__ uint32_t red[SCAN_THREADS / WAVE];
-  const int n_tiles = (int)((record_count(cursor, cap) + BIN_TILE - 1) / BIN_TILE);
-  const uint32_t* row = H + (size_t)blockIdx.x * n_tiles_cap;
-  uint32_t s = 0;
-  for (int t = threadIdx.x; t < n_tiles; t += SCAN_THREADS) s += row[t];
-  s = block_sum_u32(s, red);
-  if (threadIdx.x == 0) total[blockIdx.x] = s;
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) H[(size_t)tile * n_bins + b] = hist[b];
 }
 
 // Summing items of a bin of n records.
@@ -130,52 +109,110 @@ __device__ __forceinline__ uint32_t bin_items(uint32_t n) {
   return (n + ACC_PART_RECORDS - 1) / ACC_PART_RECORDS;
 }
 
-// base[b] = records in bins before b; H[b][t] becomes the place of tile t's
-// first record of bin b (exclusive scan in (bin, tile) order).  Items:
-// item_base[b] = items of the bins before b, item_bin[item_base[b] + j] = b
-// for the bin's items j, and the last bin's block writes the item count.
-__global__ void __launch_bounds__(SCAN_THREADS) bin_offsets_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
-                                                                  uint32_t* __restrict__ H, int n_tiles_cap,
-                                                                  const uint32_t* __restrict__ total,
-                                                                  uint32_t* __restrict__ base,
-                                                                  uint32_t* __restrict__ item_base,
-                                                                  uint32_t* __restrict__ item_bin,
-                                                                  uint32_t* __restrict__ n_items) {
-  __shared__ uint32_t red[SCAN_THREADS / WAVE];
-  __shared__ uint32_t scan[SCAN_THREADS];
-  const int b = blockIdx.x;
-  const int n_tiles = (int)((record_count(cursor, cap) + BIN_TILE - 1) / BIN_TILE);
-  uint32_t s = 0, q = 0;
-  for (int k = threadIdx.x; k < b; k += SCAN_THREADS) {
-    s += total[k];
-    q += bin_items(total[k]);
-  }
-  uint32_t carry = block_sum_u32(s, red);
-  const uint32_t first_item = block_sum_u32(q, red);
-  const uint32_t my_items = bin_items(total[b]);
-  if (threadIdx.x == 0) {
-    base[b] = carry;
-    item_base[b] = first_item;
-    if (b == (int)gridDim.x - 1) *n_items = first_item + my_items;
-  }
-  for (uint32_t j = threadIdx.x; j < my_items; j += SCAN_THREADS) item_bin[first_item + j] = (uint32_t)b;
-  uint32_t* row = H + (size_t)b * n_tiles_cap;
-  for (int t0 = 0; t0 < n_tiles; t0 += SCAN_THREADS) {
-    const int t = t0 + threadIdx.x;
-    const uint32_t v = t < n_tiles ? row[t] : 0u;
-    scan[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < SCAN_THREADS; d <<= 1) {  // inclusive Hillis-Steele scan
-      const uint32_t o = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0u;
-      __syncthreads();
-      scan[threadIdx.x] += o;
-      __syncthreads();
+// Tiles of segment s (the per-bin scans over tiles run in BIN_SEGS
+// segments, one block per segment and BIN_SCAN_BINS bins).
+__device__ __forceinline__ void segment_tiles(uint32_t count, int s, int& t0, int& t1) {
+  const int n_tiles = (int)((count + BIN_TILE - 1) / BIN_TILE);
+  const int per = (n_tiles + BIN_SEGS - 1) / BIN_SEGS;
+  t0 = min(n_tiles, s * per);
+  t1 = min(n_tiles, t0 + per);
+}
+
+// seg[s][b] = records of bin b in the tiles of segment s.
+__global__ void __launch_bounds__(BIN_SCAN_BINS) bin_segsum_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                  const uint32_t* __restrict__ H, int n_bins,
+                                                                  uint32_t* __restrict__ seg) {
+  const int b = blockIdx.x * BIN_SCAN_BINS + threadIdx.x, s = blockIdx.y;
+  if (b >= n_bins) return;
+  int t0, t1;
+  segment_tiles(record_count(cursor, cap), s, t0, t1);
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (int t = t0; t < t1; ++t) sum += H[(size_t)t * n_bins + b];
+  seg[(size_t)s * n_bins + b] = sum;
+}
+
+// One block: total[b] = records of bin b (the sum of its segments' counts);
+// base[b] = records of the bins before b; the summing items: item_base[b] =
+// items of the bins before b, item_bin[item_base[b] + j] = b for the bin's
+// items j, and their count.
+constexpr int BIN_SCAN_THREADS = 1024;
+__global__ void __launch_bounds__(BIN_SCAN_THREADS) bin_scan_kernel(const uint32_t* __restrict__ seg, int n_bins,
+                                                                   uint32_t* __restrict__ total,
+                                                                   uint32_t* __restrict__ base,
+                                                                   uint32_t* __restrict__ item_base,
+                                                                   uint32_t* __restrict__ item_bin,
+                                                                   uint32_t* __restrict__ n_items) {
+  __shared__ uint32_t red[2][BIN_SCAN_THREADS / WAVE];
+  constexpr int PER = MAX_BINS / BIN_SCAN_THREADS;  // consecutive bins per thread
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
+  uint32_t tot[PER], rec = 0, items = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int b = threadIdx.x * PER + j;
+    uint32_t sum = 0;
+    if (b < n_bins) {
+#pragma unroll 16
+      for (int s = 0; s < BIN_SEGS; ++s) sum += seg[(size_t)s * n_bins + b];
     }
-    if (t < n_tiles) row[t] = carry + scan[threadIdx.x] - v;
-    const uint32_t chunk = scan[SCAN_THREADS - 1];
-    __syncthreads();
-    carry += chunk;
+    tot[j] = sum;
+    rec += sum;
+    items += bin_items(sum);
   }
+  // exclusive scans of (records, items) over the threads' bin groups
+  uint32_t ir = rec, ii = items;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o1 = __shfl_up(ir, d, WAVE), o2 = __shfl_up(ii, d, WAVE);
+    if (lane >= d) { ir += o1; ii += o2; }
+  }
+  if (lane == WAVE - 1) { red[0][wave] = ir; red[1][wave] = ii; }
+  __syncthreads();
+  uint32_t r0 = ir - rec, i0 = ii - items;
+  for (int w = 0; w < wave; ++w) { r0 += red[0][w]; i0 += red[1][w]; }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int b = threadIdx.x * PER + j;
+    if (b >= n_bins) break;
+    total[b] = tot[j];
+    base[b] = r0;
+    item_base[b] = i0;
+    const uint32_t nb = bin_items(tot[j]);
+    for (uint32_t k = 0; k < nb; ++k) item_bin[i0 + k] = (uint32_t)b;
+    r0 += tot[j];
+    i0 += nb;
+    if (b == n_bins - 1) *n_items = i0;
+  }
+}
+
+// H[t][b] becomes the place of tile t's first record of bin b (records in
+// (bin, tile) order).
+__global__ void __launch_bounds__(BIN_SCAN_BINS) bin_offsets_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
+                                                                   uint32_t* __restrict__ H, int n_bins,
+                                                                   const uint32_t* __restrict__ seg,
+                                                                   const uint32_t* __restrict__ base) {
+  const int b = blockIdx.x * BIN_SCAN_BINS + threadIdx.x, s = blockIdx.y;
+  if (b >= n_bins) return;
+  int t0, t1;
+  segment_tiles(record_count(cursor, cap), s, t0, t1);
+  uint32_t run = base[b];
+  for (int q = 0; q < s; ++q) run += seg[(size_t)q * n_bins + b];  // the bin's records in earlier segments
+#pragma unroll 8
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = H[(size_t)t * n_bins + b];
+    H[(size_t)t * n_bins + b] = run;
+    run += v;
+  }
+}
+
+// Tile of scatter block i: the 8 XCDs take contiguous ranges of tiles
+// (block i runs on XCD i mod 8), so that a bin's records from neighbouring
+// tiles, which land next to each other, are written through one L2.
+__device__ __forceinline__ int scatter_tile(uint32_t count) {
+  const int n_tiles = (int)((count + BIN_TILE - 1) / BIN_TILE);
+  const int per = (n_tiles + 7) / 8;
+  const int j = (int)(blockIdx.x >> 3);
+  return j < per ? (int)(blockIdx.x & 7) * per + j : n_tiles;
 }
 
 // Each tile's records are first sorted by bin in LDS (a counting sort), then
@@ -186,7 +223,7 @@ constexpr int SCATTER_LDS = MAX_BINS * 4 * 2 + BIN_TILE * (4 + 8);
 __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t* __restrict__ cursor, uint32_t cap,
                                                                   const uint32_t* __restrict__ keys,
                                                                   const f2* __restrict__ vals, int shift, int n_bins,
-                                                                  int n_tiles_cap, const uint32_t* __restrict__ H,
+                                                                  const uint32_t* __restrict__ H,
                                                                   uint32_t* __restrict__ skeys,
                                                                   f2* __restrict__ svals) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -196,7 +233,7 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
   f2* lvals = (f2*)(lkeys + BIN_TILE);
   __shared__ uint32_t red[BIN_THREADS / WAVE];
   const uint32_t count = record_count(cursor, cap);
-  const int tile = blockIdx.x;
+  const int tile = scatter_tile(count);
   if ((int64_t)tile * BIN_TILE >= count) return;
   const uint32_t t0 = (uint32_t)tile * BIN_TILE;
   const int n_here = (int)min((uint32_t)BIN_TILE, count - t0);
@@ -264,7 +301,7 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
   __shared__ uint32_t n_sorted;
   if (threadIdx.x == 0) n_sorted = start[n_bins - 1] + cur[n_bins - 1];
   __syncthreads();
-  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) cur[b] = H[(size_t)b * n_tiles_cap + tile];
+  for (int b = threadIdx.x; b < n_bins; b += BIN_THREADS) cur[b] = H[(size_t)tile * n_bins + b];
   __syncthreads();
   for (int p = threadIdx.x; p < (int)n_sorted; p += BIN_THREADS) {
     const uint32_t kk = lkeys[p];
@@ -287,15 +324,16 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
 // each value is rounded once, by at most 2^-(S+1).  The items of a split bin
 // add their (exact) sums to the table gradient with float atomics.  An item
 // holding a non-finite value is summed in floats instead.  Keys map to
-// table rows through the key map.
+// table rows or dL/dW^c elements through the key map.
 __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint32_t* __restrict__ skeys,
                                                                      const f2* __restrict__ svals, int shift,
-                                                                     int64_t n_keys, const uint32_t* __restrict__ total,
+                                                                     const uint32_t* __restrict__ total,
                                                                      const uint32_t* __restrict__ base,
                                                                      const uint32_t* __restrict__ item_base,
                                                                      const uint32_t* __restrict__ item_bin,
                                                                      const uint32_t* __restrict__ n_items,
-                                                                     const KeyMap map, float* __restrict__ grad) {
+                                                                     const KeyMap map, float* __restrict__ grad,
+                                                                     float* __restrict__ grad_w) {
   extern __shared__ unsigned long long acc[];  // [2][rows]: the two features in separate planes
   __shared__ uint32_t max_bits;
   const int parts_log2 = shift > ACC_SHIFT ? shift - ACC_SHIFT : 0;
@@ -360,11 +398,31 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   }
   __syncthreads();
   const int64_t k0 = ((int64_t)b << shift) + lo;
+  if (k0 >= (int64_t)map.wc_start && k0 < (int64_t)map.wc_end) {
+    // dL/dW^c: element k0 + r takes plane 0 of its own key and plane 1 of
+    // the key before (the pair's second corner); pairs never cross slices
+    for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
+      const int64_t key = k0 + r;
+      float v;
+      if (fixed) {
+        const long long s = (long long)acc[r] + (r > 0 ? (long long)acc[rows + r - 1] : 0ll);
+        v = (float)((double)s / scale);
+      } else {
+        v = accf[r] + (r > 0 ? accf[rows + r - 1] : 0.f);
+      }
+      if (v != 0.f && key < (int64_t)map.wc_end) {
+        float* g = grad_w + (key - map.wc_start);
+        if (shared) unsafeAtomicAdd(g, v);
+        else *g += v;
+      }
+    }
+    return;
+  }
   for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
     const f2 v = fixed ? f2{(float)((double)(long long)acc[r] / scale), (float)((double)(long long)acc[rows + r] / scale)}
                        : f2{accf[r], accf[rows + r]};
     const int64_t key = k0 + r;
-    if ((v[0] != 0.f || v[1] != 0.f) && key < n_keys) {
+    if ((v[0] != 0.f || v[1] != 0.f) && key < (int64_t)map.start[map.n]) {
       int j = 0;
       while (j + 1 < map.n && (uint32_t)key >= map.start[j + 1]) ++j;
       const int64_t row = ((int64_t)map.level[j] << map.log2_T) + ((uint32_t)key - map.start[j]);
@@ -379,23 +437,26 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   }
 }
 
-hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, hipStream_t st) {
+hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, float* grad_weights, hipStream_t st) {
   const int parts_log2 = p.shift > ACC_SHIFT ? p.shift - ACC_SHIFT : 0;
   const int lds = (2 << (p.shift - parts_log2)) * (int)sizeof(unsigned long long);
   static PersistentGrid once_acc, once_sc;  // raise the LDS limits once
   persistent_blocks(bin_accumulate_kernel, ACC_THREADS, (2 << ACC_SHIFT) * (int)sizeof(unsigned long long), once_acc);
   persistent_blocks(bin_scatter_kernel, BIN_THREADS, SCATTER_LDS, once_sc);
   hipLaunchKernelGGL(bin_histogram_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), 0, st, p.cursor, p.cap, p.keys,
-                     p.shift, p.n_bins, p.n_tiles_cap, p.hist);
-  hipLaunchKernelGGL(bin_totals_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
-                     p.n_tiles_cap, p.total);
-  hipLaunchKernelGGL(bin_offsets_kernel, dim3(p.n_bins), dim3(SCAN_THREADS), 0, st, p.cursor, p.cap, p.hist,
-                     p.n_tiles_cap, p.total, p.base, p.item_base, p.item_bin, p.n_items);
-  hipLaunchKernelGGL(bin_scatter_kernel, dim3(p.n_tiles_cap), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
-                     p.keys, p.vals, p.shift, p.n_bins, p.n_tiles_cap, p.hist, p.skeys, p.svals);
+                     p.shift, p.n_bins, p.hist);
+  const dim3 seg_grid((p.n_bins + BIN_SCAN_BINS - 1) / BIN_SCAN_BINS, BIN_SEGS);
+  hipLaunchKernelGGL(bin_segsum_kernel, seg_grid, dim3(BIN_SCAN_BINS), 0, st, p.cursor, p.cap, p.hist, p.n_bins,
+                     p.seg);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(BIN_SCAN_THREADS), 0, st, p.seg, p.n_bins, p.total, p.base,
+                     p.item_base, p.item_bin, p.n_items);
+  hipLaunchKernelGGL(bin_offsets_kernel, seg_grid, dim3(BIN_SCAN_BINS), 0, st, p.cursor, p.cap, p.hist, p.n_bins,
+                     p.seg, p.base);
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3((p.n_tiles_cap + 7) / 8 * 8), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
+                     p.keys, p.vals, p.shift, p.n_bins, p.hist, p.skeys, p.svals);
   hipLaunchKernelGGL(bin_accumulate_kernel, dim3((unsigned)p.max_items << parts_log2), dim3(ACC_THREADS), lds, st,
-                     p.skeys, p.svals, p.shift, p.n_keys, p.total, p.base, p.item_base, p.item_bin, p.n_items, p.map,
-                     grad_table);
+                     p.skeys, p.svals, p.shift, p.total, p.base, p.item_base, p.item_bin, p.n_items, p.map,
+                     grad_table, grad_weights);
   return hipGetLastError();
 }
 

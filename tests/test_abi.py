@@ -211,32 +211,44 @@ def test_build_script_loads_without_the_package():
     assert r.returncode == 0, r.stderr
 
 
+def _scatter_ws_bytes(n_rays, spp, per_sample, n_keys):
+    # records (12 bytes, twice), per-tile bin histograms, per-bin counts in
+    # 64 tile segments, per-bin totals, places and first items, the items'
+    # bins (a bin of t records is ceil(t / 65536) items) and their count,
+    # each part 256-byte aligned
+    a256 = lambda b: (b + 255) // 256 * 256
+    cap = n_rays * spp * per_sample
+    n_bins = -(-n_keys // (1 << 12))      # slices of 2^12 rows
+    tiles = -(-cap // 8192)
+    items = n_bins + -(-cap // 65536)
+    return (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + a256(64 * n_bins * 4) +
+            3 * a256(n_bins * 4) + a256(items * 4) + a256(4))
+
+
 def test_adjoint_workspace_size_and_checks():
-    # Adjoint workspace: binned-scatter records for every sample, level and
-    # corner (the dense levels are keyed too while hashed levels x T plus
-    # dense rows fit the key space), twice, plus per-tile bin histograms, the
-    # per-bin totals and places and the summing items (a bin of t records is
-    # ceil(t / 65536) items); with a residual
-    # network or the frequency-encoded field, 21 floats per sample slot and
-    # 64 floats of bias gradient, and for the frequency-encoded field 512
-    # bytes of saved activations per slot (include/metanerf.h).
+    # Adjoint workspace: binned-scatter room for 8 records per sample and
+    # keyed grid level (the dense levels are keyed too while hashed levels x
+    # T plus dense rows fit the key space) and 4 per sample and bone (the
+    # blend-weight gradient's corner pairs, keyed from a multiple of 2^14
+    # when res is a power of two); with a residual network or the
+    # frequency-encoded field, 21 floats per sample slot and 64 floats of
+    # bias gradient, and for the frequency-encoded field 512 bytes of saved
+    # activations per slot (include/metanerf.h).
     m = _lib()
     sc = scenes.scene_body(H=8, W=8, spp=8, res=8, log2_T=19)
     _, f, mo, pose, cam = _args(sc)
+    assert (mo.n_bones, mo.res) == (24, 8)
     nh = sum(1 for n in sc.level_res if (int(n) + 1) ** 3 > 1 << 19)
     assert nh == 9
     a256 = lambda b: (b + 255) // 256 * 256
     nk = len(sc.level_res)                 # every level is keyed
     dense_rows = sum((int(n) + 1) ** 3 for n in sc.level_res if (int(n) + 1) ** 3 <= 1 << 19)
     assert dense_rows == 4913 + 9261 + 17576 + 35937 + 68921 + 132651 + 274625
+    table_keys = (nh << 19) + dense_rows   # hashed levels' keys, then the dense levels' rows
+    wc0 = -(-table_keys // (1 << 14)) << 14
+    n_keys = wc0 + 24 * 8 ** 3
     for n_rays, spp in ((8192, 128), (100, 7)):
-        cap = n_rays * spp * nk * 8
-        n_keys = (nh << 19) + dense_rows       # hashed levels' keys, then the dense levels' rows
-        n_bins = -(-n_keys // (1 << 12))      # slices of 2^12 rows
-        tiles = -(-cap // 8192)
-        items = n_bins + -(-cap // 65536)
-        want = (a256(256) + 2 * a256(cap * 4) + 2 * a256(cap * 8) + a256(n_bins * tiles * 4) + 3 * a256(n_bins * 4) +
-                a256(items * 4) + a256(4))
+        want = _scatter_ws_bytes(n_rays, spp, nk * 8 + 24 * 4, n_keys)
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
         for k in range(6):
             mo.res_w[k] = 0x7000 + 0x100 * k
@@ -244,7 +256,10 @@ def test_adjoint_workspace_size_and_checks():
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split
         for k in range(6):
             mo.res_w[k] = None
-    ff = m.Field()      # the frequency-encoded field: no records, split scratch and saved activations
+    mo.res = 6          # not a power of two: the blend-weight gradient keeps atomics
+    assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 100, 7) == _scatter_ws_bytes(100, 7, nk * 8, table_keys)
+    mo.res = 8
+    ff = m.Field()      # the frequency-encoded field: blend-weight records, split scratch and saved activations
     ff.encoding, ff.mlp_dtype, ff.n_layers = 1, m.BF16, 5
     ff.width[:6] = [64, 64, 64, 64, 64, 4]
     ff.box_min[:], ff.box_max[:] = [-0.5] * 3, [0.5] * 3
@@ -252,10 +267,11 @@ def test_adjoint_workspace_size_and_checks():
         ff.w[k] = 0x9000 + 0x100 * k
     for n_rays, spp in ((8192, 128), (100, 7)):
         chunks = n_rays * -(-spp // 64)
-        want = a256(21 * chunks * 64 * 4) + 256 + chunks * 4 * 4 * 2 * 64 * 16
+        want = (_scatter_ws_bytes(n_rays, spp, 24 * 4, 24 * 8 ** 3) + a256(21 * chunks * 64 * 4) + 256 +
+                chunks * 4 * 4 * 2 * 64 * 16)
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(ff), C.byref(mo), n_rays, spp) == want
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
-    f.log2_T = 24       # the largest table: its 4 hashed levels fill the key space (4096 slices of 2^14 rows), dense levels keep atomics
+    f.log2_T = 24       # the largest table: its 4 hashed levels fill the key space (4096 slices of 2^14 rows), the rest keeps atomics
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 64, 8) > 0
     f.log2_T = 19
     gw = (C.c_void_p * 4)(0x100, 0x200, 0x300, 0x400)

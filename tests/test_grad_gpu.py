@@ -244,9 +244,9 @@ def test_adjoint_on_the_full_size_field():
 
 
 def test_binned_scatter_equals_atomic_scatter():
-    # The same adjoint with the table gradient summed through the binned
-    # scatter and through global atomics: the same sums in another order
-    # (float32 reassociation only), on a batch of 512 rays.
+    # The same adjoint with the table and blend-weight gradients summed
+    # through the binned scatter and through global atomics: the same sums
+    # in another order (float32 reassociation only), on a batch of 512 rays.
     sc = scenes.scene_body(H=64, W=64, spp=128, res=32, log2_T=16, seed=16541 + 4)
     g = np.random.default_rng(9)
     pid = g.integers(0, sc.H * sc.W, 512).astype(np.int32)
@@ -259,7 +259,15 @@ def test_binned_scatter_equals_atomic_scatter():
           f"{int((ta != 0).sum())} nonzero entries", flush=True)
     assert (ta != 0).sum() > 10000
     assert err <= 1e-5
-    for x, y in zip(a[2], b[2]):       # the other gradients are untouched by the switch
+    # the blend-weight gradient (records of corner pairs when binned), seen
+    # through the softmax adjoint as the logits' gradient
+    la, lb = a[3], b[3]
+    err_l = float(np.abs(la - lb).max() / np.abs(la).max())
+    print(f"  binned vs atomic logits gradient: max diff {err_l:.2e} of max, "
+          f"{int((la != 0).sum())} nonzero entries", flush=True)
+    assert (la != 0).sum() > 1000
+    assert err_l <= 1e-5
+    for x, y in zip(a[2], b[2]):       # the MLP gradients are untouched by the switch
         assert float(np.abs(x - y).max()) <= 1e-5 * float(np.abs(x).max())
 
 
@@ -283,6 +291,10 @@ def test_binned_scatter_splits_crowded_bins():
                   f"max diff {err:.2e} of max, {int((ta != 0).sum())} nonzero entries", flush=True)
         assert mx > 0, l
         assert err <= 1e-5, (l, err)
+    la, lb = a[3], b[3]
+    err_l = float(np.abs(la - lb).max() / np.abs(la).max())
+    print(f"  logits (blend-weight records): max diff {err_l:.2e} of max", flush=True)
+    assert err_l <= 1e-5
 
 
 @pytest.mark.parametrize("ert_tau", [0.0, 1e-6])
