@@ -40,7 +40,7 @@
 
 namespace mnr {
 
-constexpr int BIN_THREADS = 512;
+constexpr int BIN_THREADS = 1024;
 constexpr int BIN_TILE = BIN_TILE_RECORDS;  // records per tile
 constexpr int BIN_PER_THREAD = BIN_TILE / BIN_THREADS;
 constexpr int ACC_THREADS = 1024;           // the per-bin sums
