@@ -15,7 +15,7 @@
 //      gradient), written tile-major to H[tile][bin] (one contiguous row per
 //      tile: thousands of bins make a bin-major layout's column writes and
 //      reads the slowest part of the pipeline);
-//   2. bin_segsum / bin_scan / bin_offsets: exclusive scan of H in (bin,
+//   2. bin_segsum / bin_total / bin_scan / bin_offsets: exclusive scan of H in (bin,
 //      tile) order, per bin over BIN_SEGS segments of tiles in parallel,
 //      giving every (bin, tile) pair its place in bin order, and the list of
 //      summing items (a bin of t records is ceil(t / ACC_PART_RECORDS)
@@ -132,13 +132,22 @@ __global__ void __launch_bounds__(BIN_SCAN_BINS) bin_segsum_kernel(const uint32_
   seg[(size_t)s * n_bins + b] = sum;
 }
 
-// One block: total[b] = records of bin b (the sum of its segments' counts);
-// base[b] = records of the bins before b; the summing items: item_base[b] =
-// items of the bins before b, item_bin[item_base[b] + j] = b for the bin's
-// items j, and their count.
+// total[b] = records of bin b (the sum of its segments' counts).
+__global__ void __launch_bounds__(BIN_SCAN_BINS) bin_total_kernel(const uint32_t* __restrict__ seg, int n_bins,
+                                                                 uint32_t* __restrict__ total) {
+  const int b = blockIdx.x * BIN_SCAN_BINS + threadIdx.x;
+  if (b >= n_bins) return;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int s = 0; s < BIN_SEGS; ++s) sum += seg[(size_t)s * n_bins + b];
+  total[b] = sum;
+}
+
+// One block: base[b] = records of the bins before b; the summing items:
+// item_base[b] = items of the bins before b, item_bin[item_base[b] + j] = b
+// for the bin's items j, and their count.
 constexpr int BIN_SCAN_THREADS = 1024;
-__global__ void __launch_bounds__(BIN_SCAN_THREADS) bin_scan_kernel(const uint32_t* __restrict__ seg, int n_bins,
-                                                                   uint32_t* __restrict__ total,
+__global__ void __launch_bounds__(BIN_SCAN_THREADS) bin_scan_kernel(const uint32_t* __restrict__ total, int n_bins,
                                                                    uint32_t* __restrict__ base,
                                                                    uint32_t* __restrict__ item_base,
                                                                    uint32_t* __restrict__ item_bin,
@@ -150,14 +159,9 @@ __global__ void __launch_bounds__(BIN_SCAN_THREADS) bin_scan_kernel(const uint32
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int b = threadIdx.x * PER + j;
-    uint32_t sum = 0;
-    if (b < n_bins) {
-#pragma unroll 16
-      for (int s = 0; s < BIN_SEGS; ++s) sum += seg[(size_t)s * n_bins + b];
-    }
-    tot[j] = sum;
-    rec += sum;
-    items += bin_items(sum);
+    tot[j] = b < n_bins ? total[b] : 0u;
+    rec += tot[j];
+    items += bin_items(tot[j]);
   }
   // exclusive scans of (records, items) over the threads' bin groups
   uint32_t ir = rec, ii = items;
@@ -174,7 +178,6 @@ __global__ void __launch_bounds__(BIN_SCAN_THREADS) bin_scan_kernel(const uint32
   for (int j = 0; j < PER; ++j) {
     const int b = threadIdx.x * PER + j;
     if (b >= n_bins) break;
-    total[b] = tot[j];
     base[b] = r0;
     item_base[b] = i0;
     const uint32_t nb = bin_items(tot[j]);
@@ -448,7 +451,8 @@ hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, float*
   const dim3 seg_grid((p.n_bins + BIN_SCAN_BINS - 1) / BIN_SCAN_BINS, BIN_SEGS);
   hipLaunchKernelGGL(bin_segsum_kernel, seg_grid, dim3(BIN_SCAN_BINS), 0, st, p.cursor, p.cap, p.hist, p.n_bins,
                      p.seg);
-  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(BIN_SCAN_THREADS), 0, st, p.seg, p.n_bins, p.total, p.base,
+  hipLaunchKernelGGL(bin_total_kernel, dim3(seg_grid.x), dim3(BIN_SCAN_BINS), 0, st, p.seg, p.n_bins, p.total);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(BIN_SCAN_THREADS), 0, st, p.total, p.n_bins, p.base,
                      p.item_base, p.item_bin, p.n_items);
   hipLaunchKernelGGL(bin_offsets_kernel, seg_grid, dim3(BIN_SCAN_BINS), 0, st, p.cursor, p.cap, p.hist, p.n_bins,
                      p.seg, p.base);
