@@ -9,33 +9,43 @@
 
 namespace mnr {
 
-// Gradient scatter with fewer atomics.  The 64 lanes of a wave are 64
-// consecutive samples of one ray, so at coarse grid levels (and in the
-// blend-weight volume) neighbouring lanes often fall in the same cell and
-// would add to the same addresses.  Such runs are summed across the wave
-// first and only the first lane of a run issues the atomics.  Global float
-// atomics are executed at the memory side on this GPU (its eight L2s are
-// not coherent with each other), so their count bounds the adjoint.
+// Gradient scatter with fewer atomics (or records).  The 64 lanes of a
+// wave are 64 consecutive samples of one ray, so at coarse grid levels (and
+// in the blend-weight volume) neighbouring lanes often fall in the same cell
+// and would add to the same addresses.  Such runs are summed across the
+// wave first and only the last lane of a run (its owner) issues the atomics
+// or writes the record.
 struct CellRuns {
-  int seg;    // run index of the lane (number of run starts at lanes <= lane)
-  int steps;  // suffix-scan steps needed to sum the longest run
-  bool head;  // first lane of its run
+  int seg;     // run index of the lane (number of run starts at lanes <= lane)
+  int steps;   // in-row scan steps needed for the longest run (0..4)
+  bool owner;  // last lane of its run: holds the run's sum after run_sums
+  bool b15;    // (wave-uniform) a run crosses from row 0 to 1 or from row 2 to 3
+  bool b31;    // (wave-uniform) a run crosses from row 1 to 2
 };
+
+// Lane i - 1's value across the whole wave (DPP wave_shr:1; lane 0 keeps old).
+__device__ __forceinline__ int wave_prev(int x, int old) {
+  return __builtin_amdgcn_update_dpp(old, x, 0x138, 0xf, 0xf, false);
+}
 
 __device__ __forceinline__ CellRuns cell_runs(bool live, int x, int y, int z) {
   const int lane = lane_id();
-  const int px = __shfl_up(x, 1, WAVE), py = __shfl_up(y, 1, WAVE), pz = __shfl_up(z, 1, WAVE);
-  const int plive = __shfl_up(live ? 1 : 0, 1, WAVE);
+  const int px = wave_prev(x, 0), py = wave_prev(y, 0), pz = wave_prev(z, 0);
+  const int plive = wave_prev(live ? 1 : 0, 0);
+  const bool head = !live || lane == 0 || !plive || px != x || py != y || pz != z;
+  const uint64_t heads = __ballot(head);
   CellRuns r;
-  r.head = !live || lane == 0 || !plive || px != x || py != y || pz != z;
-  const uint64_t heads = __ballot(r.head);
   r.seg = (int)__popcll(heads & (~0ull >> (63 - lane)));
-  // Longest run: a run of length >= 2^j + 1 needs 2^j non-start lanes in a
-  // row after its start; count the doublings (bits past lane 63 are starts).
+  r.owner = lane == WAVE - 1 || (((heads >> lane) >> 1) & 1ull);
+  r.b15 = !((heads >> 16) & (heads >> 48) & 1ull);
+  r.b31 = !((heads >> 32) & 1ull);
+  // Longest run within a row: a run of length >= 2^j + 1 needs 2^j
+  // non-start lanes in a row after its start; count the doublings (at most
+  // 4 within a 16-lane row; bits past lane 63 are starts).
   uint64_t z0 = ~heads;
   int steps = 0;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < 4; ++j) {
     if (z0 == 0) break;
     ++steps;
     z0 &= z0 >> (1 << j);
@@ -44,22 +54,33 @@ __device__ __forceinline__ CellRuns cell_runs(bool live, int x, int y, int z) {
   return r;
 }
 
-// In-run suffix sums: afterwards the first lane of every run holds the sum
-// of the run's values (segmented Hillis-Steele scan over the wave).
+// One step of the segmented scan: every lane adds the value DPP control
+// CTRL brings from another lane (0 where it brings none) when that lane is
+// in the same run.
+template <int CTRL, int ROWS, int NV>
+__device__ __forceinline__ void run_step(int seg, float (&v)[NV]) {
+  const bool same = __builtin_amdgcn_update_dpp(-1, seg, CTRL, ROWS, 0xf, false) == seg;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const float o = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), CTRL,
+                                                                          ROWS, 0xf, false));
+    v[k] += same ? o : 0.f;
+  }
+}
+
+// In-run prefix sums on DPP (no LDS traffic): afterwards the last lane of
+// every run holds the sum of the run's values.  Segmented Hillis-Steele
+// scan within each 16-lane row (row_shr 1, 2, 4, 8, as far as the longest
+// run needs), then the row carries (row_bcast 15 into rows 1 and 3,
+// row_bcast 31 into rows 2 and 3), each only where some run crosses.
 template <int NV>
 __device__ __forceinline__ void run_sums(const CellRuns& r, float (&v)[NV]) {
-  const int lane = lane_id();
-#pragma unroll 1
-  for (int j = 0; j < r.steps; ++j) {
-    const int d = 1 << j;
-    const int seg_d = __shfl_down(r.seg, d, WAVE);
-    const bool same = lane + d < WAVE && seg_d == r.seg;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const float o = __shfl_down(v[k], d, WAVE);
-      v[k] += same ? o : 0.f;
-    }
-  }
+  if (r.steps >= 1) run_step<0x111, 0xf>(r.seg, v);
+  if (r.steps >= 2) run_step<0x112, 0xf>(r.seg, v);
+  if (r.steps >= 3) run_step<0x114, 0xf>(r.seg, v);
+  if (r.steps >= 4) run_step<0x118, 0xf>(r.seg, v);
+  if (r.b15) run_step<0x142, 0xa>(r.seg, v);
+  if (r.b31) run_step<0x143, 0xc>(r.seg, v);
 }
 
 // Corner pair q of a weight-volume cell (corners 2q at x0 and 2q + 1 at
@@ -86,7 +107,7 @@ __device__ __forceinline__ uint32_t wc_record_count(const RenderArgs& a, const f
     const CellRuns cr = cell_runs(live, t.i0[0], t.i0[1], t.i0[2]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      n += (uint32_t)__popcll(__ballot(live && cr.head && wc_pair_inside(t, a.m.res, q)));
+      n += (uint32_t)__popcll(__ballot(live && cr.owner && wc_pair_inside(t, a.m.res, q)));
   }
   return n;
 }
@@ -165,7 +186,7 @@ __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[
       const int x0 = t.i0[0];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {  // pair q: corners 2q (x0) and 2q + 1 (x0 + 1) at y0 + (q & 1), z0 + (q >> 1)
-        const bool in = live && cr.head && wc_pair_inside(t, R, q);
+        const bool in = live && cr.owner && wc_pair_inside(t, R, q);
         const uint64_t m = __ballot(in);
         if (in) {
           const uint32_t idx = wc_off + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
@@ -181,7 +202,7 @@ __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[
         }
         wc_off += (uint32_t)__popcll(m);
       }
-    } else if (live && cr.head) {
+    } else if (live && cr.owner) {
       float* gplane = a.grad_weights + b * plane;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {

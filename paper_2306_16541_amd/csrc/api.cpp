@@ -717,20 +717,28 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   const int64_t n_wc = (int64_t)(motion->n_bones + 1) * n_vox;
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; return r == hipSuccess; };
-  if (n_table) ok(launch_zero(st->table_grad, n_table * 4, s));
-  for (int k = 0; k < field->n_layers; ++k) ok(launch_zero(st->w_grad[k], layer_elems(field, k) * 4, s));
-  ok(launch_zero(st->weights_grad, n_wc * 4, s));
+  // every gradient buffer (and the render queues) cleared in one launch
+  ZeroList zl{};
+  auto clear = [&](void* p, int64_t bytes) {
+    zl.p[zl.n] = p;
+    zl.bytes[zl.n++] = bytes;
+  };
+  if (n_table) clear(st->table_grad, n_table * 4);
+  for (int k = 0; k < field->n_layers; ++k) clear(st->w_grad[k], layer_elems(field, k) * 4);
+  clear(st->weights_grad, n_wc * 4);
   const int64_t n_omega = 3 * (int64_t)motion->n_bones;
   const int64_t res_n[6] = {64 * 32, 64 * 64, 64 * 64, 64 * 96, 3 * 64, 64 * n_omega};  // W1..W5, W_omega
   if (motion->res_w[0])
-    for (int k = 0; k < 6; ++k) ok(launch_zero(st->res_grad[k], res_n[k] * 4, s));
+    for (int k = 0; k < 6; ++k) clear(st->res_grad[k], res_n[k] * 4);
+  if (st->train_motion) clear(st->logits_grad, n_wc * 4);
+  if (st->workspace) clear(st->workspace, MNR_WORKSPACE_BYTES);
+  ok(launch_zero_list(zl, s));
   RenderArgs a;
   pack_args(a, field, motion, pose, cam, H, W, spp, opts, pixel_ids, n_rays);
   const int slots = slot_count(H, W, pixel_ids, n_rays);
   a.out = st->rgba;
   a.t_chunks = st->t_chunks;
   a.queues = (int32_t*)st->workspace;
-  if (st->workspace) ok(launch_zero(st->workspace, MNR_WORKSPACE_BYTES, s));
   ok(launch_render_fwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
   ok(launch_mse(st->rgba, target, n_rays, st->grad_rgba, st->loss, s));
   a.grad_rgba = st->grad_rgba;
@@ -743,23 +751,37 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
     for (int k = 0; k < 6; ++k) a.grad_res[k] = st->res_grad[k];
   if (st->workspace) ok(launch_zero(st->workspace, MNR_WORKSPACE_BYTES, s));
   ok(adjoint_launches(a, plan, slots, field, st->table_grad, s));
-  if (motion->res_w[0])  // Adam on the residual network's FP32 masters, then its BF16 copies
-    for (int k = 0; k < 6; ++k)
-      ok(launch_adam(st->res_master[k], st->res_grad[k], st->res_m[k], st->res_v[k], res_n[k], st->lr_res, st->beta1,
-                     st->beta2, st->eps, st->step, (void*)motion->res_w[k], MNR_BF16, s));
+  if (motion->res_w[0]) {  // Adam on the residual network's FP32 masters, then its BF16 copies
+    AdamList rl{};
+    for (int k = 0; k < 6; ++k) {
+      rl.p[k] = st->res_master[k];
+      rl.g[k] = st->res_grad[k];
+      rl.m[k] = st->res_m[k];
+      rl.v[k] = st->res_v[k];
+      rl.low[k] = (void*)motion->res_w[k];
+      rl.n[k] = res_n[k];
+    }
+    rl.count = 6;
+    ok(launch_adam_list(rl, st->lr_res, st->beta1, st->beta2, st->eps, st->step, MNR_BF16, s));
+  }
   if (n_table)
     ok(launch_adam(st->table_master, st->table_grad, st->table_m, st->table_v, n_table, st->lr_field, st->beta1,
                    st->beta2, st->eps, st->step, field->table_dtype == MNR_F32 ? nullptr : (void*)field->table,
                    field->table_dtype, s));
   if (field->dense_packed && a.f.dense_mask) ok(launch_pack_dense(a.f, field->table_dtype, s));
-  for (int k = 0; k < field->n_layers; ++k)
-    ok(launch_adam(st->w_master[k], st->w_grad[k], st->w_m[k], st->w_v[k], layer_elems(field, k), st->lr_field,
-                   st->beta1, st->beta2, st->eps, st->step,
-                   field->mlp_dtype == MNR_F32 ? nullptr : (void*)field->w[k], field->mlp_dtype, s));
-  if (st->train_motion) {
-    ok(launch_zero(st->logits_grad, n_wc * 4, s));
-    ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));
+  AdamList ml{};  // the MLP's layers in one launch
+  for (int k = 0; k < field->n_layers; ++k) {
+    ml.p[k] = st->w_master[k];
+    ml.g[k] = st->w_grad[k];
+    ml.m[k] = st->w_m[k];
+    ml.v[k] = st->w_v[k];
+    ml.low[k] = field->mlp_dtype == MNR_F32 ? nullptr : (void*)field->w[k];
+    ml.n[k] = layer_elems(field, k);
   }
+  ml.count = field->n_layers;
+  ok(launch_adam_list(ml, st->lr_field, st->beta1, st->beta2, st->eps, st->step, field->mlp_dtype, s));
+  if (st->train_motion)  // (logits_grad was cleared with the gradients)
+    ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));
   if (st->train_motion == 1) {
     ok(launch_adam(st->logits, st->logits_grad, st->logits_m, st->logits_v, n_wc, st->lr_motion, st->beta1,
                    st->beta2, st->eps, st->step, nullptr, MNR_F32, s));

@@ -102,6 +102,27 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float eps, int step, void* lowp, mnr_dtype dt, hipStream_t st);
 hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st);
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
+// Several fills, or Adam on several tensors (same hyper-parameters, BF16 or
+// F16 copies or none), in one launch each: the training step's small
+// tensors would otherwise cost a launch apiece.
+constexpr int MAX_LIST = 24;
+struct ZeroList {
+  void* p[MAX_LIST];
+  int64_t bytes[MAX_LIST];
+  int n;
+};
+hipError_t launch_zero_list(const ZeroList& z, hipStream_t st);
+struct AdamList {
+  float* p[MAX_LIST];
+  const float* g[MAX_LIST];
+  float* m[MAX_LIST];
+  float* v[MAX_LIST];
+  void* low[MAX_LIST];  // the low-precision copy (NULL: none)
+  int64_t n[MAX_LIST];
+  int count;
+};
+hipError_t launch_adam_list(const AdamList& l, float lr, float b1, float b2, float eps, int step, mnr_dtype low_dt,
+                            hipStream_t st);
 // Packed copy of the bone channels of a blend-weight volume (2x2 x-y corners
 // per float4; layout in mnr_motion_packed_bytes' declaration).
 hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hipStream_t st);

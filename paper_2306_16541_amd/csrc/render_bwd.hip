@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
             if (!((a.f.dense_mask >> l) & 1u)) continue;
             const GridCell gc = grid_cell(u, a.f.level_res[l]);
             const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
-            n_runs += (uint32_t)__popcll(__ballot(live && cr.head));
+            n_runs += (uint32_t)__popcll(__ballot(live && cr.owner));
           }
         }
         const uint32_t n_tab = (n_live * n_hashed + n_runs) * 8u;
@@ -433,9 +433,9 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
         const CellRuns cr = cell_runs(live, gc.i0[0], gc.i0[1], gc.i0[2]);
         run_sums<16>(cr, v);
         if (rec_ok && a.rec.dense) {  // dense level: one record per corner and run
-          const uint64_t hm = __ballot(live && cr.head);
+          const uint64_t hm = __ballot(live && cr.owner);
           const uint32_t n_runs = (uint32_t)__popcll(hm);
-          if (live && cr.head) {
+          if (live && cr.owner) {
             const uint32_t r = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
             const uint32_t first = rec_base + n_live * n_hashed * 8u + dense_off * 8u;
 #pragma unroll
@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           dense_key += (uint32_t)(N + 1) * (uint32_t)(N + 1) * (uint32_t)(N + 1);
           continue;
         }
-        if (live && cr.head) {
+        if (live && cr.owner) {
           float* gt = a.grad_table + (size_t)l * T * 2;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {

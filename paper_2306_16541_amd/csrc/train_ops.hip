@@ -102,6 +102,44 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   return hipGetLastError();
 }
 
+// Tensor blockIdx.y of the list; the x blocks stride over it.
+template <typename LowT>
+__global__ void adam_list_kernel(const AdamList l, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  const int k = blockIdx.y;
+  float* __restrict__ p = l.p[k];
+  const float* __restrict__ g = l.g[k];
+  float* __restrict__ m = l.m[k];
+  float* __restrict__ v = l.v[k];
+  LowT* __restrict__ low = (LowT*)l.low[k];
+  const int64_t n = l.n[k];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    if (low) low[i] = (LowT)pi;
+  }
+}
+
+hipError_t launch_adam_list(const AdamList& l, float lr, float b1, float b2, float eps, int step, mnr_dtype low_dt,
+                            hipStream_t st) {
+  if (l.count <= 0) return hipSuccess;
+  if (l.count > MAX_LIST) return hipErrorInvalidValue;
+  const float bc1 = 1.f - (float)std::pow((double)b1, (double)step);
+  const float bc2 = 1.f - (float)std::pow((double)b2, (double)step);
+  int64_t most = 0;
+  for (int k = 0; k < l.count; ++k) most = l.n[k] > most ? l.n[k] : most;
+  const dim3 grid(grid_for(most, 256), l.count);
+  if (low_dt == MNR_BF16)
+    hipLaunchKernelGGL(adam_list_kernel<__bf16>, grid, dim3(256), 0, st, l, lr, b1, b2, eps, bc1, bc2);
+  else
+    hipLaunchKernelGGL(adam_list_kernel<_Float16>, grid, dim3(256), 0, st, l, lr, b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
 template <typename LowT>
 __global__ void convert_kernel(const float* __restrict__ s, LowT* __restrict__ d, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -119,6 +157,24 @@ hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, 
 __global__ void zero_kernel(uint32_t* __restrict__ d, int64_t n_words) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
     d[i] = 0u;
+}
+
+// Buffer blockIdx.y of the list (byte counts that are multiples of 4).
+__global__ void zero_list_kernel(const ZeroList z) {
+  const int k = blockIdx.y;
+  uint32_t* __restrict__ d = (uint32_t*)z.p[k];
+  const int64_t n = z.bytes[k] / 4;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = 0u;
+}
+
+hipError_t launch_zero_list(const ZeroList& z, hipStream_t st) {
+  if (z.n <= 0) return hipSuccess;
+  if (z.n > MAX_LIST) return hipErrorInvalidValue;
+  int64_t most = 0;
+  for (int k = 0; k < z.n; ++k) most = z.bytes[k] / 4 > most ? z.bytes[k] / 4 : most;
+  hipLaunchKernelGGL(zero_list_kernel, dim3(grid_for(most, 256), z.n), dim3(256), 0, st, z);
+  return hipGetLastError();
 }
 
 // One float4 per (bone, z, y+1, x+1): the blend weights of the cell's four
@@ -142,9 +198,21 @@ hipError_t launch_pack_motion(const float* w, f4* packed, int n_bones, int R, hi
 
 // One group per (z, y, x) cell base of a dense level: the rows of its four
 // x-y corners in plane z, 2 features each, copied in the table's dtype.
+// Dense level blockIdx.y of the list, all levels in one launch.
+struct DenseList {
+  const void* level[MNR_MAX_LEVELS];
+  void* out[MNR_MAX_LEVELS];
+  int N[MNR_MAX_LEVELS];
+  int n;
+};
+
 template <typename TableT>
-__global__ void pack_dense_kernel(const TableT* __restrict__ level, TableT* __restrict__ out, int N, int64_t n) {
-  const int64_t s = N + 1;
+__global__ void pack_dense_kernel(const DenseList d) {
+  const int k = blockIdx.y;
+  const TableT* __restrict__ level = (const TableT*)d.level[k];
+  TableT* __restrict__ out = (TableT*)d.out[k];
+  const int N = d.N[k];
+  const int64_t s = N + 1, n = (int64_t)(N + 1) * N * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = e % N, y = (e / N) % N, z = e / ((int64_t)N * N);
     const int64_t r0 = x + s * (y + s * z);
@@ -159,22 +227,25 @@ __global__ void pack_dense_kernel(const TableT* __restrict__ level, TableT* __re
 
 hipError_t launch_pack_dense(const FieldArgs& f, mnr_dtype dt, hipStream_t st) {
   const size_t T = (size_t)1 << f.log2_T;
+  const size_t esz = dt == MNR_F32 ? 4 : 2;
+  DenseList d{};
+  int64_t most = 0;
   for (int l = 0; l < f.n_levels; ++l) {
     if (!((f.dense_mask >> l) & 1u)) continue;
     const int N = f.level_res[l];
+    d.level[d.n] = (const char*)f.table + (size_t)l * T * 2 * esz;
+    d.out[d.n] = (char*)f.dpk + f.dpk_off[l];  // (a byte offset)
+    d.N[d.n++] = N;
     const int64_t n = (int64_t)(N + 1) * N * N;
-    if (dt == MNR_F32)
-      hipLaunchKernelGGL(pack_dense_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, st,
-                         (const float*)f.table + (size_t)l * T * 2, (float*)(f.dpk + f.dpk_off[l]), N, n);
-    else
-      hipLaunchKernelGGL(pack_dense_kernel<_Float16>, dim3(grid_for(n, 256)), dim3(256), 0, st,
-                         (const _Float16*)f.table + (size_t)l * T * 2, (_Float16*)(f.dpk + f.dpk_off[l]), N, n);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    most = n > most ? n : most;
   }
-  return hipSuccess;
+  if (d.n == 0) return hipSuccess;
+  if (dt == MNR_F32)
+    hipLaunchKernelGGL(pack_dense_kernel<float>, dim3(grid_for(most, 256), d.n), dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL(pack_dense_kernel<_Float16>, dim3(grid_for(most, 256), d.n), dim3(256), 0, st, d);
+  return hipGetLastError();
 }
-
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st) {
   const int64_t n = (int64_t)(bytes / 4);
   hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, (uint32_t*)dst, n);
