@@ -278,9 +278,10 @@ __device__ __forceinline__ void composite_adjoint(float T0, float delta, const f
 // Ray slot r of a split-adjoint kernel: waves take slots in turn.
 __device__ __forceinline__ bool split_ray(const RenderArgs& a, int slot, int& orow, RaySetup& rs, int& n_done,
                                           int nchunks) {
-  const int pix = ray_pixel(a.r, slot);
+  const int row = ray_row(a.r, slot);
+  const int pix = ray_pixel(a.r, row);
   if (!a.r.pixel_ids && pix < 0) return false;
-  orow = a.r.pixel_ids ? slot : pix;
+  orow = a.r.pixel_ids ? row : pix;
   if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) return false;
   n_done = (int)a.t_chunks[(size_t)orow * (nchunks + 1) + nchunks];
   return true;

@@ -414,19 +414,24 @@ static uint64_t split_layout(const mnr_field* f, const mnr_motion* m, int n_rays
 
 // The adjoint workspace: the binned scatter's part (table and blend-weight
 // gradient records), then the split adjoint's (with a residual network or
-// the frequency-encoded field).
+// the frequency-encoded field), then (with either) a ray list's processing
+// order (n_rays rows).
 static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, char* ws,
-                               ScatterPlan* p, SplitArgs* sp) {
+                               ScatterPlan* p, SplitArgs* sp, int32_t** order = nullptr) {
   const uint64_t a = scatter_layout(f, m, n_rays, spp, ws, p);
   const uint64_t b = split_layout(f, m, n_rays, spp, ws ? ws + a : nullptr, sp);
-  return a + b;
+  const uint64_t c = (a + b) ? align256((uint64_t)n_rays * 4) : 0;
+  if (order) *order = (ws && c) ? (int32_t*)(ws + a + b) : nullptr;
+  return a + b + c;
 }
 
 // Validates a caller's adjoint workspace and points the adjoint at it.
 static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
-                                uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp) {
+                                uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp,
+                                int32_t*& order) {
   rec = RecordSink{nullptr, nullptr, nullptr, 0, 0, 0, 0u};
   sp = SplitArgs{nullptr, 0, nullptr, nullptr};
+  order = nullptr;
   if (!ws) {
     if (m->res_w[0]) return fail(MNR_E_INVALID, "the residual network's adjoint needs the adjoint workspace");
     if (f->encoding == MNR_ENC_FREQ)
@@ -436,7 +441,8 @@ static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_r
   if ((uintptr_t)ws & 255) return fail(MNR_E_INVALID, "adjoint workspace not 256-byte aligned");
   ScatterPlan pp{};
   SplitArgs ss{nullptr, 0, nullptr, nullptr};
-  const uint64_t need = adjoint_layout(f, m, n_rays, spp, (char*)ws, &pp, &ss);
+  int32_t* ord = nullptr;
+  const uint64_t need = adjoint_layout(f, m, n_rays, spp, (char*)ws, &pp, &ss, &ord);
   if (need == 0) return fail(MNR_E_UNSUPPORTED, "adjoint workspace: nothing to use it for (nothing keyed, no residual network, not the frequency-encoded field, or a batch or table too large)");
   if (ws_bytes < need)
     return fail(MNR_E_SHAPE, "adjoint workspace has %llu bytes, needs %llu", (unsigned long long)ws_bytes,
@@ -446,7 +452,16 @@ static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_r
     rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0, p.wc ? 1 : 0, p.map.wc_start};
   }
   sp = ss;
+  order = ord;
   return MNR_OK;
+}
+
+// With a ray list and room in the adjoint workspace: the spatially coherent
+// processing order, computed on the stream.
+static hipError_t order_rays(RenderArgs& a, int32_t* order, hipStream_t st) {
+  if (!a.r.pixel_ids || !order) return hipSuccess;
+  a.r.order = order;
+  return launch_ray_order(a.r.pixel_ids, a.r.n_rays, a.r.H, a.r.W, order, st);
 }
 
 // The adjoint's launches: with the residual network or the frequency-
@@ -550,13 +565,16 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
   if (motion->res_w[0])
     for (int k = 0; k < 6; ++k) a.grad_res[k] = grad_res[k];
   ScatterPlan plan{};
-  if (mnr_status s = adjoint_setup(field, motion, n_rays, spp, adjoint_ws, adjoint_ws_bytes, a.rec, plan, a.split))
+  int32_t* order = nullptr;
+  if (mnr_status s = adjoint_setup(field, motion, n_rays, spp, adjoint_ws, adjoint_ws_bytes, a.rec, plan, a.split,
+                                   order))
     return s;
   a.queues = (int32_t*)workspace;
   hipStream_t st = (hipStream_t)stream;
   if (workspace) {
     if (mnr_status s = hip_status(launch_zero(workspace, MNR_WORKSPACE_BYTES, st), "workspace")) return s;
   }
+  if (mnr_status s = hip_status(order_rays(a, order, st), "ray order")) return s;
   return hip_status(adjoint_launches(a, plan, slot_count(H, W, pixel_ids, n_rays), field, grad_table, st),
                     "backward launch");
 }
@@ -708,7 +726,9 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   ScatterPlan plan{};
   RecordSink rec{};
   SplitArgs split{};
-  if (mnr_status r = adjoint_setup(field, motion, n_rays, spp, st->adjoint_ws, st->adjoint_ws_bytes, rec, plan, split))
+  int32_t* order = nullptr;
+  if (mnr_status r = adjoint_setup(field, motion, n_rays, spp, st->adjoint_ws, st->adjoint_ws_bytes, rec, plan, split,
+                                   order))
     return r;
   hipStream_t s = (hipStream_t)stream;
   const int64_t T = int64_t(1) << field->log2_T;
@@ -739,6 +759,7 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   a.out = st->rgba;
   a.t_chunks = st->t_chunks;
   a.queues = (int32_t*)st->workspace;
+  ok(order_rays(a, order, s));  // forward and adjoint in the same coherent order
   ok(launch_render_fwd(a, slots, field->table_dtype, field->mlp_dtype, field->n_layers - 2, s));
   ok(launch_mse(st->rgba, target, n_rays, st->grad_rgba, st->loss, s));
   a.grad_rgba = st->grad_rgba;

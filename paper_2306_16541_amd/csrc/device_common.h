@@ -63,6 +63,7 @@ struct RayArgs {
   double bmin[3], bmax[3];
   int32_t H, W, spp, n_rays;
   const int32_t* pixel_ids;  // NULL: full frame in 16x16-tile order
+  const int32_t* order;      // ray list only: row of the ray that slot b processes (NULL: row b)
   int32_t tiles_x;           // full-frame tiling
   float ert_tau;
   float bg[3];
@@ -166,6 +167,12 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
 // Pixel id of ray slot b: explicit list, or full frame in 16x16 tiles
 // (rows of tiles, row-major inside a tile) so that consecutive rays are
 // 2-D neighbours.  Returns -1 for tile slots outside the image.
+// Ray-list row processed by slot b: a spatially coherent order of the list
+// when there is one (neighbouring slots share an XCD's work queue, so their
+// gathers share its L2), else b.
+__device__ __forceinline__ int ray_row(const RayArgs& r, int b) { return r.order ? r.order[b] : b; }
+
+// Pixel of ray-list row b, or of full-frame slot b.
 __device__ __forceinline__ int ray_pixel(const RayArgs& r, int b) {
   if (r.pixel_ids) return r.pixel_ids[b];
   const int tile = b >> 8, inner = b & 255;

@@ -102,6 +102,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float eps, int step, void* lowp, mnr_dtype dt, hipStream_t st);
 hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st);
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
+// Spatially coherent processing order of a ray list (order[slot] = row).
+hipError_t launch_ray_order(const int32_t* pixel_ids, int n, int H, int W, int32_t* order, hipStream_t st);
 // Several fills, or Adam on several tensors (same hyper-parameters, BF16 or
 // F16 copies or none), in one launch each: the training step's small
 // tensors would otherwise cost a launch apiece.

@@ -89,9 +89,10 @@ __global__ void __launch_bounds__(64 * NW) render_fwd_kernel(const RenderArgs a,
       slot = ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
       if (slot < 0) continue;
     }
-    const int pix = ray_pixel(a.r, slot);
+    const int row = ray_row(a.r, slot);
+    const int pix = ray_pixel(a.r, row);
     if (!a.r.pixel_ids && pix < 0) continue;  // tile slot outside the image
-    const int orow = a.r.pixel_ids ? slot : pix;
+    const int orow = a.r.pixel_ids ? row : pix;
     RaySetup rs;
     const bool hit = pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs);
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, Tr = 1.f;

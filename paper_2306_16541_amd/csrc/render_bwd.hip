@@ -271,9 +271,10 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       slot = bwd_ray_slot<NW>(blockIdx.x, gridDim.x, wave, it, n_slots);
       if (slot < 0) continue;
     }
-    const int pix = ray_pixel(a.r, slot);
+    const int row = ray_row(a.r, slot);
+    const int pix = ray_pixel(a.r, row);
     if (!a.r.pixel_ids && pix < 0) continue;
-    const int orow = a.r.pixel_ids ? slot : pix;
+    const int orow = a.r.pixel_ids ? row : pix;
     RaySetup rs;
     if (!(pix >= 0 && pix < a.r.H * a.r.W && setup_ray(a.r, pix, rs))) continue;
     const f4 gout = *(const f4*)(a.grad_rgba + (size_t)orow * 4);

@@ -159,6 +159,63 @@ __global__ void zero_kernel(uint32_t* __restrict__ d, int64_t n_words) {
     d[i] = 0u;
 }
 
+// Processing order of a ray list: a counting sort of the rays by the
+// Morton index of their pixel's cell in a 64 x 64 grid over the image (one
+// block; not stable).  Rays that are close on the image sample close points,
+// so neighbouring slots then gather from the same table and blend-weight
+// lines.
+constexpr int ORDER_THREADS = 1024;
+constexpr int ORDER_CELLS = 4096;
+
+__device__ __forceinline__ uint32_t order_cell(int pix, int H, int W) {
+  if (pix < 0 || pix >= H * W) return 0u;
+  const uint32_t x = (uint32_t)(pix % W) * 64u / (uint32_t)W, y = (uint32_t)(pix / W) * 64u / (uint32_t)H;
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) m |= (((x >> b) & 1u) << (2 * b)) | (((y >> b) & 1u) << (2 * b + 1));
+  return m;
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS) ray_order_kernel(const int32_t* __restrict__ pixel_ids, int n, int H,
+                                                                 int W, int32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[ORDER_CELLS];
+  __shared__ uint32_t red[ORDER_THREADS / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x >> 6;
+  for (int c = threadIdx.x; c < ORDER_CELLS; c += ORDER_THREADS) cnt[c] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += ORDER_THREADS) atomicAdd(&cnt[order_cell(pixel_ids[i], H, W)], 1u);
+  __syncthreads();
+  constexpr int PER = ORDER_CELLS / ORDER_THREADS;  // consecutive cells per thread
+  uint32_t loc[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    loc[j] = cnt[threadIdx.x * PER + j];
+    sum += loc[j];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, WAVE);
+    if (lane >= d) incl += o;
+  }
+  if (lane == WAVE - 1) red[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += red[w];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    cnt[threadIdx.x * PER + j] = run;
+    run += loc[j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += ORDER_THREADS) order[atomicAdd(&cnt[order_cell(pixel_ids[i], H, W)], 1u)] = i;
+}
+
+hipError_t launch_ray_order(const int32_t* pixel_ids, int n, int H, int W, int32_t* order, hipStream_t st) {
+  hipLaunchKernelGGL(ray_order_kernel, dim3(1), dim3(ORDER_THREADS), 0, st, pixel_ids, n, H, W, order);
+  return hipGetLastError();
+}
+
 // Buffer blockIdx.y of the list (byte counts that are multiples of 4).
 __global__ void zero_list_kernel(const ZeroList z) {
   const int k = blockIdx.y;

@@ -233,7 +233,8 @@ def test_adjoint_workspace_size_and_checks():
     # when res is a power of two); with a residual network or the
     # frequency-encoded field, 21 floats per sample slot and 64 floats of
     # bias gradient, and for the frequency-encoded field 512 bytes of saved
-    # activations per slot (include/metanerf.h).
+    # activations per slot; then 4 bytes per ray of processing order
+    # (include/metanerf.h).
     m = _lib()
     sc = scenes.scene_body(H=8, W=8, spp=8, res=8, log2_T=19)
     _, f, mo, pose, cam = _args(sc)
@@ -249,15 +250,17 @@ def test_adjoint_workspace_size_and_checks():
     n_keys = wc0 + 24 * 8 ** 3
     for n_rays, spp in ((8192, 128), (100, 7)):
         want = _scatter_ws_bytes(n_rays, spp, nk * 8 + 24 * 4, n_keys)
-        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want
+        order = a256(n_rays * 4)
+        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + order
         for k in range(6):
             mo.res_w[k] = 0x7000 + 0x100 * k
         split = a256(21 * n_rays * -(-spp // 64) * 64 * 4) + 256
-        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split
+        assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), n_rays, spp) == want + split + order
         for k in range(6):
             mo.res_w[k] = None
     mo.res = 6          # not a power of two: the blend-weight gradient keeps atomics
-    assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 100, 7) == _scatter_ws_bytes(100, 7, nk * 8, table_keys)
+    assert (m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 100, 7) ==
+            _scatter_ws_bytes(100, 7, nk * 8, table_keys) + a256(400))
     mo.res = 8
     ff = m.Field()      # the frequency-encoded field: blend-weight records, split scratch and saved activations
     ff.encoding, ff.mlp_dtype, ff.n_layers = 1, m.BF16, 5
@@ -268,7 +271,7 @@ def test_adjoint_workspace_size_and_checks():
     for n_rays, spp in ((8192, 128), (100, 7)):
         chunks = n_rays * -(-spp // 64)
         want = (_scatter_ws_bytes(n_rays, spp, 24 * 4, 24 * 8 ** 3) + a256(21 * chunks * 64 * 4) + 256 +
-                chunks * 4 * 4 * 2 * 64 * 16)
+                chunks * 4 * 4 * 2 * 64 * 16 + a256(n_rays * 4))
         assert m.lib.mnr_adjoint_ws_bytes(C.byref(ff), C.byref(mo), n_rays, spp) == want
     assert m.lib.mnr_adjoint_ws_bytes(C.byref(f), C.byref(mo), 1 << 20, 1024) == 0   # >= 2^31 records
     f.log2_T = 24       # the largest table: its 4 hashed levels fill the key space (4096 slices of 2^14 rows), the rest keeps atomics
