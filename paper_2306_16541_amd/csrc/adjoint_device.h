@@ -83,6 +83,20 @@ __device__ __forceinline__ void run_sums(const CellRuns& r, float (&v)[NV]) {
   if (r.b31) run_step<0x143, 0xc>(r.seg, v);
 }
 
+// The wave's largest value bounds (float bits) into the sink's bounds: one
+// atomic per wave at the end of a kernel that wrote records.
+__device__ __forceinline__ void flush_value_bounds(const RecordSink& rec, uint32_t tab_mb, uint32_t wc_mb) {
+#pragma unroll
+  for (int k = WAVE / 2; k > 0; k >>= 1) {
+    tab_mb = max(tab_mb, (uint32_t)__shfl_xor((int)tab_mb, k, WAVE));
+    wc_mb = max(wc_mb, (uint32_t)__shfl_xor((int)wc_mb, k, WAVE));
+  }
+  if (lane_id() == 0) {
+    if (tab_mb) atomicMax(rec.vmax, tab_mb);
+    if (wc_mb) atomicMax(rec.vmax + 1, wc_mb);
+  }
+}
+
 // Corner pair q of a weight-volume cell (corners 2q at x0 and 2q + 1 at
 // x0 + 1, both at y0 + (q & 1), z0 + (q >> 1)) has a corner inside the
 // volume.  Points far from a bone map far outside its volume, so most
@@ -113,7 +127,9 @@ __device__ __forceinline__ uint32_t wc_record_count(const RenderArgs& a, const f
 }
 
 // Where skin_adjoint writes the chunk's blend-weight records: [base, end)
-// (records == false: global atomics).
+// (records == false: global atomics).  It raises wc_mb (the lane's largest
+// |value| written, as float bits: non-negative floats order as their bits,
+// NaN above infinity) for the binned sums' scale.
 struct WcRecords {
   bool records;
   uint32_t base, end;
@@ -132,7 +148,7 @@ struct WcRecords {
 // contribute nothing.
 __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[3], const float xs[3], float L,
                                              const float g_xs[3], float g_L, bool live, float* dg,
-                                             const WcRecords wr = WcRecords{false, 0u, 0u}) {
+                                             const WcRecords wr, uint32_t& wc_mb) {
   const int lane = lane_id();
   const int R = a.m.res;
   const size_t plane = (size_t)R * R * R;
@@ -199,6 +215,7 @@ __device__ __forceinline__ void skin_adjoint(const RenderArgs& a, const float x[
             a.rec.keys[idx] = key;
             a.rec.vals[idx] = val;
           }
+          wc_mb = max(wc_mb, max(__float_as_uint(fabsf(val[0])), __float_as_uint(fabsf(val[1]))));
         }
         wc_off += (uint32_t)__popcll(m);
       }

@@ -366,6 +366,7 @@ static uint64_t scatter_layout(const mnr_field* f, const mnr_motion* m, int n_ra
   char* n_items = take(4);
   if (p) {
     p->cursor = (uint32_t*)cursor;
+    p->vmax = (uint32_t*)cursor + 16;  // (the cursor's 256 bytes are cleared before every adjoint)
     p->keys = (uint32_t*)keys;
     p->vals = (f2*)vals;
     p->skeys = (uint32_t*)skeys;
@@ -429,7 +430,7 @@ static uint64_t adjoint_layout(const mnr_field* f, const mnr_motion* m, int n_ra
 static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_rays, int spp, void* ws,
                                 uint64_t ws_bytes, RecordSink& rec, ScatterPlan& p, SplitArgs& sp,
                                 int32_t*& order) {
-  rec = RecordSink{nullptr, nullptr, nullptr, 0, 0, 0, 0u};
+  rec = RecordSink{nullptr, nullptr, nullptr, 0, 0, 0, 0u, nullptr};
   sp = SplitArgs{nullptr, 0, nullptr, nullptr};
   order = nullptr;
   if (!ws) {
@@ -449,7 +450,7 @@ static mnr_status adjoint_setup(const mnr_field* f, const mnr_motion* m, int n_r
                 (unsigned long long)need);
   if (scatter_layout(f, m, n_rays, spp, nullptr, nullptr)) {
     p = pp;
-    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0, p.wc ? 1 : 0, p.map.wc_start};
+    rec = RecordSink{p.cursor, p.keys, p.vals, p.cap, p.dense ? 1 : 0, p.wc ? 1 : 0, p.map.wc_start, p.vmax};
   }
   sp = ss;
   order = ord;

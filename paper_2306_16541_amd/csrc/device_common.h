@@ -94,6 +94,8 @@ struct RecordSink {
   int32_t dense;     // 1: the dense levels leave as records too (keys after the hashed levels')
   int32_t wc;        // 1: the blend-weight gradient leaves as records too (else global atomics)
   uint32_t wc_key0;  // its first key
+  uint32_t* vmax;    // [2] bound on |value| (float bits, integer max) of the table's and the blend
+                     // weights' records: the binned sums' fixed-point scale (zero before the adjoint)
 };
 
 // Per-sample scratch of the split adjoint (used with the residual motion

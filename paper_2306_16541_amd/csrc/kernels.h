@@ -74,6 +74,7 @@ struct KeyMap {  // keyed level j: keys [start[j], start[j + 1]) are rows 0, 1, 
 };
 struct ScatterPlan {
   uint32_t* cursor;          // records written by the adjoint
+  uint32_t* vmax;            // [2] bounds on |value| of the table's and the blend weights' records
   uint32_t* keys;            // [cap]
   f2* vals;                  // [cap]
   uint32_t* skeys;           // [cap] records in bin order

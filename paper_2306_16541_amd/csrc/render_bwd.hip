@@ -261,6 +261,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
       for (int kt = 0; kt < 2; ++kt) acc.first[mt][kt] = z;
   }
   int q = blockIdx.x & 7, tried = 0;
+  uint32_t tab_mb = 0u, wc_mb = 0u;  // largest |value| of the lane's table / blend-weight records (float bits)
   for (int it = 0;; ++it) {
     int slot;
     if (a.queues) {  // dynamic: pull rays from per-XCD queues
@@ -415,6 +416,13 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
                   ((k & 4) ? gc.f[2] : 1.f - gc.f[2]);
         if (rec_ok && !dense) {  // hashed level: records
           if (live) {
+            // |wk d| <= max|wk| max|d| (rounding is monotone); maxima taken on
+            // the bits, so that NaN and infinity carry through
+            uint32_t wb = 0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wb = max(wb, __float_as_uint(fabsf(wk[k])));
+            const float dmax = __uint_as_float(max(__float_as_uint(fabsf(d0)), __float_as_uint(fabsf(d1))));
+            tab_mb = max(tab_mb, __float_as_uint(fabsf(dmax * __uint_as_float(wb))));
             const uint32_t h = (uint32_t)__popc(~a.f.dense_mask & ((1u << l) - 1u));
             const uint32_t key0 = h << a.f.log2_T;  // the hashed levels take the first keys
 #pragma unroll
@@ -446,6 +454,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
                 a.rec.keys[idx] = dense_key + grid_row(gc, N, dense, tmask, k);
                 a.rec.vals[idx] = f2{v[2 * k], v[2 * k + 1]};
               }
+              tab_mb = max(tab_mb, max(__float_as_uint(fabsf(v[2 * k])), __float_as_uint(fabsf(v[2 * k + 1]))));
             }
           }
           dense_off += n_runs;
@@ -480,11 +489,12 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
           sb[SPLIT_GL * ss + sj] = live ? g_L : 0.f;
         }
       } else {
-        skin_adjoint(a, st.x, st.xs, st.L, g_xs, g_L, live, dg, wcr);
+        skin_adjoint(a, st.x, st.xs, st.L, g_xs, g_L, live, dg, wcr, wc_mb);
       }
       wave_sync_lds();
     }
   }
+  if (a.rec.keys) flush_value_bounds(a.rec, tab_mb, wc_mb);
   // the waves' register sums into the block's LDS sums, one wave at a time
   for (int w = 0; w < NW; ++w) {
     if (wave == w) {

@@ -322,6 +322,7 @@ __global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderA
   const float* sb = a.split.buf;
   const int64_t ss = a.split.stride;
   const int gfield = a.res.w[0] ? SPLIT_GS : SPLIT_G;  // dL/dx_skel
+  uint32_t wc_mb = 0u;  // largest |value| of the lane's blend-weight records (float bits)
   for (int slot = blockIdx.x * SKIN_WAVES + wave; slot < n_slots; slot += gridDim.x * SKIN_WAVES) {
     int orow, n_done;
     RaySetup rs;
@@ -352,9 +353,10 @@ __global__ void __launch_bounds__(64 * SKIN_WAVES) skin_bwd_kernel(const RenderA
         const uint32_t base = __builtin_amdgcn_readfirstlane(b);
         wcr = WcRecords{cnt > 0 && (uint64_t)base + cnt <= (uint64_t)a.rec.cap, base, base + cnt};
       }
-      skin_adjoint(a, x, xs, L, gs, gL, live, dg, wcr);
+      skin_adjoint(a, x, xs, L, gs, gL, live, dg, wcr, wc_mb);
     }
   }
+  if (a.rec.keys) flush_value_bounds(a.rec, 0u, wc_mb);
   __syncthreads();
   if (a.grad_G)
     for (int i = threadIdx.x; i < a.m.n_bones * 12; i += blockDim.x)

@@ -320,14 +320,16 @@ __global__ void __launch_bounds__(BIN_THREADS) bin_scatter_kernel(const uint32_t
 // One block per item of a bin (and per 2^ACC_SHIFT-row part of the bin when
 // bins are larger): the slice's sums in LDS as 64-bit fixed point.  LDS
 // float atomics on this GPU are ~40x slower than integer ones, so every
-// value is scaled by a power of two chosen from the item's largest magnitude
-// and its record count (n max 2^S < 2^62: no sum can overflow), rounded to
-// an integer and added with integer atomics.  The integer sums are exact, so
-// a bin summed by one item does not depend on the order of its records;
-// each value is rounded once, by at most 2^-(S+1).  The items of a split bin
-// add their (exact) sums to the table gradient with float atomics.  An item
-// holding a non-finite value is summed in floats instead.  Keys map to
-// table rows or dL/dW^c elements through the key map.
+// value is scaled by a power of two chosen from a bound M on the values'
+// magnitudes (the adjoint's largest table or blend-weight record value) and
+// the item's record count (n M < 2^62: no sum can overflow), rounded to an
+// integer and added with integer atomics.  The integer sums are exact, so a
+// bin summed by one item does not depend on the order of its records; each
+// value is rounded once, by at most n M 2^-63 (for n = 2^16 records, 1e-14
+// of the largest value).  The items of a split bin add their (exact) sums to
+// the gradient with float atomics.  If M is not finite the values are summed
+// in floats instead.  Keys map to table rows or dL/dW^c elements through
+// the key map.
 __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint32_t* __restrict__ skeys,
                                                                      const f2* __restrict__ svals, int shift,
                                                                      const uint32_t* __restrict__ total,
@@ -335,10 +337,10 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
                                                                      const uint32_t* __restrict__ item_base,
                                                                      const uint32_t* __restrict__ item_bin,
                                                                      const uint32_t* __restrict__ n_items,
+                                                                     const uint32_t* __restrict__ vmax,
                                                                      const KeyMap map, float* __restrict__ grad,
                                                                      float* __restrict__ grad_w) {
   extern __shared__ unsigned long long acc[];  // [2][rows]: the two features in separate planes
-  __shared__ uint32_t max_bits;
   const int parts_log2 = shift > ACC_SHIFT ? shift - ACC_SHIFT : 0;
   const uint32_t item = blockIdx.x >> parts_log2;
   const int part = blockIdx.x & ((1 << parts_log2) - 1);
@@ -351,24 +353,12 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
   const int rows = 1 << (shift - parts_log2);
   const uint32_t lo = (uint32_t)part * rows, kmask = (1u << shift) - 1u;
   const uint32_t s0 = base[b] + r0;
-  if (threadIdx.x == 0) max_bits = 0u;
+  const int64_t k0 = ((int64_t)b << shift) + lo;
+  const bool wc_slice = k0 >= (int64_t)map.wc_start && k0 < (int64_t)map.wc_end;
+  const float M = __uint_as_float(vmax[wc_slice ? 1 : 0]);
+  if (M == 0.f) return;  // every value is zero
   for (int i = threadIdx.x; i < 2 * rows; i += ACC_THREADS) acc[i] = 0ull;
   __syncthreads();
-  // pass 1: the largest magnitude among the item's values (non-negative
-  // floats order as their bit patterns; NaN sorts above infinity)
-  float mx = 0.f;
-  for (uint32_t i = threadIdx.x; i < n; i += ACC_THREADS) {
-    const uint32_t r = (skeys[s0 + i] & kmask) - lo;
-    const f2 v = svals[s0 + i];
-    if (r < (uint32_t)rows) mx = fmaxf(mx, fmaxf(fabsf(v[0]), fabsf(v[1])));
-    if (r < (uint32_t)rows && !(fabsf(v[0]) <= FLT_MAX && fabsf(v[1]) <= FLT_MAX)) mx = __uint_as_float(0x7F800000u);
-  }
-#pragma unroll
-  for (int k = WAVE / 2; k > 0; k >>= 1) mx = fmaxf(mx, __shfl_xor(mx, k, WAVE));
-  if ((threadIdx.x & 63) == 0) atomicMax(&max_bits, __float_as_uint(mx));
-  __syncthreads();
-  const float M = __uint_as_float(max_bits);
-  if (M == 0.f) return;  // every value of the item is zero
   const bool fixed = M <= FLT_MAX;
   int e = 0;
   frexp((double)M * (double)n, &e);  // M n < 2^e
@@ -400,8 +390,7 @@ __global__ void __launch_bounds__(ACC_THREADS) bin_accumulate_kernel(const uint3
     }
   }
   __syncthreads();
-  const int64_t k0 = ((int64_t)b << shift) + lo;
-  if (k0 >= (int64_t)map.wc_start && k0 < (int64_t)map.wc_end) {
+  if (wc_slice) {
     // dL/dW^c: element k0 + r takes plane 0 of its own key and plane 1 of
     // the key before (the pair's second corner); pairs never cross slices
     for (int r = threadIdx.x; r < rows; r += ACC_THREADS) {
@@ -459,7 +448,7 @@ hipError_t launch_binned_scatter(const ScatterPlan& p, float* grad_table, float*
   hipLaunchKernelGGL(bin_scatter_kernel, dim3((p.n_tiles_cap + 7) / 8 * 8), dim3(BIN_THREADS), SCATTER_LDS, st, p.cursor, p.cap,
                      p.keys, p.vals, p.shift, p.n_bins, p.hist, p.skeys, p.svals);
   hipLaunchKernelGGL(bin_accumulate_kernel, dim3((unsigned)p.max_items << parts_log2), dim3(ACC_THREADS), lds, st,
-                     p.skeys, p.svals, p.shift, p.total, p.base, p.item_base, p.item_bin, p.n_items, p.map,
+                     p.skeys, p.svals, p.shift, p.total, p.base, p.item_base, p.item_bin, p.n_items, p.vmax, p.map,
                      grad_table, grad_weights);
   return hipGetLastError();
 }
