@@ -306,9 +306,12 @@ def train_bench(steps, warmup):
                           b["w_grad"], b["weights_grad"], grad_bones=gG, adjoint_ws=ws)
     for t in [b["table_grad"], b["weights_grad"]] + b["w_grad"]:
         t.zero_()
-    # the adjoint as the training step runs it (hashed levels through the
-    # binned scatter), and with every table gradient added by global atomics
+    # the adjoint as the training step runs it (table and blend-weight
+    # gradients through the binned scatter), and with every gradient added by
+    # global atomics
     _, bwd_ms = timed_launches(lambda: bwd(tr.adjoint_ws), steps, 1)
+    torch.cuda.synchronize()
+    n_records = int(tr.adjoint_ws[:4].view(torch.int32).item())  # the workspace's first word: records written
     _, bwd_atomic_ms = timed_launches(lambda: bwd(None), steps, 1)
     gG = torch.zeros(24, 3, 4, device=dev)
     _, bwd_pose_ms = timed_launches(lambda: bwd(tr.adjoint_ws, gG), steps, 1)
@@ -324,7 +327,7 @@ def train_bench(steps, warmup):
     atomics = n_eval * (16 * 8 * 2 + 24 * 8)
     res["split_ms"] = {"forward": fwd_ms, "adjoint": bwd_ms, "rest": wall - fwd_ms - bwd_ms}
     res.update(train_variants(sc, pose, cam, pid, tgt, steps))
-    res["hashed_level_records"] = n_eval * 9 * 8
+    res["binned_records"] = n_records
     res["evaluated_samples"] = n_eval
     res["adjoint_atomics_per_s_upper"] = atomics / (bwd_atomic_ms * 1e-3)
     return res

@@ -315,14 +315,21 @@ mnr_status mnr_render_noalloc(const mnr_field* field, const mnr_motion* motion, 
  * adjoint at x_skel, passing per-sample values through the workspace.
  * adjoint_ws (dev, 256-byte aligned, adjoint_ws_bytes >=
  * mnr_adjoint_ws_bytes(field, motion, n_rays, spp); contents are scratch):
- *   - with a grid-encoded field, the table gradient leaves the adjoint as
- *     (row, value) records that are binned by table slice and summed in
- *     LDS, instead of one global float atomic per sample, corner and
- *     feature (the same sum in another order): every hashed level's, and
- *     the dense levels' (one record per corner and run of consecutive
- *     samples in one cell) when the hashed levels' T rows each plus the
- *     dense levels' (N+1)^3 rows fit 4096 x 2^14 keys -- else the dense
- *     levels keep run-summed atomics;
+ *   - the table and blend-weight gradients leave the adjoint as (key,
+ *     value) records that are binned by slice and summed in LDS in 64-bit
+ *     fixed point, instead of global float atomics (the same sum in
+ *     another order): every hashed level's (one record per sample, corner
+ *     and two features), the dense levels' (one per corner and run of
+ *     consecutive samples in one cell) when the hashed levels' T rows each
+ *     plus the dense levels' (N+1)^3 rows fit 4096 x 2^14 keys, and
+ *     dL/dW^c's (one per run and pair of x-adjacent cell corners inside the
+ *     volume) when it fits too and res is a power of two up to 4096; what
+ *     does not fit keeps run-summed atomics.  After the call the
+ *     workspace's first 32-bit word holds the number of records written;
+ *   - with a ray list, the rays are processed in a spatially coherent order
+ *     (a counting sort by the Morton index of their pixel's cell in a
+ *     64 x 64 grid over the image), which keeps neighbouring rays' gathers
+ *     in one L2; the results are the same;
  *   - with a residual network or the frequency-encoded field, the split
  *     adjoint's per-sample values.
  * NULL: atomics for the table; with a residual network or the
@@ -336,16 +343,17 @@ mnr_status mnr_render_backward(const mnr_field* field, const mnr_motion* motion,
                                void* adjoint_ws, uint64_t adjoint_ws_bytes, void* stream);
 
 /* Bytes of the adjoint workspace for a batch of n_rays rays of spp samples:
- * binned-scatter room for a record per sample, keyed level and corner (12
- * bytes each, twice: 192 bytes per sample and keyed level) plus bin
- * histograms and the summing items -- about 3.1 KB per sample for the 16
- * levels of a 2^19-row table, none when the
- * batch (>= 2^31 records) or table (hashed levels of more than 4096 x 2^14
- * rows) is too large for the binned path -- plus, with a residual network or the
- * frequency-encoded field, 84 bytes per sample slot (n_rays * ceil(spp / 64)
- * * 64 slots, rounded up to 256 bytes) and 256 bytes, and for the
- * frequency-encoded field 512 bytes more per sample slot (its saved hidden
- * activations).  0: nothing to use it for. */
+ * binned-scatter room for a record per sample, keyed level and corner and
+ * for 4 per sample and bone (12 bytes each, twice) plus bin histograms and
+ * the summing items -- about 5.4 KB per sample for the 16 levels of a
+ * 2^19-row table and 24 bones, none when the batch (>= 2^31 records) or
+ * table (hashed levels of more than 4096 x 2^14 rows) is too large for the
+ * binned path -- plus, with a residual network or the frequency-encoded
+ * field, 84 bytes per sample slot (n_rays * ceil(spp / 64) * 64 slots,
+ * rounded up to 256 bytes) and 256 bytes, and for the frequency-encoded
+ * field 512 bytes more per sample slot (its saved hidden activations);
+ * then 4 bytes per ray (the processing order).  0: nothing to use it
+ * for. */
 uint64_t mnr_adjoint_ws_bytes(const mnr_field* field, const mnr_motion* motion, int32_t n_rays, int32_t spp);
 
 /* Patch ray batch for training (Sec. 5.2: n_patches patches of size x size

@@ -418,8 +418,9 @@ def adjoint_ws_bytes(field: DeviceField, n_rays: int, spp: int) -> int:
 
 
 def adjoint_workspace(field: DeviceField, n_rays: int, spp: int) -> Optional[torch.Tensor]:
-    """A device buffer for the adjoint (binned table scatter, split adjoint of
-    the residual network), or None when there is nothing to use it for."""
+    """A device buffer for the adjoint (binned scatter of the table and
+    blend-weight gradients, split adjoints, the ray list's processing order),
+    or None when there is nothing to use it for."""
     nb = adjoint_ws_bytes(field, n_rays, spp)
     if nb == 0:
         return None
@@ -433,8 +434,8 @@ def render_backward(field: DeviceField, pose: PoseHost, cam: Camera, H: int, W: 
                     grad_res: Optional[List[torch.Tensor]] = None) -> None:
     """Accumulates the adjoint into the gradient buffers; grad_bones
     (optional, [n_bones, 3, 4]) receives dL/dG of the bone transforms.
-    adjoint_ws (from adjoint_workspace): binned scatter of the hashed levels'
-    table gradient instead of atomics, and the residual network's split
+    adjoint_ws (from adjoint_workspace): binned scatter of the table and
+    blend-weight gradients instead of atomics, and the residual network's split
     adjoint, whose gradients (W1..W5, W_omega) go to grad_res.  The
     frequency-encoded field has no table (grad_table None) and needs
     adjoint_ws."""
@@ -640,8 +641,8 @@ class Trainer:
         """skel_cnn: generate the blend-weight logits with the skeleton-motion
         CNN (logits32 is then ignored) and train its weights instead of free
         logits (lr_motion applies to them).  binned_scatter: give the adjoint
-        a workspace for the binned scatter of the hashed levels' gradient
-        (else it adds them with atomics).  residual: (W1..W5, W_omega, alpha)
+        a workspace for the binned scatter of the table and blend-weight
+        gradients (else it adds them with atomics).  residual: (W1..W5, W_omega, alpha)
         of the residual motion network, trained with Adam at lr_res (the
         window position alpha is the caller's schedule: set_alpha)."""
         dev = table32.device
