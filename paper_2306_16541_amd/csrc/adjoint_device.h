@@ -335,6 +335,55 @@ __device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
 // atomics on this GPU cost far more than the products).  With ld = 4
 // (mod 16) the 64 lanes of one access (rows 4g + j, columns c) fall in
 // distinct banks.
+// dw_tile's accumulating form for one 16-row tile of d: the products with
+// NT tiles of h are added to MFMA accumulators acc[kt] (16 x 16 blocks of
+// the wave's rows, D layout: lane c + 16 g holds rows 4 g + j of column
+// 16 kt + c), which stay in registers until the kernel's end (store_dw).
+template <int NT>
+__device__ __forceinline__ void dw_acc(__bf16* tb, const f4& d, const f4* h, f4 (&acc)[NT], int lane) {
+  __bf16* td = tb;            // [16 rows][16 samples]
+  __bf16* th = tb + 64 * 16;  // [16 NT columns][16 samples]
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) td[(4 * g + j) * 16 + c] = (__bf16)d[j];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
+  wave_sync_lds();
+  bf16x8 av;
+  if (g < 2) {
+    av = *(const bf16x8*)(td + c * 16 + 8 * g);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) av[e] = (__bf16)0.0f;
+  }
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    bf16x8 bv;
+    if (g < 2) {
+      bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bv[e] = (__bf16)0.0f;
+    }
+    acc[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[kt], 0, 0, 0);
+  }
+  wave_sync_lds();
+}
+
+// The wave's accumulated rows (the first `rows` of its 16) into the block's
+// LDS sums (row stride ld); each wave owns its rows, so plain stores.
+template <int NT>
+__device__ __forceinline__ void store_dw(const f4 (&acc)[NT], float* dw, int rows, int ld, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * g + j < rows) dw[(4 * g + j) * ld + 16 * kt + c] = acc[kt][j];
+}
+
 template <int MT, int NT>
 __device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int ld,
                                         int lane) {

@@ -205,6 +205,13 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
   float* dw2 = dw + FreqGrad::o2 + 16 * wave * FreqGrad::L2;
   float* dw3 = dw + FreqGrad::o3 + 16 * wave * FreqGrad::L3;
   float* dw4 = dw + FreqGrad::o4 + 16 * wave * FreqGrad::L4;
+  // the wave's rows of every weight gradient, summed on the MFMAs over all
+  // of the block's tiles (W4: [h3; gamma] columns; W5: wave 0)
+  f4 g1[4], g2[4], g3[4], g4[8], g5[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g1[t] = g2[t] = g3[t] = g5[t] = z4;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) g4[t] = z4;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
@@ -254,14 +261,14 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
           if (g == 0) d5[0] = f4{q0, q1, q2, q3};
         }
         f4 tmp[8], d[4], dgam[4], dw_rows[1];
-        if (wave == 0) dw_tile<1, 4>(tb, d5, h4, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
+        if (wave == 0) dw_acc<4>(tb, d5[0], h4, g5, lane);
         mm_t<4, 1>(rt + FreqTShape::o5, d5, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
         // layer 4: input [h3; gamma]
         dw_rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, dw_rows, h3, dw4, 16, FreqGrad::L4, lane);
-        dw_tile<1, 4>(tb, dw_rows, gam, dw4 + HIDDEN, 16, FreqGrad::L4, lane);
+        dw_acc<4>(tb, dw_rows[0], h3, *(f4(*)[4])g4, lane);
+        dw_acc<4>(tb, dw_rows[0], gam, *(f4(*)[4])(g4 + 4), lane);
         mm_t<8, 2>(rt + FreqTShape::o4, d, tmp, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) dgam[t] = tmp[4 + t];
@@ -269,19 +276,19 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
         // layer 3
         dw_rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, dw_rows, h2, dw3, 16, FreqGrad::L3, lane);
+        dw_acc<4>(tb, dw_rows[0], h2, g3, lane);
         mm_t<4, 2>(rt + FreqTShape::o3, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
         // layer 2
         dw_rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, dw_rows, h1, dw2, 16, FreqGrad::L2, lane);
+        dw_acc<4>(tb, dw_rows[0], h1, g2, lane);
         mm_t<4, 2>(rt + FreqTShape::o2, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
         // layer 1: input gamma
         dw_rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, dw_rows, gam, dw1, 16, FreqGrad::L1, lane);
+        dw_acc<4>(tb, dw_rows[0], gam, g1, lane);
         if (wave != 0) continue;
         mm_t<4, 2>(rt, d, tmp, lane);
 #pragma unroll
@@ -306,6 +313,11 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
       }
     }
   }
+  store_dw(g1, dw1, 16, FreqGrad::L1, lane);
+  store_dw(g2, dw2, 16, FreqGrad::L2, lane);
+  store_dw(g3, dw3, 16, FreqGrad::L3, lane);
+  store_dw(g4, dw4, 16, FreqGrad::L4, lane);
+  if (wave == 0) store_dw(g5, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
   __syncthreads();
   // flush: element k of layer l (row-major, K columns) sits at row k / K of
   // the padded block

@@ -178,6 +178,14 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
   float* dw2 = dw + ResGrad::o2 + 16 * wave * ResGrad::L2;
   float* dw3 = dw + ResGrad::o3 + 16 * wave * ResGrad::L3;
   float* dw4 = dw + ResGrad::o4 + 16 * wave * ResGrad::L4;
+  // the wave's rows of every weight gradient, summed on the MFMAs over all
+  // of the block's tiles (W4: [h3; gamma] columns; W5: wave 0)
+  f4 g1[2], g2[4], g3[4], g4[6], g5[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g2[t] = g3[t] = g5[t] = z4;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) g4[t] = z4;
+  g1[0] = g1[1] = z4;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
@@ -235,15 +243,15 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         // output gradient: rows 0..2 of sample sl are dL/dx_res = dL/dx_final
         const float q0 = __shfl(gf[0], sl, WAVE), q1 = __shfl(gf[1], sl, WAVE), q2 = __shfl(gf[2], sl, WAVE);
         f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : z4, z4};
-        if (wave == 0) dw_tile<1, 4>(tb, d5, h4, dw + ResGrad::o5, 3, ResGrad::L5, lane);
+        if (wave == 0) dw_acc<4>(tb, d5[0], h4, g5, lane);
         f4 d[4], rows[1], dg2[2];
         mm_t<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
         // layer 4: input [h3; gamma]
         rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, rows, h3, dw4, 16, ResGrad::L4, lane);
-        dw_tile<1, 2>(tb, rows, x, dw4 + 64, 16, ResGrad::L4, lane);
+        dw_acc<4>(tb, rows[0], h3, *(f4(*)[4])g4, lane);
+        dw_acc<2>(tb, rows[0], x, *(f4(*)[2])(g4 + 4), lane);
         mm_t<6, 2>(rt + ResTShape::o4, d, tmp, lane);
         dg2[0] = tmp[4];
         dg2[1] = tmp[5];
@@ -251,13 +259,13 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
         // layer 3
         rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, rows, h2, dw3, 16, ResGrad::L3, lane);
+        dw_acc<4>(tb, rows[0], h2, g3, lane);
         mm_t<4, 2>(rt + ResTShape::o3, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
         // layer 2
         rows[0] = pick4(d, wave);
-        dw_tile<1, 4>(tb, rows, h1, dw2, 16, ResGrad::L2, lane);
+        dw_acc<4>(tb, rows[0], h1, g2, lane);
         mm_t<4, 2>(rt + ResTShape::o2, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
@@ -268,7 +276,7 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         f4 xb[2] = {x[0], x[1]};
         if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
         rows[0] = pick4(d, wave);
-        dw_tile<1, 2>(tb, rows, xb, dw1, 16, ResGrad::L1, lane);
+        dw_acc<2>(tb, rows[0], xb, g1, lane);
         if (wave != 0) continue;
         mm_t<2, 2>(rt, d, tmp, lane);
         dg2[0] += tmp[0];
@@ -294,6 +302,11 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
       }
     }
   }
+  store_dw(g1, dw1, 16, ResGrad::L1, lane);
+  store_dw(g2, dw2, 16, ResGrad::L2, lane);
+  store_dw(g3, dw3, 16, ResGrad::L3, lane);
+  store_dw(g4, dw4, 16, ResGrad::L4, lane);
+  if (wave == 0) store_dw(g5, dw + ResGrad::o5, 3, ResGrad::L5, lane);
   __syncthreads();
   // flush the block's sums (element k of layer l sits at row k / K of the
   // padded block); column 27 of dW1 is the bias gradient
