@@ -319,76 +319,24 @@ __device__ void stage_t(char* lds, const WT* __restrict__ w, int M, int K, int K
   }
 }
 
-// Tile w (0..3) of d, without indexing a register array by a runtime value.
-__device__ __forceinline__ f4 pick4(const f4 (&d)[4], int w) {
-  return w == 0 ? d[0] : (w == 1 ? d[1] : (w == 2 ? d[2] : d[3]));
-}
-
 __device__ __forceinline__ f4 relu_mask4(f4 d, f4 h) {
   return f4{h[0] > 0.f ? d[0] : 0.f, h[1] > 0.f ? d[1] : 0.f, h[2] > 0.f ? d[2] : 0.f, h[3] > 0.f ? d[3] : 0.f};
 }
 
-// dW[M_out x K] (row stride ld) += d (MT tiles) x h^T (NT tiles) over the
-// 16 samples of one tile, through the wave's transpose buffer tb
-// (2 x 64 x 16 bf16).  The sums are added with plain LDS read-add-write:
-// the caller guarantees that no other wave adds to the same rows (LDS float
-// atomics on this GPU cost far more than the products).  With ld = 4
-// (mod 16) the 64 lanes of one access (rows 4g + j, columns c) fall in
-// distinct banks.
-// dw_tile's accumulating form for one 16-row tile of d: the products with
-// NT tiles of h are added to MFMA accumulators acc[kt] (16 x 16 blocks of
-// the wave's rows, D layout: lane c + 16 g holds rows 4 g + j of column
-// 16 kt + c), which stay in registers until the kernel's end (store_dw).
-template <int NT>
-__device__ __forceinline__ void dw_acc(__bf16* tb, const f4& d, const f4* h, f4 (&acc)[NT], int lane) {
-  __bf16* td = tb;            // [16 rows][16 samples]
+// Weight-gradient products of one 16-sample tile, dW += d h^T: MT 16-row
+// tiles of d (the wave's rows) times NT tiles of h, both transposed through
+// the wave's buffer tb (2 x 64 x 16 bf16) into MFMA operands (K = the
+// tile's samples), added to MFMA accumulators acc[mt][KT0 + kt] (16 x 16
+// blocks, D layout: lane c + 16 g holds rows 16 mt + 4 g + j of column
+// 16 (KT0 + kt) + c).  The accumulators stay in registers over all of a
+// block's tiles and reach LDS once, at the kernel's end (add_dw): LDS float
+// atomics on this GPU cost far more than the products, and even plain
+// read-add-write per tile costs more than keeping the sums in registers.
+template <int MT, int NT, int KT0 = 0, int NTA>
+__device__ __forceinline__ void dw_acc(__bf16* tb, const f4* d, const f4* h, f4 (&acc)[MT][NTA], int lane) {
+  static_assert(MT <= 4 && NT <= 4 && KT0 + NT <= NTA, "tile counts");
+  __bf16* td = tb;            // [16 MT rows][16 samples]
   __bf16* th = tb + 64 * 16;  // [16 NT columns][16 samples]
-  const int c = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) td[(4 * g + j) * 16 + c] = (__bf16)d[j];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
-  wave_sync_lds();
-  bf16x8 av;
-  if (g < 2) {
-    av = *(const bf16x8*)(td + c * 16 + 8 * g);
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) av[e] = (__bf16)0.0f;
-  }
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-    bf16x8 bv;
-    if (g < 2) {
-      bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) bv[e] = (__bf16)0.0f;
-    }
-    acc[kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[kt], 0, 0, 0);
-  }
-  wave_sync_lds();
-}
-
-// The wave's accumulated rows (the first `rows` of its 16) into the block's
-// LDS sums (row stride ld); each wave owns its rows, so plain stores.
-template <int NT>
-__device__ __forceinline__ void store_dw(const f4 (&acc)[NT], float* dw, int rows, int ld, int lane) {
-  const int c = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int kt = 0; kt < NT; ++kt)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (4 * g + j < rows) dw[(4 * g + j) * ld + 16 * kt + c] = acc[kt][j];
-}
-
-template <int MT, int NT>
-__device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, float* dw, int M_out, int ld,
-                                        int lane) {
-  __bf16* td = tb;            // [64 rows][16 samples]
-  __bf16* th = tb + 64 * 16;  // [64 columns][16 samples]
   const int c = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < MT; ++t)
@@ -399,27 +347,47 @@ __device__ __forceinline__ void dw_tile(__bf16* tb, const f4* d, const f4* h, fl
 #pragma unroll
     for (int j = 0; j < 4; ++j) th[(16 * t + 4 * g + j) * 16 + c] = (__bf16)h[t][j];
   wave_sync_lds();
+  bf16x8 bv[NT];
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    if (g < 2) {
+      bv[kt] = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bv[kt][e] = (__bf16)0.0f;
+    }
+  }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
+    bf16x8 av;
+    if (g < 2) {
+      av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
+    } else {
 #pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-      bf16x8 av, bv;
-      if (g < 2) {
-        av = *(const bf16x8*)(td + (16 * mt + c) * 16 + 8 * g);
-        bv = *(const bf16x8*)(th + (16 * kt + c) * 16 + 8 * g);
-      } else {
+      for (int e = 0; e < 8; ++e) av[e] = (__bf16)0.0f;
+    }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = bv[e] = (__bf16)0.0f;
-      }
-      const f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    for (int kt = 0; kt < NT; ++kt)
+      acc[mt][KT0 + kt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[kt], acc[mt][KT0 + kt], 0, 0, 0);
+  }
+  wave_sync_lds();
+}
+
+// The wave's accumulated rows (the first `rows` of its 16 MT) added into the
+// block's LDS sums (row stride ld); the caller keeps two waves from adding
+// to the same rows at once.
+template <int MT, int NT>
+__device__ __forceinline__ void add_dw(const f4 (&acc)[MT][NT], float* dw, int rows, int ld, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = 16 * mt + 4 * g + j;
-        if (row < M_out) dw[row * ld + 16 * kt + c] += acc[j];
+        if (row < rows) dw[row * ld + 16 * kt + c] += acc[mt][kt][j];
       }
-    }
-  }
-  wave_sync_lds();
 }
 
 // out[mt] = W^T-fragments (MT m-tiles, KS 32-wide k steps) x x (2 KS tiles).

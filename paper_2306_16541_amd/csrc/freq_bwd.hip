@@ -176,12 +176,14 @@ __device__ __forceinline__ void load_act(const bf16x8* act, int layer, int nt, i
   h[3] = f4{(float)q[4], (float)q[5], (float)q[6], (float)q[7]};
 }
 
-// The four waves of a block work on the same rays, chunks and tiles: each
-// runs the whole backward chain of the tile (the dX products, cheap on the
-// MFMAs) but adds only its own 16 rows of every weight gradient (wave w:
-// rows 16 w .. 16 w + 15; W5's four rows: wave 0), so no two waves add to
-// one LDS entry and the sums need no atomics.  Wave 0 writes dL/dx_final.
-// Lane c + 16 g works on sample 16 nt + c.
+// The four waves of a block work on the same rays and chunks in two pairs:
+// pair p takes the chunk's 16-sample tiles p and p + 2, both of its waves
+// run the tile's whole backward chain (the dX products, cheap on the
+// MFMAs), and wave h of the pair sums only rows 32 h .. 32 h + 31 of every
+// weight gradient (W5's four rows: h = 0) in MFMA accumulators that stay in
+// registers over all of the block's tiles; at the end the two pairs add
+// their sums to LDS one after the other.  Wave h = 0 of a pair writes
+// dL/dx_final.  Lane c + 16 g works on sample 16 nt + c.
 __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const RenderArgs a, int n_slots) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -200,18 +202,18 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
   const int64_t ss = a.split.stride;
   const int c = lane & 15, g = lane >> 4;
   const f4 z4 = {0.f, 0.f, 0.f, 0.f};
-  // this wave's rows of each gradient block
-  float* dw1 = dw + 16 * wave * FreqGrad::L1;
-  float* dw2 = dw + FreqGrad::o2 + 16 * wave * FreqGrad::L2;
-  float* dw3 = dw + FreqGrad::o3 + 16 * wave * FreqGrad::L3;
-  float* dw4 = dw + FreqGrad::o4 + 16 * wave * FreqGrad::L4;
-  // the wave's rows of every weight gradient, summed on the MFMAs over all
-  // of the block's tiles (W4: [h3; gamma] columns; W5: wave 0)
-  f4 g1[4], g2[4], g3[4], g4[8], g5[4];
+  const int pair = wave >> 1, half = wave & 1;
+  // the wave's rows of every weight gradient (W4: [h3; gamma] columns)
+  f4 g1[2][4], g2[2][4], g3[2][4], g4[2][8], g5[1][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) g1[t] = g2[t] = g3[t] = g5[t] = z4;
+  for (int m = 0; m < 2; ++m) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) g4[t] = z4;
+    for (int t = 0; t < 4; ++t) g1[m][t] = g2[m][t] = g3[m][t] = z4;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) g4[m][t] = z4;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g5[0][t] = z4;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
       }
       const bf16x8* act = (const bf16x8*)a.split.act + cj * FREQ_ACT_VECS;
 #pragma unroll 1
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = pair; nt < 4; nt += 2) {
         if (!((live_mask >> (16 * nt)) & 0xFFFFull)) continue;
         const int sl = 16 * nt + c;  // the lane's sample
         const bool slive = (live_mask >> sl) & 1ull;
@@ -260,36 +262,40 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
           const float q2 = __shfl(go[2], sl, WAVE), q3 = __shfl(go[3], sl, WAVE);
           if (g == 0) d5[0] = f4{q0, q1, q2, q3};
         }
-        f4 tmp[8], d[4], dgam[4], dw_rows[1];
-        if (wave == 0) dw_acc<4>(tb, d5[0], h4, g5, lane);
+        f4 tmp[8], d[4], dgam[4], dr[2];
+        if (half == 0) dw_acc<1, 4>(tb, d5, h4, g5, lane);
         mm_t<4, 1>(rt + FreqTShape::o5, d5, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
         // layer 4: input [h3; gamma]
-        dw_rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, dw_rows[0], h3, *(f4(*)[4])g4, lane);
-        dw_acc<4>(tb, dw_rows[0], gam, *(f4(*)[4])(g4 + 4), lane);
+        dr[0] = half ? d[2] : d[0];
+        dr[1] = half ? d[3] : d[1];
+        dw_acc<2, 4, 0>(tb, dr, h3, g4, lane);
+        dw_acc<2, 4, 4>(tb, dr, gam, g4, lane);
         mm_t<8, 2>(rt + FreqTShape::o4, d, tmp, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) dgam[t] = tmp[4 + t];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
         // layer 3
-        dw_rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, dw_rows[0], h2, g3, lane);
+        dr[0] = half ? d[2] : d[0];
+        dr[1] = half ? d[3] : d[1];
+        dw_acc<2, 4>(tb, dr, h2, g3, lane);
         mm_t<4, 2>(rt + FreqTShape::o3, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
         // layer 2
-        dw_rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, dw_rows[0], h1, g2, lane);
+        dr[0] = half ? d[2] : d[0];
+        dr[1] = half ? d[3] : d[1];
+        dw_acc<2, 4>(tb, dr, h1, g2, lane);
         mm_t<4, 2>(rt + FreqTShape::o2, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
         // layer 1: input gamma
-        dw_rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, dw_rows[0], gam, g1, lane);
-        if (wave != 0) continue;
+        dr[0] = half ? d[2] : d[0];
+        dr[1] = half ? d[3] : d[1];
+        dw_acc<2, 4>(tb, dr, gam, g1, lane);
+        if (half != 0) continue;
         mm_t<4, 2>(rt, d, tmp, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) dgam[t] += tmp[t];
@@ -313,12 +319,17 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
       }
     }
   }
-  store_dw(g1, dw1, 16, FreqGrad::L1, lane);
-  store_dw(g2, dw2, 16, FreqGrad::L2, lane);
-  store_dw(g3, dw3, 16, FreqGrad::L3, lane);
-  store_dw(g4, dw4, 16, FreqGrad::L4, lane);
-  if (wave == 0) store_dw(g5, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
-  __syncthreads();
+  // the pairs add their rows to the block's LDS sums one after the other
+  for (int pp = 0; pp < 2; ++pp) {
+    if (pair == pp) {
+      add_dw(g1, dw + 32 * half * FreqGrad::L1, 32, FreqGrad::L1, lane);
+      add_dw(g2, dw + FreqGrad::o2 + 32 * half * FreqGrad::L2, 32, FreqGrad::L2, lane);
+      add_dw(g3, dw + FreqGrad::o3 + 32 * half * FreqGrad::L3, 32, FreqGrad::L3, lane);
+      add_dw(g4, dw + FreqGrad::o4 + 32 * half * FreqGrad::L4, 32, FreqGrad::L4, lane);
+      if (half == 0) add_dw(g5, dw + FreqGrad::o5, 4, FreqGrad::L5, lane);
+    }
+    __syncthreads();
+  }
   // flush: element k of layer l (row-major, K columns) sits at row k / K of
   // the padded block
   const int cols[5] = {64, 64, 64, 128, 64}, rows[5] = {64, 64, 64, 64, 4};

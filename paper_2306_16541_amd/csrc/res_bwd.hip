@@ -143,14 +143,17 @@ __device__ __forceinline__ void res_posenc_lane(const float x[3], const float (&
 }
 
 // Four waves per block share the weights, their transposes and the
-// gradient sums, and work on the same rays, chunks and tiles: each recomputes
-// the tile's forward pass and runs the whole backward chain (the products
-// are cheap on the MFMAs) but adds only its own 16 rows of every weight
-// gradient (wave w: rows 16 w .. 16 w + 15; W5's three rows: wave 0), so no
-// two waves add to one LDS entry and the sums need no atomics.  gamma and
-// its derivative are formed in registers, in the D layout; wave 0 writes
-// dL/dx_skel = dL/dx_final + (d gamma / d x_skel)^T dL/dgamma, to a field
-// of its own (the other waves may still be reading dL/dx_final).
+// gradient sums, and work on the same rays and chunks in two pairs: pair p
+// takes the chunk's 16-sample tiles p and p + 2, both of its waves
+// recompute the tile's forward pass and run the whole backward chain (the
+// products are cheap on the MFMAs), and wave h of the pair sums only rows
+// 32 h .. 32 h + 31 of every weight gradient (W5's three rows: h = 0) in
+// MFMA accumulators that stay in registers over all of the block's tiles;
+// at the end the two pairs add their sums to LDS one after the other.
+// gamma and its derivative are formed in registers, in the D layout; wave
+// h = 0 of a pair writes dL/dx_skel = dL/dx_final + (d gamma / d x_skel)^T
+// dL/dgamma, to a field of its own (the other waves may still be reading
+// dL/dx_final).
 __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const RenderArgs a, int n_slots) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -173,19 +176,19 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
   const int64_t ss = a.split.stride;
   const int c = lane & 15, g = lane >> 4;
   const f4 z4 = {0.f, 0.f, 0.f, 0.f};
-  // this wave's rows of each gradient block
-  float* dw1 = dw + 16 * wave * ResGrad::L1;
-  float* dw2 = dw + ResGrad::o2 + 16 * wave * ResGrad::L2;
-  float* dw3 = dw + ResGrad::o3 + 16 * wave * ResGrad::L3;
-  float* dw4 = dw + ResGrad::o4 + 16 * wave * ResGrad::L4;
-  // the wave's rows of every weight gradient, summed on the MFMAs over all
-  // of the block's tiles (W4: [h3; gamma] columns; W5: wave 0)
-  f4 g1[2], g2[4], g3[4], g4[6], g5[4];
+  const int pair = wave >> 1, half = wave & 1;
+  // the wave's rows of every weight gradient (W4: [h3; gamma] columns)
+  f4 g1[2][2], g2[2][4], g3[2][4], g4[2][6], g5[1][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) g2[t] = g3[t] = g5[t] = z4;
+  for (int m = 0; m < 2; ++m) {
+    g1[m][0] = g1[m][1] = z4;
 #pragma unroll
-  for (int t = 0; t < 6; ++t) g4[t] = z4;
-  g1[0] = g1[1] = z4;
+    for (int t = 0; t < 4; ++t) g2[m][t] = g3[m][t] = z4;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) g4[m][t] = z4;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) g5[0][t] = z4;
   for (int slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     int orow, n_done;
     RaySetup rs;
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         }
       }
 #pragma unroll 1
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = pair; nt < 4; nt += 2) {
         if (!((live_mask >> (16 * nt)) & 0xFFFFull)) continue;
         const int sl = 16 * nt + c;  // the lane's sample
         const bool slive = (live_mask >> sl) & 1ull;
@@ -243,29 +246,32 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         // output gradient: rows 0..2 of sample sl are dL/dx_res = dL/dx_final
         const float q0 = __shfl(gf[0], sl, WAVE), q1 = __shfl(gf[1], sl, WAVE), q2 = __shfl(gf[2], sl, WAVE);
         f4 d5[2] = {g == 0 ? f4{q0, q1, q2, 0.f} : z4, z4};
-        if (wave == 0) dw_acc<4>(tb, d5[0], h4, g5, lane);
-        f4 d[4], rows[1], dg2[2];
+        if (half == 0) dw_acc<1, 4>(tb, d5, h4, g5, lane);
+        f4 d[4], rows[2], dg2[2];
         mm_t<4, 1>(rt + ResTShape::o5, d5, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h4[mt]);
         // layer 4: input [h3; gamma]
-        rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, rows[0], h3, *(f4(*)[4])g4, lane);
-        dw_acc<2>(tb, rows[0], x, *(f4(*)[2])(g4 + 4), lane);
+        rows[0] = half ? d[2] : d[0];
+        rows[1] = half ? d[3] : d[1];
+        dw_acc<2, 4, 0>(tb, rows, h3, g4, lane);
+        dw_acc<2, 2, 4>(tb, rows, x, g4, lane);
         mm_t<6, 2>(rt + ResTShape::o4, d, tmp, lane);
         dg2[0] = tmp[4];
         dg2[1] = tmp[5];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h3[mt]);
         // layer 3
-        rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, rows[0], h2, g3, lane);
+        rows[0] = half ? d[2] : d[0];
+        rows[1] = half ? d[3] : d[1];
+        dw_acc<2, 4>(tb, rows, h2, g3, lane);
         mm_t<4, 2>(rt + ResTShape::o3, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h2[mt]);
         // layer 2
-        rows[0] = pick4(d, wave);
-        dw_acc<4>(tb, rows[0], h1, g2, lane);
+        rows[0] = half ? d[2] : d[0];
+        rows[1] = half ? d[3] : d[1];
+        dw_acc<2, 4>(tb, rows, h1, g2, lane);
         mm_t<4, 2>(rt + ResTShape::o2, d, tmp, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) d[mt] = relu_mask4(tmp[mt], h1[mt]);
@@ -275,9 +281,10 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
         // collects exactly that sum
         f4 xb[2] = {x[0], x[1]};
         if (g == 2) xb[1][3] = 1.f;  // input 16 + 4 g + 3 = 27
-        rows[0] = pick4(d, wave);
-        dw_acc<2>(tb, rows[0], xb, g1, lane);
-        if (wave != 0) continue;
+        rows[0] = half ? d[2] : d[0];
+        rows[1] = half ? d[3] : d[1];
+        dw_acc<2, 2>(tb, rows, xb, g1, lane);
+        if (half != 0) continue;
         mm_t<2, 2>(rt, d, tmp, lane);
         dg2[0] += tmp[0];
         dg2[1] += tmp[1];
@@ -302,12 +309,17 @@ __global__ void __launch_bounds__(64 * RES_BWD_WAVES) res_bwd_kernel(const Rende
       }
     }
   }
-  store_dw(g1, dw1, 16, ResGrad::L1, lane);
-  store_dw(g2, dw2, 16, ResGrad::L2, lane);
-  store_dw(g3, dw3, 16, ResGrad::L3, lane);
-  store_dw(g4, dw4, 16, ResGrad::L4, lane);
-  if (wave == 0) store_dw(g5, dw + ResGrad::o5, 3, ResGrad::L5, lane);
-  __syncthreads();
+  // the pairs add their rows to the block's LDS sums one after the other
+  for (int pp = 0; pp < 2; ++pp) {
+    if (pair == pp) {
+      add_dw(g1, dw + 32 * half * ResGrad::L1, 32, ResGrad::L1, lane);
+      add_dw(g2, dw + ResGrad::o2 + 32 * half * ResGrad::L2, 32, ResGrad::L2, lane);
+      add_dw(g3, dw + ResGrad::o3 + 32 * half * ResGrad::L3, 32, ResGrad::L3, lane);
+      add_dw(g4, dw + ResGrad::o4 + 32 * half * ResGrad::L4, 32, ResGrad::L4, lane);
+      if (half == 0) add_dw(g5, dw + ResGrad::o5, 3, ResGrad::L5, lane);
+    }
+    __syncthreads();
+  }
   // flush the block's sums (element k of layer l sits at row k / K of the
   // padded block); column 27 of dW1 is the bias gradient
   const int cols[5] = {32, 64, 64, 96, 64}, rows[5] = {64, 64, 64, 64, 3};
