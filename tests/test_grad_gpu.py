@@ -271,6 +271,43 @@ def test_binned_scatter_equals_atomic_scatter():
         assert float(np.abs(x - y).max()) <= 1e-5 * float(np.abs(x).max())
 
 
+def test_binned_scatter_non_finite_gradient():
+    # A non-finite loss gradient on one ray: the adjoint's bound on the
+    # record values is then NaN, and the binned scatter sums in floats
+    # instead of fixed point.  The rows that ray reaches are NaN in both
+    # paths and every other entry agrees.
+    sc = scenes.scene_body(H=64, W=64, spp=128, res=32, log2_T=16, seed=16541 + 4)
+    import paper_2306_16541_amd as m
+    g = np.random.default_rng(10)
+    pid = torch.as_tensor(g.integers(0, sc.H * sc.W, 256).astype(np.int32), device="cuda")
+    fld, _ = m.upload_scene(sc, "cuda", m.F32, 0)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    opts = m.make_opts(ert_tau=0.0, stratified=True, seed=SEED)
+    tch = torch.zeros(256, m.saved_size(sc.spp), device="cuda")
+    rgba = m.render(fld, pose, cam, sc.H, sc.W, sc.spp, opts, pid, t_chunks=tch)
+    hit = torch.nonzero(rgba[:, 3] > 0.5)[:, 0]
+    assert hit.numel() > 0
+    grad_rgba = torch.full((256, 4), 1e-2, device="cuda")
+    grad_rgba[int(hit[0]), 0] = float("nan")
+    out = []
+    for binned in (False, True):
+        g_table = torch.zeros(sc.table.shape, device="cuda")
+        g_w = [torch.zeros(w.shape, device="cuda") for w in sc.mlp]
+        g_wc = torch.zeros(sc.logits.shape, device="cuda")
+        ws = m.adjoint_workspace(fld, 256, sc.spp) if binned else None
+        m.render_backward(fld, pose, cam, sc.H, sc.W, sc.spp, opts, pid, tch, grad_rgba, g_table, g_w, g_wc,
+                          adjoint_ws=ws)
+        torch.cuda.synchronize()
+        out.append((g_table.cpu().numpy(), g_wc.cpu().numpy()))
+    for (a, b), name in zip(zip(out[0], out[1]), ("table", "dL/dW^c")):
+        na, nb = np.isnan(a), np.isnan(b)
+        print(f"  {name}: {int(na.sum())} NaN entries (atomic), {int(nb.sum())} (binned)", flush=True)
+        assert na.sum() > 0 and np.array_equal(na, nb), name
+        fa, fb = a[~na], b[~nb]
+        assert float(np.abs(fa - fb).max()) <= 1e-5 * float(np.abs(fa).max()), name
+
+
 def test_binned_scatter_splits_crowded_bins():
     # The full-size field's coarse dense levels put hundreds of thousands of
     # records into one 4096-row bin (level 0 has 17^3 rows), which the
