@@ -751,7 +751,7 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   const int64_t res_n[6] = {64 * 32, 64 * 64, 64 * 64, 64 * 96, 3 * 64, 64 * n_omega};  // W1..W5, W_omega
   if (motion->res_w[0])
     for (int k = 0; k < 6; ++k) clear(st->res_grad[k], res_n[k] * 4);
-  if (st->train_motion) clear(st->logits_grad, n_wc * 4);
+  if (st->train_motion == 2) clear(st->logits_grad, n_wc * 4);  // (the softmax adjoint accumulates into it)
   if (st->workspace) clear(st->workspace, MNR_WORKSPACE_BYTES);
   ok(launch_zero_list(zl, s));
   RenderArgs a;
@@ -802,12 +802,12 @@ mnr_status mnr_train_step(const mnr_field* field, const mnr_motion* motion, cons
   }
   ml.count = field->n_layers;
   ok(launch_adam_list(ml, st->lr_field, st->beta1, st->beta2, st->eps, st->step, field->mlp_dtype, s));
-  if (st->train_motion)  // (logits_grad was cleared with the gradients)
+  if (st->train_motion == 2)  // dL/dlogits for the skeleton CNN's adjoint (logits_grad was cleared above)
     ok(launch_softmax_bwd(motion->weights, st->weights_grad, st->logits_grad, motion->n_bones + 1, n_vox, s));
-  if (st->train_motion == 1) {
-    ok(launch_adam(st->logits, st->logits_grad, st->logits_m, st->logits_v, n_wc, st->lr_motion, st->beta1,
-                   st->beta2, st->eps, st->step, nullptr, MNR_F32, s));
-    ok(launch_softmax_fwd(st->logits, (float*)motion->weights, motion->n_bones + 1, n_vox, s));
+  if (st->train_motion == 1) {  // softmax adjoint, Adam and softmax in one pass, then the packed copy
+    ok(launch_motion_step(st->logits, (float*)motion->weights, st->weights_grad, st->logits_grad, st->logits_m,
+                          st->logits_v, motion->n_bones + 1, n_vox, st->lr_motion, st->beta1, st->beta2, st->eps,
+                          st->step, s));
     if (motion->packed)
       ok(launch_pack_motion(motion->weights, (f4*)motion->packed, motion->n_bones, motion->res, s));
   }

@@ -102,6 +102,9 @@ hipError_t launch_softmax_bwd(const float* w, const float* g, float* gl, int C, 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int step, void* lowp, mnr_dtype dt, hipStream_t st);
 hipError_t launch_convert(const float* src, void* dst, mnr_dtype dt, int64_t n, hipStream_t st);
+// Softmax adjoint, Adam on the logits and softmax of the new logits, in one pass.
+hipError_t launch_motion_step(float* logits, float* w, const float* g, float* gl, float* m, float* v, int C,
+                              int64_t V, float lr, float b1, float b2, float eps, int step, hipStream_t st);
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t st);
 // Spatially coherent processing order of a ray list (order[slot] = row).
 hipError_t launch_ray_order(const int32_t* pixel_ids, int n, int H, int W, int32_t* order, hipStream_t st);

@@ -72,6 +72,46 @@ hipError_t launch_softmax_bwd(const float* w, const float* g, float* gl, int C, 
   return hipGetLastError();
 }
 
+// The blend-weight logits' whole update in one pass per voxel (free logits,
+// Sec. 4.2 as trained here): the softmax adjoint dL/dlogit_c =
+// w_c (g_c - sum_k w_k g_k), written to gl; Adam on the logits (the same
+// arithmetic as adam_kernel); the softmax of the new logits into w: the
+// work of the three separate kernels in one pass over the volume.
+__global__ void motion_step_kernel(float* __restrict__ logits, float* __restrict__ w, const float* __restrict__ g,
+                                   float* __restrict__ gl, float* __restrict__ m, float* __restrict__ v, int C,
+                                   int64_t V, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < V; x += (int64_t)gridDim.x * blockDim.x) {
+    float dot = 0.f;
+    for (int c = 0; c < C; ++c) dot += w[c * V + x] * g[c * V + x];
+    float mx = -INFINITY;
+    for (int c = 0; c < C; ++c) {
+      const int64_t i = c * V + x;
+      const float gi = 0.f + w[i] * (g[i] - dot);
+      gl[i] = gi;
+      const float mi = b1 * m[i] + (1.f - b1) * gi;
+      const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+      m[i] = mi;
+      v[i] = vi;
+      const float pi = logits[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+      logits[i] = pi;
+      mx = fmaxf(mx, pi);
+    }
+    float s = 0.f;
+    for (int c = 0; c < C; ++c) s += expf(logits[c * V + x] - mx);
+    const float inv = 1.0f / s;
+    for (int c = 0; c < C; ++c) w[c * V + x] = expf(logits[c * V + x] - mx) * inv;
+  }
+}
+
+hipError_t launch_motion_step(float* logits, float* w, const float* g, float* gl, float* m, float* v, int C,
+                              int64_t V, float lr, float b1, float b2, float eps, int step, hipStream_t st) {
+  const float bc1 = 1.f - (float)std::pow((double)b1, (double)step);
+  const float bc2 = 1.f - (float)std::pow((double)b2, (double)step);
+  hipLaunchKernelGGL(motion_step_kernel, dim3(grid_for(V, 256)), dim3(256), 0, st, logits, w, g, gl, m, v, C, V, lr,
+                     b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
 template <typename LowT>
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
