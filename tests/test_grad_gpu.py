@@ -243,11 +243,14 @@ def test_adjoint_on_the_full_size_field():
             _elementwise(name, a, b, TAU[mlp_dtype])
 
 
-def test_binned_scatter_equals_atomic_scatter():
+@pytest.mark.parametrize("res", [32, 24])
+def test_binned_scatter_equals_atomic_scatter(res):
     # The same adjoint with the table and blend-weight gradients summed
     # through the binned scatter and through global atomics: the same sums
     # in another order (float32 reassociation only), on a batch of 512 rays.
-    sc = scenes.scene_body(H=64, W=64, spp=128, res=32, log2_T=16, seed=16541 + 4)
+    # With a blend-weight volume whose side is not a power of two (24) only
+    # the table is binned and dL/dW^c keeps run-summed atomics.
+    sc = scenes.scene_body(H=64, W=64, spp=128, res=res, log2_T=16, seed=16541 + 4)
     g = np.random.default_rng(9)
     pid = g.integers(0, sc.H * sc.W, 512).astype(np.int32)
     tgt = g.random((512, 3)).astype(np.float32)
