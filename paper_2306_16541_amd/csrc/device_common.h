@@ -140,7 +140,7 @@ struct RenderArgs {
   float* grad_w[MNR_MAX_LAYERS];
   float* grad_weights;
   float* grad_G;                     // optional [n_bones][12]
-  RecordSink rec;                    // optional: hashed-level table gradient as records
+  RecordSink rec;                    // optional: table and blend-weight gradients as records
   SplitArgs split;                   // split adjoint (residual motion network, frequency-encoded field)
   float* grad_res[6];                // residual network: W1..W5, W_omega (FP32)
 };

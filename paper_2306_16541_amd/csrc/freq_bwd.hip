@@ -13,8 +13,9 @@
 //                     values the next layer consumed), and the compositing
 //                     adjoint, storing dL/d(outputs) and dL/dL;
 //   freq_bwd_kernel   per 16-sample tile, the MLP's adjoint from the saved
-//                     activations: dL/dW1..W5 (block sums in LDS, each
-//                     wave adding its own rows) and
+//                     activations: dL/dW1..W5 (each wave summing its own
+//                     rows in MFMA accumulators, block sums in LDS at the
+//                     end) and
 //                     dL/dx_final = (d gamma / dx)^T dL/dgamma, where
 //                     dL/dgamma collects the first layer's and the skip's
 //                     terms;

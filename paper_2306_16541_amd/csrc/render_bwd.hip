@@ -13,13 +13,16 @@
 //      registers and added to the block's LDS sums at the end;
 //   3. encoding adjoint: scatter-add into the table gradient and the
 //      encoding's spatial derivative back to the skinned point x_skel;
-//      consecutive samples in the same cell are summed in the wave first;
-//      with a record sink the hashed levels write (row, gradient) records
-//      instead, summed afterwards without float atomics (scatter.hip);
+//      consecutive samples in the same cell are summed in the wave first
+//      (with a record sink only at the dense levels, whose runs are long),
+//      and with a record sink the levels write (key, gradient) records
+//      instead of atomics, summed afterwards without float atomics
+//      (scatter.hip);
 //   4. skinning adjoint (Eq. 7, 9): dx_skel/dw_i = (y_i - x_skel)/L and the
 //      likelihood term dalpha'/dL = alpha [L < 1], scattered through the
-//      trilinear weights into dL/dW^c; optionally dL/dG_i through the
-//      points y_i = G_i x and the weights' spatial gradient.
+//      trilinear weights into dL/dW^c (records of x-adjacent corner pairs
+//      with a record sink); optionally dL/dG_i through the points
+//      y_i = G_i x and the weights' spatial gradient.
 #include "adjoint_device.h"
 #include "kernels.h"
 
