@@ -311,6 +311,34 @@ def test_binned_scatter_non_finite_gradient():
         assert float(np.abs(fa - fb).max()) <= 1e-5 * float(np.abs(fa).max()), name
 
 
+def test_binned_scatter_largest_table():
+    # T = 2^24: the 4 hashed levels fill the key space (4096 bins of 2^14
+    # rows, each summed in four 2^12-row parts); the dense levels and the
+    # blend weights keep atomics.  Binned against atomic, hashed level by
+    # hashed level, on 256 rays.
+    print("[largest table] building the 2^24-row scene", flush=True)
+    sc = scenes.scene_body(H=64, W=64, spp=64, res=32, log2_T=24, seed=16541 + 4)
+    g = np.random.default_rng(11)
+    pid = g.integers(0, sc.H * sc.W, 256).astype(np.int32)
+    tgt = g.random((256, 3)).astype(np.float32)
+    hashed = [l for l, n in enumerate(sc.level_res) if (int(n) + 1) ** 3 > 1 << 24]
+    assert len(hashed) == 4
+    a = gpu_grads(sc, pid, tgt, 0, binned=False)
+    print("[largest table] atomic adjoint done", flush=True)
+    b = gpu_grads(sc, pid, tgt, 0, binned=True)
+    print("[largest table] binned adjoint done", flush=True)
+    for l in hashed:
+        ta, tb = a[1][l], b[1][l]
+        mx = float(np.abs(ta).max())
+        err = float(np.abs(ta - tb).max()) / mx
+        print(f"  level {l} (N={int(sc.level_res[l])}): max diff {err:.2e} of max, "
+              f"{int((ta != 0).sum())} nonzero entries", flush=True)
+        assert mx > 0 and err <= 1e-5, (l, err)
+    for l in range(len(sc.level_res)):  # the dense levels took the same atomics in both runs
+        if l not in hashed:
+            assert float(np.abs(a[1][l] - b[1][l]).max()) <= 1e-5 * float(np.abs(a[1][l]).max() + 1e-30), l
+
+
 def test_binned_scatter_splits_crowded_bins():
     # The full-size field's coarse dense levels put hundreds of thousands of
     # records into one 4096-row bin (level 0 has 17^3 rows), which the
