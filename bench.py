@@ -335,8 +335,9 @@ def train_bench(steps, warmup):
 
 def train_variants(sc, pose, cam, pid, tgt, steps):
     """The same 8192-ray batch with the residual motion network on (grid
-    field) and with the paper's frequency-encoded field: step time and the
-    adjoint alone (both split adjoints, through the adjoint workspace)."""
+    field), with the paper's frequency-encoded field, and with an FP32 MLP
+    on the grid field: step time and the adjoint alone (through the adjoint
+    workspace)."""
     dev = "cuda"
     out = {}
     rw, w_omega = scenes.residual_weights(21)
@@ -347,6 +348,9 @@ def train_variants(sc, pose, cam, pid, tgt, steps):
                                       max_rays=8192, spp=sc.spp, residual=(rw, w_omega, 4.0)),
         "frequency_field": m.Trainer.frequency([torch.as_tensor(w, device=dev) for w in scenes.freq_field_weights(31)],
                                                torch.as_tensor(sc.logits, device=dev), max_rays=8192, spp=sc.spp),
+        "fp32_mlp": m.Trainer(torch.as_tensor(sc.table, device=dev), [torch.as_tensor(w, device=dev) for w in sc.mlp],
+                              torch.as_tensor(sc.logits, device=dev), sc.level_res, m.F32, m.F32,
+                              max_rays=8192, spp=sc.spp),
     }
     opts = m.make_opts(stratified=True, seed=1)
     for name, tr in trainers.items():

@@ -47,9 +47,12 @@ struct BwdShape {
   static constexpr int tbuf_bytes() { return 2 * 64 * 16 * (int)sizeof(TB); }
   static constexpr int wave_bytes() { return S::feat_bytes_per_wave() + 64 * IN_FEAT * 4 + tbuf_bytes(); }
   static constexpr int dg_floats() { return MNR_MAX_BONES * 12; }  // block sums of dL/dG
+  // The block's dW sums are needed only after the main loop, when the
+  // weights are dead: they overlay the weights' LDS.
   static constexpr int lds_bytes(int nhh, int nw) {
-    return S::bytes_total(nhh) + bytes_t(nhh) + (dw_floats(nhh) + dg_floats()) * 4 + nw * wave_bytes();
+    return S::bytes_total(nhh) + bytes_t(nhh) + dg_floats() * 4 + nw * wave_bytes();
   }
+  static_assert(dw_floats(2) * 4 <= S::bytes_total(2) + bytes_t(2), "the dW sums fit over the weights");
 };
 
 // Stage W^T of a layer W [M][K] as the A operand of an (K x Mpad) product.
@@ -224,8 +227,9 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* wl = lds;
   char* wt = wl + S::bytes_total(NHH);
-  float* dw = (float*)(wt + B::bytes_t(NHH));
-  float* dg = dw + B::dw_floats(NHH);
+  static_assert(B::dw_floats(NHH) * 4 <= S::bytes_total(NHH) + B::bytes_t(NHH), "the dW sums fit over the weights");
+  float* dw = (float*)lds;  // after the main loop only: over the weights
+  float* dg = (float*)(wt + B::bytes_t(NHH));
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   char* wbase = (char*)(dg + B::dg_floats()) + wave * B::wave_bytes();
   char* feat = wbase;
@@ -234,7 +238,7 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 
   stage_weights<P, NHH>(wl, a.f);
   stage_weights_t<P, NHH>(wt, a.f);
-  for (int i = threadIdx.x; i < B::dw_floats(NHH) + B::dg_floats(); i += blockDim.x) dw[i] = 0.f;
+  for (int i = threadIdx.x; i < B::dg_floats(); i += blockDim.x) dg[i] = 0.f;
   __syncthreads();
 
   const size_t T = (size_t)1 << a.f.log2_T;
@@ -498,7 +502,11 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
     }
   }
   if (a.rec.keys) flush_value_bounds(a.rec, tab_mb, wc_mb);
-  // the waves' register sums into the block's LDS sums, one wave at a time
+  // the weights are dead now: their LDS takes the block's dW sums, and the
+  // waves' register sums go there one wave at a time
+  __syncthreads();
+  for (int i = threadIdx.x; i < B::dw_floats(NHH); i += blockDim.x) dw[i] = 0.f;
+  __syncthreads();
   for (int w = 0; w < NW; ++w) {
     if (wave == w) {
       flush_dw(acc.out, dw + B::off_hidden(NHH), 4, B::LD_HID, lane);
@@ -532,11 +540,11 @@ __global__ void __launch_bounds__(64 * NW) render_bwd_kernel(const RenderArgs a,
 }
 
 static_assert(BwdShape<MNR_BF16>::lds_bytes(2, 4) <= 160 * 1024, "LDS of the BF16 adjoint");
-static_assert(BwdShape<MNR_F32>::lds_bytes(2, 1) <= 160 * 1024, "LDS of the FP32 adjoint");
+static_assert(BwdShape<MNR_F32>::lds_bytes(2, 2) <= 160 * 1024, "LDS of the FP32 adjoint");
 
 template <typename TableT, int P, int NHH, bool SPLIT>
 static hipError_t launch_bwd_s(const RenderArgs& a, int n_slots, hipStream_t st) {
-  constexpr int NW = (P == MNR_F32) ? 1 : 4;
+  constexpr int NW = (P == MNR_F32) ? 2 : 4;  // (one wave per SIMD at most: the BF16 kernel's registers)
   const int lds = BwdShape<P>::lds_bytes(NHH, NW);
   auto kern = render_bwd_kernel<TableT, P, NHH, NW, SPLIT>;
   static PersistentGrid pg;
