@@ -274,6 +274,43 @@ def test_binned_scatter_equals_atomic_scatter(res):
         assert float(np.abs(x - y).max()) <= 1e-5 * float(np.abs(x).max())
 
 
+def test_ray_list_processing_order():
+    # With a ray list and an adjoint workspace, the adjoint processes the
+    # rays in a spatially coherent order kept at the end of the workspace:
+    # a permutation of the rows, sorted by the Morton index of the pixel's
+    # cell in a 64 x 64 grid over the image.
+    import paper_2306_16541_amd as m
+    sc = scenes.scene_body(H=48, W=80, spp=64, res=32, log2_T=16, seed=16541 + 4)
+    g = np.random.default_rng(12)
+    n = 1000
+    pid = g.integers(0, sc.H * sc.W, n).astype(np.int32)
+    tgt = g.random((n, 3)).astype(np.float32)
+    fld, _ = m.upload_scene(sc, "cuda", m.F32, 0)
+    pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
+    cam = m.make_camera(sc.cam)
+    opts = m.make_opts(ert_tau=0.0, stratified=True, seed=SEED)
+    pid_t = torch.as_tensor(pid, device="cuda")
+    tch = torch.zeros(n, m.saved_size(sc.spp), device="cuda")
+    rgba = m.render(fld, pose, cam, sc.H, sc.W, sc.spp, opts, pid_t, t_chunks=tch)
+    grad_rgba = torch.empty(n, 4, device="cuda")
+    m.mse_loss(rgba, torch.as_tensor(tgt, device="cuda"), grad_rgba)
+    ws = m.adjoint_workspace(fld, n, sc.spp)
+    m.render_backward(fld, pose, cam, sc.H, sc.W, sc.spp, opts, pid_t, tch, grad_rgba,
+                      torch.zeros(sc.table.shape, device="cuda"), [torch.zeros(w.shape, device="cuda") for w in sc.mlp],
+                      torch.zeros(sc.logits.shape, device="cuda"), adjoint_ws=ws)
+    torch.cuda.synchronize()
+    tail = -(-n * 4 // 256) * 256           # the order is the workspace's last part
+    order = ws[ws.numel() - tail:ws.numel() - tail + 4 * n].view(torch.int32).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(n))
+
+    def cell(p):
+        x = (p % sc.W) * 64 // sc.W
+        y = (p // sc.W) * 64 // sc.H
+        return sum((((x >> b) & 1) << (2 * b)) | (((y >> b) & 1) << (2 * b + 1)) for b in range(6))
+    cells = np.array([cell(int(p)) for p in pid[order]])
+    assert np.all(np.diff(cells) >= 0)
+
+
 def test_binned_scatter_non_finite_gradient():
     # A non-finite loss gradient on one ray: the adjoint's bound on the
     # record values is then NaN, and the binned scatter sums in floats
