@@ -335,9 +335,10 @@ def train_bench(steps, warmup):
 
 def train_variants(sc, pose, cam, pid, tgt, steps):
     """The same 8192-ray batch with the residual motion network on (grid
-    field), with the paper's frequency-encoded field, and with an FP32 MLP
-    on the grid field: step time and the adjoint alone (through the adjoint
-    workspace)."""
+    field), with the paper's frequency-encoded field, with an FP32 MLP on the
+    grid field, and with the renderer reading an FP16 copy of the table (FP32
+    masters and Adam state): step time and the adjoint alone (through the
+    adjoint workspace)."""
     dev = "cuda"
     out = {}
     rw, w_omega = scenes.residual_weights(21)
@@ -351,6 +352,9 @@ def train_variants(sc, pose, cam, pid, tgt, steps):
         "fp32_mlp": m.Trainer(torch.as_tensor(sc.table, device=dev), [torch.as_tensor(w, device=dev) for w in sc.mlp],
                               torch.as_tensor(sc.logits, device=dev), sc.level_res, m.F32, m.F32,
                               max_rays=8192, spp=sc.spp),
+        "fp16_table": m.Trainer(torch.as_tensor(sc.table, device=dev), [torch.as_tensor(w, device=dev) for w in sc.mlp],
+                                torch.as_tensor(sc.logits, device=dev), sc.level_res, m.F16, m.BF16,
+                                max_rays=8192, spp=sc.spp),
     }
     opts = m.make_opts(stratified=True, seed=1)
     for name, tr in trainers.items():

@@ -45,11 +45,12 @@ def _rays(sc, n=16):
     return pid, tgt
 
 
-def gpu_grads(sc, pid, tgt, mlp_dtype, ert_tau=1e-6, binned=False):
+def gpu_grads(sc, pid, tgt, mlp_dtype, ert_tau=1e-6, binned=False, table_dtype=0):
     """binned: the table gradient goes through the binned scatter (records
-    summed in LDS) instead of global atomics."""
+    summed in LDS) instead of global atomics.  table_dtype: the renderer's
+    copy of the table (FP32 or FP16)."""
     import paper_2306_16541_amd as m
-    fld, _ = m.upload_scene(sc, "cuda", m.F32, mlp_dtype)
+    fld, _ = m.upload_scene(sc, "cuda", table_dtype, mlp_dtype)
     pose = m.PoseHost(sc.parents, sc.rest_joints, sc.axis_angle)
     cam = m.make_camera(sc.cam)
     opts = m.make_opts(ert_tau=ert_tau, stratified=True, seed=SEED)
@@ -145,6 +146,28 @@ def test_adjoint_matches_oracle_gradient(mlp_dtype, tol, binned):
     np.testing.assert_allclose(sg, so, rtol=0, atol=max(tol, 1e-4) * np.abs(so).max())
     # softmax adjoint: gradients of each voxel's logits sum to zero
     assert np.abs(logg.sum(0)).max() <= 1e-6 * max(np.abs(logg).max(), 1e-12) + 1e-12
+
+
+def test_adjoint_with_fp16_table():
+    # The renderer reading an FP16 copy of the table (mixed-precision
+    # training keeps FP32 masters): the adjoint is that of the field with
+    # the table rounded to FP16, so the FP64 oracle on the rounded table is
+    # the reference, element by element as for the FP32 table.
+    import dataclasses
+    import paper_2306_16541_amd as m
+    sc = _scene()
+    sc16 = dataclasses.replace(sc, table=sc.table.astype(np.float16).astype(np.float32))
+    pid, tgt = _rays(sc)
+    for binned in (False, True):
+        lg, tg, wg, logg, rg = gpu_grads(sc, pid, tgt, 0, binned=binned, table_dtype=m.F16)
+        lo, to, wo, logo, ro = oracle_grads(sc16, pid, tgt)
+        print(f"[fp16 table, binned {binned}] loss gpu {lg:.8f} oracle {lo:.8f}", flush=True)
+        assert abs(lg - lo) <= 1e-5 * abs(lo)
+        groups = [("table", tg, to), ("logits", logg, logo)] + [(f"w{k}", a, b) for k, (a, b) in enumerate(zip(wg, wo))]
+        for name, a, b in groups:
+            assert np.linalg.norm(b) > 0, name
+            assert _rel(a, b) <= 2e-3, (name, _rel(a, b))
+            _elementwise(name, a, b, TAU[0])
 
 
 def test_adjoint_directional_derivative_matches_oracle_differences():
