@@ -18,7 +18,9 @@
 //                     end) and
 //                     dL/dx_final = (d gamma / dx)^T dL/dgamma, where
 //                     dL/dgamma collects the first layer's and the skip's
-//                     terms;
+//                     terms (gamma recomputed with its inputs in an order
+//                     that gives each lane one sincospi per band and axis,
+//                     W1's and W4's gamma columns permuted to match);
 // then the residual network's adjoint (if it is on) and the skinning
 // adjoint (res_bwd.hip).
 #include "adjoint_device.h"
@@ -134,39 +136,65 @@ __global__ void __launch_bounds__(64 * FREQ_SAVE_WAVES) freq_save_kernel(const R
 
 // ---- 2. the skip MLP's adjoint ----------------------------------------------
 
-// gamma of sample x at the 16 inputs k = 16 t + 4 g + e (t, e = 0..3) that
-// lane group g holds in the D layout, with d gamma_k / d x_q(k): value, the
-// derivative and its axis.  The arguments of sincospi are formed as the
-// forward pass forms them, so the values round to the same BF16 operands.
+// The adjoint holds gamma's 64 inputs in its own order so that each lane
+// evaluates one sincospi per (band, axis) pair and takes both its sine and
+// its cosine: lane group g's slot n (D-layout input 16 (n / 4) + 4 g + n % 4)
+// holds pair p = 8 g + n / 2 (band p / 3, axis p % 3), its sine for even n
+// and its cosine for odd n; pairs 30 and 31 (g = 3, slots 12..15) hold the
+// raw coordinates and the zero pad.  gamma_input(pos) is the forward's input
+// index of adjoint position pos: W1's and W4's gamma columns are staged, and
+// their weight gradients written back, through it.
+__device__ __forceinline__ int gamma_input(int pos) {
+  const int g = (pos >> 2) & 3, n = ((pos >> 4) << 2) | (pos & 3);
+  const int p = 8 * g + (n >> 1);
+  if (p >= 30) return n == 15 ? 63 : n - 12;
+  const int band = p / 3;
+  return 3 + 6 * band + 3 * (n & 1) + (p - 3 * band);
+}
+
+// stage_t with the input columns from gamma0 on taken in the adjoint's order.
+__device__ void stage_t_gamma(char* lds, const __bf16* __restrict__ w, int M, int K, int Kpad, int gamma0) {
+  for (int e = threadIdx.x; e < K * Kpad; e += blockDim.x) {
+    const int m = e / Kpad, k = e - m * Kpad;  // element (m, k) of W^T
+    const int col = m < gamma0 ? m : gamma0 + gamma_input(m - gamma0);
+    const float v = (k < M) ? (float)w[(size_t)k * K + col] : 0.0f;
+    *(__bf16*)(lds + frag_offset<MNR_BF16>(m, k, Kpad / 32)) = (__bf16)v;
+  }
+}
+
+// gamma of sample x at lane group g's 16 slots, with d gamma / d x_q: value,
+// the derivative and its axis q.  The arguments of sincospi are formed as
+// the forward pass forms them, so the values round to the same BF16
+// operands.
 __device__ __forceinline__ void posenc10_lane(const float x[3], int g, f4 (&val)[4], float (&der)[16],
                                               int (&axis)[16]) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 16 * t + 4 * g + e, n = 4 * t + e;
-      float v = 0.f, d = 0.f;
-      int q = 0;
-      if (k < 3) {
-        q = k;
-        v = x[0];
-        if (k == 1) v = x[1];
-        if (k == 2) v = x[2];
-        d = 1.f;
-      } else if (k < 63) {
-        const int band = (k - 3) / 6, r = (k - 3) - 6 * ((k - 3) / 6);
-        q = r < 3 ? r : r - 3;
-        const float xq = q == 0 ? x[0] : (q == 1 ? x[1] : x[2]);
-        const float f = (float)(1 << band);
-        float sv, cv;
-        sincospif(f * xq, &sv, &cv);
-        v = r < 3 ? sv : cv;
-        d = (r < 3 ? cv : -sv) * (f * 3.14159265358979f);
-      }
-      val[t][e] = v;
-      der[n] = d;
-      axis[n] = q;
+  for (int j = 0; j < 8; ++j) {
+    const int p = 8 * g + j, pc = p < 30 ? p : 29;
+    const int band = pc / 3, q = pc - 3 * band;
+    const float xq = q == 0 ? x[0] : (q == 1 ? x[1] : x[2]);
+    const float f = (float)(1 << band);
+    float sv, cv;
+    sincospif(f * xq, &sv, &cv);
+    const float fpi = f * 3.14159265358979f;
+    float v0 = sv, v1 = cv, d0 = cv * fpi, d1 = -sv * fpi;
+    int a0 = q, a1 = q;
+    if (j >= 6 && p >= 30) {  // the raw coordinates (slots 12, 13, 14) and the pad (15)
+      v0 = j == 6 ? x[0] : x[2];
+      v1 = j == 6 ? x[1] : 0.f;
+      d0 = 1.f;
+      d1 = j == 6 ? 1.f : 0.f;
+      a0 = j == 6 ? 0 : 2;
+      a1 = j == 6 ? 1 : 0;
     }
+    const int n0 = 2 * j, n1 = 2 * j + 1;
+    val[n0 >> 2][n0 & 3] = v0;
+    val[n1 >> 2][n1 & 3] = v1;
+    der[n0] = d0;
+    der[n1] = d1;
+    axis[n0] = a0;
+    axis[n1] = a1;
+  }
 }
 
 __device__ __forceinline__ void load_act(const bf16x8* act, int layer, int nt, int lane, f4 (&h)[4]) {
@@ -191,10 +219,10 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
   char* rt = lds;
   float* dw = (float*)(rt + FreqTShape::bytes());
   __bf16* tb = (__bf16*)((char*)(dw + FreqGrad::floats()) + wave * RES_TB_BYTES);
-  stage_t(rt, (const __bf16*)a.f.w[0], HIDDEN, 64, HIDDEN);
+  stage_t_gamma(rt, (const __bf16*)a.f.w[0], HIDDEN, 64, HIDDEN, 0);
   stage_t(rt + FreqTShape::o2, (const __bf16*)a.f.w[1], HIDDEN, HIDDEN, HIDDEN);
   stage_t(rt + FreqTShape::o3, (const __bf16*)a.f.w[2], HIDDEN, HIDDEN, HIDDEN);
-  stage_t(rt + FreqTShape::o4, (const __bf16*)a.f.w[3], HIDDEN, 2 * HIDDEN, HIDDEN);
+  stage_t_gamma(rt + FreqTShape::o4, (const __bf16*)a.f.w[3], HIDDEN, 2 * HIDDEN, HIDDEN, HIDDEN);
   stage_t(rt + FreqTShape::o5, (const __bf16*)a.f.w[4], 4, HIDDEN, 32);
   for (int i = threadIdx.x; i < FreqGrad::floats(); i += blockDim.x) dw[i] = 0.f;
   __syncthreads();
@@ -340,8 +368,11 @@ __global__ void __launch_bounds__(64 * FREQ_BWD_WAVES) freq_bwd_kernel(const Ren
   for (int l = 0; l < 5; ++l)
     for (int k = threadIdx.x; k < rows[l] * cols[l]; k += blockDim.x) {
       const int r = k / cols[l];
-      const float v = dw[off[l] + r * ld[l] + (k - r * cols[l])];
-      if (v != 0.f) unsafeAtomicAdd(a.grad_w[l] + k, v);
+      const int c = k - r * cols[l];
+      const float v = dw[off[l] + r * ld[l] + c];
+      // W1's columns and W4's gamma columns back in the forward's input order
+      const int col = l == 0 ? gamma_input(c) : (l == 3 && c >= 64 ? 64 + gamma_input(c - 64) : c);
+      if (v != 0.f) unsafeAtomicAdd(a.grad_w[l] + r * cols[l] + col, v);
     }
 }
 
